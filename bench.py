@@ -1,0 +1,144 @@
+"""Benchmark: Siddon P / P^T voxel-crossings per second on one MI355X.
+
+One step is the EUVI-like static inversion: 50 conjugate-gradient
+iterations on the 128^3 cube (unit sphere masked) seen by 28 views of
+512x512 pixels, i.e. one P^T for the right-hand side, then per iteration one
+P, one P^T, the prior and the vector updates, plus one P and P^T for the
+final true residual.  Inputs (phantom, data with 1% noise) are synthetic,
+generated once and resident in HBM before timing.
+
+value = (P and P^T applications in the step) x (voxel crossings per
+application) / step time.  The roofline entry is for the kernel that takes
+most of the step time, timed per launch with HIP events recorded on the
+stream the library launches it on.  The CPU baseline is the FP64 oracle on a
+bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Siddon P/Pᵀ voxel-crossings/s; time to rel. residual 1e-3 (learned vs plain)"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-views", type=int, default=2, help="views in the oracle's timed sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(wl, nviews):
+    """The FP64 oracle (as it stands) on a bounded sample: P and P^T over the
+    first `nviews` views of the same geometry, all host cores."""
+    import oracle as ora
+
+    g = wl.geom.subset(list(range(nviews)))
+    cross = ora.count_crossings(g)
+    y = np.random.default_rng(0).normal(size=g.nrays)
+    ora.project(g, wl.x)  # warm the page cache / thread pool
+    t0 = time.perf_counter()
+    ora.project(g, wl.x)
+    ora.backproject(g, y)
+    dt = time.perf_counter() - t0
+    return {"value": 2.0 * cross / dt, "unit": "voxel-crossings/s", "cores": ora.max_threads(),
+            "kind": "oracle",
+            "sample": f"P + P^T over {nviews} of the 28 views (512x512) of the 128^3 EUVI-like cube "
+                      f"({cross} crossings each), {dt:.1f} s"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on exactly one GPU; multi-GPU runs are "
+                                   "not part of this build (see DESIGN.md for the sharding plan)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_1103_5904_amd as tomo
+    import tomo_synth as ts
+
+    torch.cuda.set_device(0)
+    wl = ts.euvi()
+    g = wl.geom
+    dg = tomo.DeviceGeometry(g)
+    x_true = torch.as_tensor(wl.x.astype(np.float32)).cuda()
+    y = tomo.project(dg, x_true)
+    rms = float(torch.sqrt(torch.mean(y.double() ** 2)))
+    y += torch.as_tensor(ts.gaussian_noise(g.nrays, wl.noise_rel * rms, wl.noise_seed)
+                         .astype(np.float32)).cuda()
+    crossings = tomo.count_crossings(dg)
+    x = torch.empty(dg.cube_shape, dtype=torch.float32, device="cuda")
+
+    def step():
+        return tomo.cg_solve(dg, y, lam_r=wl.lam_r, max_iter=wl.cg_iters, time_kernels=True, out=x)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    reps = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        reps.append(step()[1])
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = 1e3 * dt / args.steps
+    apps = sum(r["n_project"] + r["n_backproject"] for r in reps) / args.steps
+    value = apps * crossings / (ms_step * 1e-3)
+
+    # per-launch kernel times (events around each P and P^T inside the solve)
+    n_it = sum(r["iters"] for r in reps)
+    ms_p = sum(r["ms_project"] for r in reps) / n_it
+    ms_bp = sum(r["ms_backproject"] for r in reps) / n_it
+    nrays = dg.npix
+    bytes_p = 4.0 * crossings + 4.0 * nrays
+    bytes_bp = 8.0 * crossings + 4.0 * nrays
+    if ms_bp >= ms_p:
+        dom, ms_dom, b_dom = "k_backproject_atomic", ms_bp, bytes_bp
+    else:
+        dom, ms_dom, b_dom = "k_project", ms_p, bytes_p
+    achieved = b_dom / (ms_dom * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-crossings/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "EUVI-like static inversion: 128^3 cube on [-1.5,1.5]^3 R_sun, "
+                               "unit sphere masked, 28 views of 512x512 at FOV 3.4, 50 CG "
+                               "iterations, lambda 1e-2",
+                   "crossings_per_application": crossings, "applications_per_step": apps,
+                   "rays": nrays, "storage": "f32", "walk": "f64",
+                   "final_rel_res": reps[-1]["rel_res"]},
+        "kernels": {"k_project_ms": ms_p, "k_backproject_ms": ms_bp,
+                    "project_crossings_per_s": crossings / (ms_p * 1e-3),
+                    "backproject_crossings_per_s": crossings / (ms_bp * 1e-3)},
+        "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_views)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

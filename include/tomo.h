@@ -1,0 +1,258 @@
+/*
+ * tomo.h -- C ABI of libtomo, a gfx950 (MI355X) implementation of the
+ * line-of-sight projector of TomograPy (Barbey, Guennou & Auchere, Solar
+ * Physics), its exact transpose, and the conjugate-gradient inversion of the
+ * paper's regularised least-squares criterion.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Voxel cube (Sec. "Single Spacecraft Static Tomography"): nx*ny*nz
+ *   identical rectangular voxels filling the box [box_min, box_max]; FP32,
+ *   x fastest: index = (k*ny + j)*nx + i.  A cube argument holding nframes
+ *   time frames is nframes such volumes back to back (the block-diagonal
+ *   operator of Eq. srt_t).  Voxels are half-open [lo + k D, lo + (k+1) D).
+ * - Images (Eq. srt): FP32, the views concatenated in order, each view
+ *   [nrow][ncol] with the column fastest.
+ * - Line of sight through pixel (col, row) of a view: the half-line
+ *   obs + t d, t >= 0, with d = w + (col - crpix0) cdelt0 u
+ *   + (row - crpix1) cdelt1 v (gnomonic / TAN projection; the paper defines
+ *   observer and projector through WCS keywords, Sec. "Instrument
+ *   Independence").  w, u, v must be orthonormal.  Pixel centres sit at
+ *   integer 0-based indices.  Lengths are in box units.
+ * - Projection (Eq. lo): image value = sum over the voxels the line crosses
+ *   of (length inside the voxel) * (voxel value), computed with Siddon's
+ *   method: the ray's crossings of the x, y and z voxel planes are merged in
+ *   order (simultaneous crossings taken as one).  The transpose scatters the
+ *   same lengths, so the two are exact adjoints of one another.
+ * - Masks (Sec. "Performance"): data_mask[ray] == 0 removes a pixel (its
+ *   row of P is zero, and it is neither projected nor back-projected);
+ *   map_mask[voxel] == 0 removes a voxel from the unknowns, so the operator
+ *   is P M with M the 0/1 diagonal of the map mask.
+ *
+ * Memory and streams
+ * ------------------
+ * Cube, image and mask arrays are caller-owned DEVICE pointers (contiguous).
+ * tomo_view arrays and all structs are HOST memory.  A stream argument is a
+ * hipStream_t (NULL = the default stream); work is enqueued asynchronously
+ * on it unless a call says otherwise, and kernel faults surface at the next
+ * synchronising call.  The library caches device copies of view tables,
+ * keyed by the geometry's contents: the first call with a new geometry
+ * allocates and uploads synchronously, so make that call before any stream
+ * capture.  tomo_release_cache() frees the cache.
+ *
+ * Errors
+ * ------
+ * Every call returns TOMO_OK (0) or a negative tomo_status; nothing aborts
+ * or throws across the ABI.  Invalid arguments are rejected before any GPU
+ * work is enqueued.  tomo_last_error() returns a text for the last failure
+ * on the calling thread.
+ */
+#ifndef TOMO_H
+#define TOMO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef void *tomo_stream; /* hipStream_t */
+
+typedef enum tomo_status {
+    TOMO_OK = 0,
+    TOMO_EINVAL = -1,      /* bad sizes, bounds, frame, NULL pointer, ...      */
+    TOMO_EHIP = -2,        /* a HIP runtime call failed                         */
+    TOMO_ENONFINITE = -3,  /* a solver scalar became NaN or infinite            */
+    TOMO_ENOCONV = -4,     /* max_iter reached before rtol (report only)        */
+    TOMO_ENOMEM = -5,      /* device or host allocation failed                  */
+    TOMO_EUNSUPPORTED = -6 /* option not supported with these arguments         */
+} tomo_status;
+
+typedef struct tomo_cube {
+    int32_t nx, ny, nz; /* voxels per axis, each >= 1, product < 2^30           */
+    int32_t nframes;    /* time frames held by a cube argument (>= 1)           */
+    double box_min[3];  /* box lower corner (box units, e.g. R_sun)             */
+    double box_max[3];  /* box upper corner, > box_min on every axis            */
+} tomo_cube;
+
+typedef struct tomo_view {
+    double obs[3];      /* observer position in the cube frame                  */
+    double w[3];        /* unit vector of the tangent point (crpix)             */
+    double u[3];        /* unit vector along +column in the tangent plane       */
+    double v[3];        /* unit vector along +row in the tangent plane          */
+    double cdelt[2];    /* tangent-plane radians per pixel (column, row), != 0  */
+    double crpix[2];    /* 0-based pixel position of the tangent point          */
+    int32_t ncol, nrow; /* image size, each >= 1                                */
+    int32_t frame;      /* time frame seen by this view, 0..nframes-1           */
+    int32_t reserved;   /* set to 0                                             */
+} tomo_view;
+
+typedef struct tomo_geometry {
+    tomo_cube cube;
+    int32_t nviews;           /* >= 1                                          */
+    int32_t reserved;         /* set to 0                                      */
+    const tomo_view *views;   /* HOST array [nviews]                           */
+    const uint8_t *data_mask; /* DEVICE [total pixels] or NULL (keep all)      */
+    const uint8_t *map_mask;  /* DEVICE [nz][ny][nx] or NULL (keep all); the
+                                 same mask applies to every frame               */
+} tomo_geometry;
+
+/* Back-projection strategies. */
+enum {
+    TOMO_BP_AUTO = 0,   /* the tuned default for this geometry                  */
+    TOMO_BP_ATOMIC = 1, /* one FP32 atomic add per ray/voxel segment            */
+    TOMO_BP_BINNED = 2  /* per-bundle LDS bins, one atomic per voxel per chunk  */
+};
+
+/*
+ * Projection y = P M x (Eq. lo, Eq. srt).
+ *   cube_d:   DEVICE float [nframes][nz][ny][nx]
+ *   images_d: DEVICE float [total pixels]; every pixel is written (masked and
+ *             missing rays get 0).
+ */
+int tomo_project(const tomo_geometry *g, const float *cube_d, float *images_d,
+                 tomo_stream stream);
+
+/*
+ * Transpose x = M P^T y (or x += M P^T y when accumulate != 0).
+ *   images_d: DEVICE float [total pixels]
+ *   cube_d:   DEVICE float [nframes][nz][ny][nx]; zeroed first unless
+ *             accumulate.  Sums use FP32 atomics: the order of additions,
+ *             and so the last bits, may change from run to run.
+ *   strategy: TOMO_BP_* (tomo_backproject uses TOMO_BP_AUTO).
+ */
+int tomo_backproject(const tomo_geometry *g, const float *images_d,
+                     float *cube_d, int accumulate, tomo_stream stream);
+int tomo_backproject_ex(const tomo_geometry *g, const float *images_d,
+                        float *cube_d, int accumulate, int strategy,
+                        tomo_stream stream);
+
+/*
+ * Number of positive-length ray/voxel segments walked by one projection
+ * (masked pixels excluded): the "voxel crossings" P and P^T each process.
+ * Synchronises the stream; *total_h is host memory.
+ */
+int tomo_count_crossings(const tomo_geometry *g, int64_t *total_h,
+                         tomo_stream stream);
+
+/*
+ * Test export: the segments the GPU walk produces for one pixel, in order
+ * along the ray: flat voxel index (of the view's frame), length, and the
+ * parametric length (difference of the ray parameter t at the segment's
+ * ends; length = parametric length * |d|).  Runs the same device code as
+ * tomo_project on a one-lane launch and synchronises.
+ *   idx_h, len_h: HOST arrays of capacity cap; dpar_h: HOST array of
+ *   capacity cap or NULL; *n_out = segments written.
+ *   Returns TOMO_EINVAL if the pixel is out of range or cap is too small.
+ */
+int tomo_trace_ray(const tomo_geometry *g, int32_t view, int32_t col,
+                   int32_t row, int32_t *idx_h, double *len_h, double *dpar_h,
+                   int32_t cap, int32_t *n_out);
+
+/*
+ * Prior term (Sec. "Single Spacecraft Static Tomography"; Eq. stsrt):
+ *   out = [out if accumulate] + lambda_r D^T D x + lambda_t D_t^T D_t x
+ * with D the forward differences between in-cube neighbours along x, y and
+ * z of each frame (D^T D is the 6-neighbour graph Laplacian with free ends)
+ * and D_t the forward difference between consecutive frames.
+ *   x_d, out_d: DEVICE float [nframes][nz][ny][nx], must not overlap.
+ */
+int tomo_apply_prior(const tomo_cube *cube, double lambda_r, double lambda_t,
+                     const float *x_d, float *out_d, int accumulate,
+                     tomo_stream stream);
+
+/* Learned preconditioner network (a 3x3x3 convolution stack, 1 -> 16 -> 16
+ * -> 1 channels with ReLU between layers, zero padding 1).  Parameters are a
+ * DEVICE float array of TOMO_CONVNET_NPARAMS values, in this order:
+ * w1[16][1][27], b1[16], w2[16][16][27], b2[16], w3[1][16][27], b3[1]
+ * (w[cout][cin][kz*9 + ky*3 + kx], cross-correlation like torch.conv3d). */
+#define TOMO_CONVNET_NPARAMS 7809
+
+typedef struct tomo_cg_params {
+    double lambda_r;       /* spatial prior weight (>= 0)                        */
+    double lambda_t;       /* temporal prior weight (>= 0; needs nframes > 1)    */
+    int32_t max_iter;      /* iteration limit (>= 0)                             */
+    int32_t x0_given;      /* 1: x_d holds the starting point; 0: start at 0     */
+    double rtol;           /* stop when ||b - A x|| <= rtol ||b|| (0: never)      */
+    int32_t check_every;   /* host convergence check period (iterations, >= 1)   */
+    int32_t use_graph;     /* 1: replay iterations from a captured HIP graph     */
+    const float *precond;  /* DEVICE convnet parameters, or NULL for plain CG    */
+    int32_t fallback_window; /* FCG: restart as plain CG after this many
+                                iterations without a residual decrease (>= 1)   */
+    int32_t bp_strategy;   /* TOMO_BP_*                                          */
+    double min_drop;       /* FCG: a residual "decreases" if it falls below
+                              (1 - min_drop) times the previous one              */
+} tomo_cg_params;
+
+typedef struct tomo_cg_report {
+    int32_t iters;         /* iterations performed                               */
+    int32_t status;        /* TOMO_OK, TOMO_ENOCONV or TOMO_ENONFINITE           */
+    int32_t fell_back;     /* FCG: iteration of the switch to plain CG, or -1    */
+    int32_t n_project;     /* projections applied (for throughput accounting)    */
+    int32_t n_backproject; /* back-projections applied                           */
+    int32_t reserved;
+    double rel_res;        /* recursive ||r_k|| / ||b|| at exit                  */
+    double true_rel_res;   /* ||b - A x|| / ||b|| recomputed at exit             */
+    double bnorm;          /* ||b||                                              */
+    double ms_project;     /* total time of projection kernels (HIP events)      */
+    double ms_backproject; /* total time of back-projection kernels              */
+    double *history;       /* HOST [history_cap] or NULL: ||r_k||/||b||, k = 0.. */
+    int32_t history_cap;
+    int32_t history_len;   /* entries written                                    */
+    int32_t time_kernels;  /* input: 1 to time P and P^T launches with events    */
+    int32_t reserved2;
+} tomo_cg_report;
+
+/*
+ * Conjugate-gradient solution of the normal equations of Eq. criterion /
+ * Eq. stsrt,  A x = b  with  A = M (P^T P + lambda_r D^T D + lambda_t D_t^T
+ * D_t) M  and  b = M P^T y  (the map mask M restricts the unknowns).
+ * Textbook CG (FP32 vectors, FP64 dot products and scalars, kept on the
+ * device); with a preconditioner network, flexible CG with z = ||r|| N(r/||r||)
+ * and the Polak-Ribiere beta, falling back to plain CG after
+ * fallback_window non-decreasing iterations or when z.r <= 0.
+ *   y_d: DEVICE float [total pixels]
+ *   x_d: DEVICE float [nframes][nz][ny][nx]: start point if x0_given, and
+ *        the solution on return (masked voxels are 0).
+ * Synchronises the stream.  Returns TOMO_OK when the call ran (the report's
+ * status says whether it converged), or an error before/while running.
+ */
+int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d,
+                  const tomo_cg_params *p, tomo_cg_report *rep,
+                  tomo_stream stream);
+
+/* Default parameters: lambda_r 1e-2, max_iter 50, check_every 10,
+ * fallback_window 3, min_drop 1e-6, everything else 0 / NULL. */
+void tomo_cg_default_params(tomo_cg_params *p);
+
+/*
+ * View from helioprojective TAN WCS keywords (the paper's instrument
+ * interface, Sec. "Instrument Independence"): observer at distance dsun
+ * (box units) and heliographic longitude / latitude (degrees); reference
+ * pixel pointing (crval1, crval2) arcsec west / north of Sun centre; image
+ * rotation crota (degrees); cdelt in arcsec per pixel; crpix 1-based (FITS).
+ * Cube frame: x toward longitude 0 latitude 0, z toward solar north.
+ * out is HOST memory; frame is set to 0.
+ */
+int tomo_view_from_wcs(double dsun, double hgln_deg, double hglt_deg,
+                       double crval1_as, double crval2_as, double crota_deg,
+                       double cdelt1_as, double cdelt2_as, double crpix1,
+                       double crpix2, int32_t ncol, int32_t nrow,
+                       tomo_view *out);
+
+/* Validate a geometry without touching the GPU. */
+int tomo_validate_geometry(const tomo_geometry *g);
+
+/* Total pixel count of a geometry (0 if invalid). */
+int64_t tomo_geometry_pixels(const tomo_geometry *g);
+
+/* Free the cached device view tables. */
+void tomo_release_cache(void);
+
+const char *tomo_status_string(int status);
+const char *tomo_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TOMO_H */

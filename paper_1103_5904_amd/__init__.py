@@ -1,0 +1,8 @@
+"""MI355X (gfx950) implementation of TomograPy's hot path: the Siddon
+line-of-sight projector P, its exact transpose P^T, and conjugate-gradient
+inversion of (P^T P + lambda D^T D) x = P^T y, as HIP kernels behind the C ABI
+in include/tomo.h.  This package is the thin Python binding."""
+from .tomo import (  # noqa: F401
+    BP_ATOMIC, BP_AUTO, BP_BINNED, DeviceGeometry, TomoError, apply_prior, backproject, cg_solve,
+    count_crossings, lib, project, status_string, trace_ray, validate, view_from_wcs,
+)

@@ -1,0 +1,326 @@
+// Host side of libtomo: argument validation, the geometry-keyed cache of
+// device view tables, error reporting, WCS pointing, and the projector
+// entry points.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "common.h"
+
+namespace tomo {
+
+static thread_local std::string g_last_error;
+
+int set_error(int status, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return status;
+}
+
+int hip_fail(hipError_t e, const char *what)
+{
+    if (e == hipSuccess) return TOMO_OK;
+    return set_error(TOMO_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+static bool finite3(const double *v) { return isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]); }
+
+static double dot3(const double *a, const double *b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2]; }
+
+int validate_cube(const tomo_cube *c)
+{
+    if (!c) return set_error(TOMO_EINVAL, "cube is NULL");
+    if (c->nx < 1 || c->ny < 1 || c->nz < 1)
+        return set_error(TOMO_EINVAL, "cube dims must be >= 1 (got %d x %d x %d)", c->nx, c->ny, c->nz);
+    if (c->nframes < 1) return set_error(TOMO_EINVAL, "nframes must be >= 1 (got %d)", c->nframes);
+    const int64_t nvox = (int64_t)c->nx * c->ny * c->nz;
+    if (nvox >= (int64_t)1 << 30)
+        return set_error(TOMO_EINVAL, "cube of %lld voxels exceeds the 2^30 limit", (long long)nvox);
+    for (int a = 0; a < 3; ++a)
+        if (!isfinite(c->box_min[a]) || !isfinite(c->box_max[a]) || !(c->box_max[a] > c->box_min[a]))
+            return set_error(TOMO_EINVAL, "box bounds on axis %d are invalid", a);
+    return TOMO_OK;
+}
+
+static int validate_geometry_impl(const tomo_geometry *g, int64_t *npix_out)
+{
+    if (!g) return set_error(TOMO_EINVAL, "geometry is NULL");
+    int rc = validate_cube(&g->cube);
+    if (rc) return rc;
+    if (g->nviews < 1) return set_error(TOMO_EINVAL, "nviews must be >= 1 (got %d)", g->nviews);
+    if (!g->views) return set_error(TOMO_EINVAL, "views is NULL");
+    int64_t npix = 0;
+    for (int k = 0; k < g->nviews; ++k) {
+        const tomo_view &v = g->views[k];
+        if (!finite3(v.obs) || !finite3(v.w) || !finite3(v.u) || !finite3(v.v))
+            return set_error(TOMO_EINVAL, "view %d: non-finite vector", k);
+        const double tol = 1e-6;
+        if (fabs(dot3(v.w, v.w) - 1) > tol || fabs(dot3(v.u, v.u) - 1) > tol ||
+            fabs(dot3(v.v, v.v) - 1) > tol)
+            return set_error(TOMO_EINVAL, "view %d: w, u, v must be unit vectors", k);
+        if (fabs(dot3(v.w, v.u)) > tol || fabs(dot3(v.w, v.v)) > tol || fabs(dot3(v.u, v.v)) > tol)
+            return set_error(TOMO_EINVAL, "view %d: w, u, v must be orthogonal", k);
+        if (!isfinite(v.cdelt[0]) || !isfinite(v.cdelt[1]) || v.cdelt[0] == 0 || v.cdelt[1] == 0)
+            return set_error(TOMO_EINVAL, "view %d: cdelt must be finite and non-zero", k);
+        if (!isfinite(v.crpix[0]) || !isfinite(v.crpix[1]))
+            return set_error(TOMO_EINVAL, "view %d: crpix must be finite", k);
+        if (v.ncol < 1 || v.nrow < 1)
+            return set_error(TOMO_EINVAL, "view %d: image size %d x %d is invalid", k, v.ncol, v.nrow);
+        if (v.frame < 0 || v.frame >= g->cube.nframes)
+            return set_error(TOMO_EINVAL, "view %d: frame %d outside [0, %d)", k, v.frame, g->cube.nframes);
+        npix += (int64_t)v.ncol * v.nrow;
+    }
+    if (npix >= (int64_t)1 << 40) return set_error(TOMO_EINVAL, "too many pixels");
+    if (npix_out) *npix_out = npix;
+    return TOMO_OK;
+}
+
+// ------------------------------------------------------------ plan cache
+
+struct CacheEntry {
+    std::vector<unsigned char> key;
+    std::shared_ptr<Plan> plan;
+};
+
+static std::mutex g_cache_mu;
+static std::unordered_map<uint64_t, std::vector<CacheEntry>> g_cache;
+
+static uint64_t fnv1a(const unsigned char *p, size_t n, uint64_t h = 1469598103934665603ull)
+{
+    for (size_t i = 0; i < n; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+static std::vector<unsigned char> geometry_key(const tomo_geometry *g)
+{
+    std::vector<unsigned char> k(sizeof(tomo_cube) + sizeof(int32_t) +
+                                 sizeof(tomo_view) * (size_t)g->nviews);
+    unsigned char *q = k.data();
+    memcpy(q, &g->cube, sizeof(tomo_cube));
+    q += sizeof(tomo_cube);
+    memcpy(q, &g->nviews, sizeof(int32_t));
+    q += sizeof(int32_t);
+    memcpy(q, g->views, sizeof(tomo_view) * (size_t)g->nviews);
+    return k;
+}
+
+static int build_plan(const tomo_geometry *g, int64_t npix, Plan &p)
+{
+    const tomo_cube &c = g->cube;
+    GridDev &gd = p.grid;
+    gd.n[0] = c.nx;
+    gd.n[1] = c.ny;
+    gd.n[2] = c.nz;
+    gd.nframes = c.nframes;
+    for (int a = 0; a < 3; ++a) {
+        gd.lo[a] = c.box_min[a];
+        gd.hi[a] = c.box_max[a];
+        gd.delta[a] = (c.box_max[a] - c.box_min[a]) / (double)gd.n[a];
+    }
+    gd.nvox = (int64_t)c.nx * c.ny * c.nz;
+    std::vector<ViewDev> hv((size_t)g->nviews);
+    int64_t pix = 0, tiles = 0;
+    for (int k = 0; k < g->nviews; ++k) {
+        const tomo_view &v = g->views[k];
+        ViewDev &d = hv[(size_t)k];
+        for (int a = 0; a < 3; ++a) {
+            d.o[a] = v.obs[a];
+            d.w[a] = v.w[a];
+            d.u[a] = v.u[a];
+            d.v[a] = v.v[a];
+        }
+        d.cd[0] = v.cdelt[0];
+        d.cd[1] = v.cdelt[1];
+        d.cp[0] = v.crpix[0];
+        d.cp[1] = v.crpix[1];
+        d.ncol = v.ncol;
+        d.nrow = v.nrow;
+        d.frame = v.frame;
+        d.tiles_x = (v.ncol + kTile - 1) / kTile;
+        d.pix_off = pix;
+        d.tile_off = tiles;
+        pix += (int64_t)v.ncol * v.nrow;
+        tiles += (int64_t)d.tiles_x * ((v.nrow + kTile - 1) / kTile);
+    }
+    if (tiles >= ((int64_t)1 << 31)) return set_error(TOMO_EINVAL, "too many pixel tiles");
+    p.nviews = g->nviews;
+    p.ntiles = tiles;
+    p.npix = npix;
+    p.max_steps = c.nx + c.ny + c.nz + 3;
+    hipError_t e = hipMalloc((void **)&p.views_d, sizeof(ViewDev) * hv.size());
+    if (e != hipSuccess) return set_error(TOMO_ENOMEM, "view table allocation: %s", hipGetErrorString(e));
+    e = hipMemcpy(p.views_d, hv.data(), sizeof(ViewDev) * hv.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        hipFree(p.views_d);
+        p.views_d = nullptr;
+        return hip_fail(e, "view table upload");
+    }
+    return TOMO_OK;
+}
+
+PlanRef get_plan(const tomo_geometry *g, int *status)
+{
+    int64_t npix = 0;
+    int rc = validate_geometry_impl(g, &npix);
+    if (rc) {
+        *status = rc;
+        return nullptr;
+    }
+    std::vector<unsigned char> key = geometry_key(g);
+    const uint64_t h = fnv1a(key.data(), key.size());
+    int dev = 0;
+    hipGetDevice(&dev);
+    const uint64_t hd = h ^ ((uint64_t)dev * 0x9e3779b97f4a7c15ull);
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    auto &bucket = g_cache[hd];
+    for (auto &e : bucket)
+        if (e.key == key) return e.plan;
+    if (g_cache.size() > 256) g_cache.clear();  // bound the cache; plans are rebuilt on demand
+    CacheEntry ent;
+    ent.key = std::move(key);
+    ent.plan = std::make_shared<Plan>();
+    rc = build_plan(g, npix, *ent.plan);
+    if (rc) {
+        *status = rc;
+        return nullptr;
+    }
+    PlanRef out = ent.plan;
+    g_cache[hd].push_back(std::move(ent));
+    return out;
+}
+
+}  // namespace tomo
+
+using namespace tomo;
+
+extern "C" {
+
+int tomo_validate_geometry(const tomo_geometry *g) { return validate_geometry_impl(g, nullptr); }
+
+int64_t tomo_geometry_pixels(const tomo_geometry *g)
+{
+    int64_t n = 0;
+    return validate_geometry_impl(g, &n) ? 0 : n;
+}
+
+void tomo_release_cache(void)
+{
+    std::lock_guard<std::mutex> lock(g_cache_mu);
+    g_cache.clear();
+}
+
+const char *tomo_status_string(int status)
+{
+    switch (status) {
+    case TOMO_OK: return "ok";
+    case TOMO_EINVAL: return "invalid argument";
+    case TOMO_EHIP: return "HIP runtime error";
+    case TOMO_ENONFINITE: return "non-finite value in the solver";
+    case TOMO_ENOCONV: return "not converged within max_iter";
+    case TOMO_ENOMEM: return "out of memory";
+    case TOMO_EUNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+    }
+}
+
+const char *tomo_last_error(void) { return g_last_error.c_str(); }
+
+int tomo_project(const tomo_geometry *g, const float *cube_d, float *images_d, tomo_stream stream)
+{
+    if (!cube_d || !images_d) return set_error(TOMO_EINVAL, "tomo_project: NULL array");
+    int st = TOMO_OK;
+    PlanRef p = get_plan(g, &st);
+    if (!p) return st;
+    return launch_project(*p, g, cube_d, images_d, true, (hipStream_t)stream);
+}
+
+int tomo_backproject_ex(const tomo_geometry *g, const float *images_d, float *cube_d,
+                        int accumulate, int strategy, tomo_stream stream)
+{
+    if (!cube_d || !images_d) return set_error(TOMO_EINVAL, "tomo_backproject: NULL array");
+    if (strategy < TOMO_BP_AUTO || strategy > TOMO_BP_BINNED)
+        return set_error(TOMO_EINVAL, "tomo_backproject: unknown strategy %d", strategy);
+    int st = TOMO_OK;
+    PlanRef p = get_plan(g, &st);
+    if (!p) return st;
+    return launch_backproject(*p, g, images_d, cube_d, accumulate != 0, true, strategy,
+                              (hipStream_t)stream);
+}
+
+int tomo_backproject(const tomo_geometry *g, const float *images_d, float *cube_d, int accumulate,
+                     tomo_stream stream)
+{
+    return tomo_backproject_ex(g, images_d, cube_d, accumulate, TOMO_BP_AUTO, stream);
+}
+
+// Helioprojective TAN pointing.  Cube frame: x toward heliographic
+// longitude 0 / latitude 0, z toward solar north.  At the observer, S points
+// to Sun centre, N is solar north projected perpendicular to S, and
+// W = S x N is solar west.  A helioprojective direction (tx, ty) is
+// cos(ty) cos(tx) S + cos(ty) sin(tx) W + sin(ty) N.  The detector frame at
+// the reference direction w uses the local unit tangent along +ty for v and
+// u = w x v along +tx, turned by the image rotation crota.
+int tomo_view_from_wcs(double dsun, double hgln_deg, double hglt_deg, double crval1_as,
+                       double crval2_as, double crota_deg, double cdelt1_as, double cdelt2_as,
+                       double crpix1, double crpix2, int32_t ncol, int32_t nrow, tomo_view *out)
+{
+    if (!out) return set_error(TOMO_EINVAL, "tomo_view_from_wcs: out is NULL");
+    const double in[] = {dsun, hgln_deg, hglt_deg, crval1_as, crval2_as, crota_deg, cdelt1_as,
+                         cdelt2_as, crpix1, crpix2};
+    for (double x : in)
+        if (!isfinite(x)) return set_error(TOMO_EINVAL, "tomo_view_from_wcs: non-finite keyword");
+    if (!(dsun > 0) || cdelt1_as == 0 || cdelt2_as == 0 || ncol < 1 || nrow < 1)
+        return set_error(TOMO_EINVAL, "tomo_view_from_wcs: invalid distance, scale or size");
+    const double deg = M_PI / 180.0, arcsec = deg / 3600.0;
+    const double lon = hgln_deg * deg, lat = hglt_deg * deg;
+    const double cl = cos(lat);
+    double obs[3] = {dsun * cl * cos(lon), dsun * cl * sin(lon), dsun * sin(lat)};
+    double S[3] = {-cl * cos(lon), -cl * sin(lon), -sin(lat)};
+    double N[3] = {-S[2] * S[0], -S[2] * S[1], 1.0 - S[2] * S[2]};
+    const double nn = sqrt(dot3(N, N));
+    for (double &x : N) x /= nn;
+    const double W[3] = {S[1] * N[2] - S[2] * N[1], S[2] * N[0] - S[0] * N[2], S[0] * N[1] - S[1] * N[0]};
+    const double tx = crval1_as * arcsec, ty = crval2_as * arcsec;
+    const double a = cos(ty) * cos(tx), b = cos(ty) * sin(tx), c = sin(ty);
+    const double ea = -sin(ty) * cos(tx), eb = -sin(ty) * sin(tx), ec = cos(ty);
+    double w[3], ety[3], etx[3];
+    for (int k = 0; k < 3; ++k) {
+        w[k] = a * S[k] + b * W[k] + c * N[k];
+        ety[k] = ea * S[k] + eb * W[k] + ec * N[k];
+    }
+    etx[0] = w[1] * ety[2] - w[2] * ety[1];
+    etx[1] = w[2] * ety[0] - w[0] * ety[2];
+    etx[2] = w[0] * ety[1] - w[1] * ety[0];
+    const double cr = cos(crota_deg * deg), sr = sin(crota_deg * deg);
+    for (int k = 0; k < 3; ++k) {
+        out->obs[k] = obs[k];
+        out->w[k] = w[k];
+        out->u[k] = cr * etx[k] + sr * ety[k];
+        out->v[k] = -sr * etx[k] + cr * ety[k];
+    }
+    out->cdelt[0] = cdelt1_as * arcsec;
+    out->cdelt[1] = cdelt2_as * arcsec;
+    out->crpix[0] = crpix1 - 1.0;
+    out->crpix[1] = crpix2 - 1.0;
+    out->ncol = ncol;
+    out->nrow = nrow;
+    out->frame = 0;
+    out->reserved = 0;
+    return TOMO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,147 @@
+// Internal definitions shared by the libtomo HIP sources (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <memory>
+
+#include "../../include/tomo.h"
+
+namespace tomo {
+
+constexpr int kThreads = 256;  // every kernel uses 256-lane workgroups
+constexpr int kTile = 16;      // a projector workgroup covers 16x16 pixels
+constexpr double kFar = 1.0e300;  // "never crossed" (finite: keeps fmin cheap)
+
+// Per-view constants, built in FP64 on the host from a tomo_view.
+struct ViewDev {
+    double o[3];        // observer
+    double w[3];        // tangent point direction
+    double u[3];        // +column direction
+    double v[3];        // +row direction
+    double cd[2];       // cdelt (radians per pixel)
+    double cp[2];       // crpix (0-based)
+    int64_t pix_off;    // first pixel of the view in the image vector
+    int64_t tile_off;   // first 16x16 tile of the view in a launch
+    int32_t ncol, nrow;
+    int32_t tiles_x;    // tiles per image row
+    int32_t frame;
+};
+
+// Voxel grid, passed to kernels by value.
+struct GridDev {
+    int32_t n[3];
+    int32_t nframes;
+    double lo[3];
+    double hi[3];
+    double delta[3];
+    int64_t nvox;       // voxels per frame
+};
+
+// Wave-level ray bundle inside a 16x16 tile: each 64-lane wavefront takes a
+// bw x bh block of pixels (bw * bh == 64), and the four wavefronts tile the
+// 16x16 workgroup tile.
+struct Bundle {
+    int32_t log2_bw;    // 3 -> 8x8, 4 -> 16x4, 2 -> 4x16
+    int32_t xcd_remap;  // 1: give each XCD a contiguous range of tiles
+};
+
+// Raw buffer resource over [base, base + bytes): loads outside the range
+// return 0 and stores/atomics outside it are dropped by the hardware.
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
+{
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, (int)bytes,
+                                             0x00020000);
+}
+
+__device__ inline float buf_load_f32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+
+__device__ inline uint32_t buf_load_u8(__amdgpu_buffer_rsrc_t r, uint32_t byte_off)
+{
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, (int)byte_off, 0, 0);
+}
+
+__device__ inline void buf_atomic_add_f32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, float v)
+{
+    __builtin_amdgcn_raw_ptr_buffer_atomic_fadd_f32(v, r, (int)byte_off, 0, 0);
+}
+
+// MI355X hands consecutive workgroups to its 8 XCDs in turn.  Remapping the
+// block index gives each XCD (and its L2) one contiguous run of tiles, so
+// the blocks resident on an XCD walk neighbouring rays through the same part
+// of the cube.  Bijective on [0, nb).
+__device__ inline int64_t xcd_remap(int64_t b, int64_t nb)
+{
+    const int64_t q = nb >> 3, r = nb & 7;
+    const int64_t x = b & 7, i = b >> 3;
+    return x * q + (x < r ? x : r) + i;
+}
+
+// Sum of one double per thread over a 256-thread block; the result is valid
+// in thread 0.  Fixed order, so deterministic.
+__device__ inline double block_sum(double v, double *lds /* >= 4 */)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) s = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+    __syncthreads();
+    return s;
+}
+
+__device__ inline int64_t block_sum_i64(int64_t v, int64_t *lds /* >= 4 */)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) lds[wid] = v;
+    __syncthreads();
+    int64_t s = 0;
+    if (threadIdx.x == 0) s = (lds[0] + lds[1]) + (lds[2] + lds[3]);
+    __syncthreads();
+    return s;
+}
+
+// ------------------------------------------------------------ host side
+
+// Device copy of a geometry's view table plus launch constants.
+struct Plan {
+    GridDev grid;
+    ViewDev *views_d = nullptr;  // device [nviews], freed with the plan
+    int32_t nviews = 0;
+    int64_t ntiles = 0;          // 16x16 tiles over all views
+    int64_t npix = 0;            // total pixels
+    int32_t max_steps = 0;       // bound on segments per ray
+    Plan() = default;
+    Plan(const Plan &) = delete;
+    Plan &operator=(const Plan &) = delete;
+    ~Plan() { if (views_d) (void)hipFree(views_d); }
+};
+
+using PlanRef = std::shared_ptr<const Plan>;
+
+// Returns the cached plan for g (building it on first use), or null with the
+// error recorded.  Thread-safe; a plan stays valid while referenced even if
+// the cache is released.
+PlanRef get_plan(const tomo_geometry *g, int *status);
+
+int set_error(int status, const char *fmt, ...);
+int hip_fail(hipError_t e, const char *what);
+int validate_cube(const tomo_cube *c);
+
+// Launchers (siddon.hip)
+int launch_project(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
+                   bool use_map_mask, hipStream_t s);
+int launch_backproject(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
+                       bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
+                       const int *done_flag = nullptr);
+int launch_project_flagged(const Plan &p, const tomo_geometry *g, const float *cube,
+                           float *images, hipStream_t s, const int *done_flag);
+int launch_fill(float *x, int64_t n, float v, hipStream_t s);
+
+}  // namespace tomo

@@ -1,0 +1,452 @@
+// Siddon line-of-sight projector P and its transpose P^T for gfx950.
+//
+// What is computed (TomograPy, Eq. lo): for every detector pixel, the sum
+// over the voxels its line of sight crosses of (length inside the voxel) x
+// (voxel value); the transpose scatters the same lengths times the pixel
+// value.  Siddon's method finds the lengths from the ray's crossings of the
+// x, y and z voxel planes taken in increasing order.
+//
+// GPU design (not the paper's OpenMP scheme):
+// * One ray per lane.  A 256-lane workgroup owns a 16x16 pixel tile of one
+//   view and each 64-lane wavefront a compact bundle (8x8 by default), so
+//   the lanes of a wave walk neighbouring rays and gather from the same few
+//   cache lines at each step.
+// * Ray set-up in FP64 (slab clip against the box, entry voxel, first
+//   crossing per axis, exit), then an incremental walk that keeps the three
+//   "next crossing" parameters relative to the entry point.  The first
+//   crossing and the spacing of each axis are rounded to one power-of-two
+//   grid sized to the ray's chord, so that every crossing value fits in 51
+//   significant bits: the incremental additions are then exact, each
+//   crossing equals first + j * spacing exactly, and the exit (the same
+//   expression at the box face) is reached exactly, so a ray can never step
+//   past the face before it stops.  The rounding moves crossings by < 1e-15
+//   of the chord.  FP64 issues at the same VALU rate as unpacked FP32 on
+//   CDNA and keeps segment lengths exact to ~1e-15, far inside the required
+//   tolerances, and dyadic rays come out bit-exact.
+// * Gathers and atomics go through raw buffer resources: 32-bit offsets and
+//   a hardware range check (out-of-range loads read 0, atomics are dropped).
+// * P^T uses hardware FP32 atomic adds at L2 (buffer_atomic_add_f32).
+// * P and P^T share the walk routine, so their matrices are identical.
+#include <math.h>
+#include <stdio.h>
+
+#include "common.h"
+
+namespace tomo {
+
+struct RayState {
+    double s[3];   // next crossing on each axis (ray parameter from the entry)
+    double ds[3];  // parameter spacing of consecutive planes on each axis
+    double send;   // exit parameter
+    double dn;     // |d|: converts parameter differences to lengths
+    int32_t off;   // flat offset of the current voxel within its frame
+    int32_t st[3]; // signed flat stride of a step on each axis
+};
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Line of sight through pixel (col, row): gnomonic pinhole d = w + x u + y v.
+// Returns false if the half-line misses the (half-open) box.
+__device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, int row,
+                                 RayState &r)
+{
+    const double x = ((double)col - v.cp[0]) * v.cd[0];
+    const double y = ((double)row - v.cp[1]) * v.cd[1];
+    double d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = v.w[a] + x * v.u[a] + y * v.v[a];
+    r.dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+
+    // slab clip of t >= 0 against the box
+    double tin = 0.0, tout = kFar;
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] != 0.0) {
+            const double t1 = (g.lo[a] - v.o[a]) / d[a];
+            const double t2 = (g.hi[a] - v.o[a]) / d[a];
+            tin = fmax(tin, fmin(t1, t2));
+            tout = fmin(tout, fmax(t1, t2));
+        } else {
+            inside = inside && (g.lo[a] <= v.o[a]) && (v.o[a] < g.hi[a]);
+        }
+    }
+    if (!inside || !(tout > tin)) return false;
+
+    int idx[3];
+    double sf[3], ds[3], jface[3];
+    const int32_t stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int N = g.n[a];
+        if (d[a] != 0.0) {
+            // voxel entered first: half-open voxels, so a ray starting on a
+            // plane belongs to the voxel on the side it moves into
+            const double p = (v.o[a] + tin * d[a] - g.lo[a]) / g.delta[a];
+            const bool up = d[a] > 0.0;
+            int i = up ? clampi((int)floor(p), 0, N - 1) : clampi((int)ceil(p) - 1, 0, N - 1);
+            const double k0 = up ? (double)(i + 1) : (double)i;  // first plane ahead
+            sf[a] = (g.lo[a] + k0 * g.delta[a] - v.o[a]) / d[a] - tin;
+            ds[a] = g.delta[a] / fabs(d[a]);
+            jface[a] = up ? (double)N - k0 : k0;  // crossings to reach the far face
+            if (sf[a] <= 0.0) {  // rounding put the entry just before plane k0
+                i = clampi(i + (up ? 1 : -1), 0, N - 1);
+                sf[a] += ds[a];
+                jface[a] -= 1.0;
+            }
+            idx[a] = i;
+            r.st[a] = up ? stride[a] : -stride[a];
+        } else {
+            idx[a] = clampi((int)floor((v.o[a] - g.lo[a]) / g.delta[a]), 0, N - 1);
+            sf[a] = kFar;
+            ds[a] = 0.0;
+            jface[a] = 0.0;
+            r.st[a] = 0;
+        }
+    }
+    // Only values up to ~3 chords are ever compared: an axis whose first
+    // crossing lies beyond 2 chords is never crossed, and a spacing above
+    // 2 chords means at most one crossing, so both are capped.  Then every
+    // value the walk forms is below span = 4 chords, and a power-of-two grid
+    // q with span < 2^51 q makes all the additions exact.
+    const double chord = tout - tin, lim = 2.0 * chord;
+    int ex = 0;
+    (void)frexp(4.0 * chord, &ex);  // 4 chord < 2^ex
+    double send = kFar;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] != 0.0 && sf[a] <= lim) {
+            ds[a] = ldexp(rint(ldexp(fmin(ds[a], lim), 51 - ex)), ex - 51);
+            sf[a] = ldexp(rint(ldexp(sf[a], 51 - ex)), ex - 51);
+            send = fmin(send, sf[a] + jface[a] * ds[a]);
+        } else {
+            sf[a] = kFar;
+            ds[a] = 0.0;
+        }
+        r.s[a] = sf[a];
+        r.ds[a] = ds[a];
+    }
+    if (!(send > 0.0) || !(send < kFar)) return false;
+    r.send = send;
+    r.off = (idx[2] * g.n[1] + idx[1]) * g.n[0] + idx[0];
+    return true;
+}
+
+// Walk the ray voxel by voxel.  visit(off, dl) receives the flat voxel
+// offset and the parameter length of the segment (length = dl * |d|).
+// Simultaneous crossings advance every tied axis in one step.  maxit bounds
+// the loop whatever the arithmetic does.
+template <class Visit>
+__device__ inline void ray_walk(RayState &r, int maxit, Visit &&visit)
+{
+    double scur = 0.0;
+    for (int it = 0; it < maxit; ++it) {
+        const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
+        visit(r.off, m - scur);
+        if (m >= r.send) break;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const bool t = (r.s[a] == m);
+            r.s[a] += t ? r.ds[a] : 0.0;  // exact on the common grid
+            r.off += t ? r.st[a] : 0;
+        }
+        scur = m;
+    }
+}
+
+// Tile -> (view, pixel of this lane).  Views are sorted by tile_off.
+struct LanePixel {
+    int view;
+    int col, row;
+};
+
+__device__ inline LanePixel lane_pixel(const ViewDev *__restrict__ views, int nviews, int64_t tile,
+                                       int log2_bw)
+{
+    int lo = 0, hi = nviews - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t t = tile - views[lo].tile_off;
+    const int tpr = views[lo].tiles_x;
+    const int tx = (int)(t % tpr), ty = (int)(t / tpr);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int bw = 1 << log2_bw, bh = 64 >> log2_bw;
+    const int wpr = kTile >> log2_bw;  // wave bundles per tile row
+    LanePixel lp;
+    lp.view = lo;
+    lp.col = tx * kTile + (w % wpr) * bw + (l & (bw - 1));
+    lp.row = ty * kTile + (w / wpr) * bh + (l >> log2_bw);
+    return lp;
+}
+
+__device__ inline int64_t block_tile(const Bundle &b)
+{
+    return b.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+}
+
+// ------------------------------------------------------------- kernels
+
+template <bool kMapMask, bool kDataMask>
+__global__ __launch_bounds__(kThreads) void k_project(
+    GridDev g, const ViewDev *__restrict__ views, int32_t nviews, Bundle bun, int32_t maxit,
+    const float *__restrict__ cube, const uint8_t *__restrict__ map_mask,
+    const uint8_t *__restrict__ data_mask, float *__restrict__ images,
+    const int *__restrict__ done_flag)
+{
+    if (done_flag && *done_flag) return;
+    const LanePixel lp = lane_pixel(views, nviews, block_tile(bun), bun.log2_bw);
+    const ViewDev &v = views[lp.view];
+    if (lp.col >= v.ncol || lp.row >= v.nrow) return;
+    const int64_t pix = v.pix_off + (int64_t)lp.row * v.ncol + lp.col;
+    float out = 0.0f;
+    RayState r;
+    if ((!kDataMask || data_mask[pix]) && ray_setup(g, v, lp.col, lp.row, r)) {
+        const auto rc = make_rsrc(cube + (int64_t)v.frame * g.nvox, (uint32_t)(g.nvox * 4));
+        double acc = 0.0;
+        if constexpr (kMapMask) {
+            const auto rm = make_rsrc(map_mask, (uint32_t)g.nvox);
+            ray_walk(r, maxit, [&](int32_t off, double dl) {
+                const float x = buf_load_f32(rc, (uint32_t)off * 4u);
+                acc = fma(dl, buf_load_u8(rm, (uint32_t)off) ? (double)x : 0.0, acc);
+            });
+        } else {
+            ray_walk(r, maxit, [&](int32_t off, double dl) {
+                acc = fma(dl, (double)buf_load_f32(rc, (uint32_t)off * 4u), acc);
+            });
+        }
+        out = (float)(acc * r.dn);
+    }
+    images[pix] = out;
+}
+
+template <bool kMapMask, bool kDataMask>
+__global__ __launch_bounds__(kThreads) void k_backproject_atomic(
+    GridDev g, const ViewDev *__restrict__ views, int32_t nviews, Bundle bun, int32_t maxit,
+    const float *__restrict__ images, const uint8_t *__restrict__ map_mask,
+    const uint8_t *__restrict__ data_mask, float *__restrict__ cube,
+    const int *__restrict__ done_flag)
+{
+    if (done_flag && *done_flag) return;
+    const LanePixel lp = lane_pixel(views, nviews, block_tile(bun), bun.log2_bw);
+    const ViewDev &v = views[lp.view];
+    if (lp.col >= v.ncol || lp.row >= v.nrow) return;
+    const int64_t pix = v.pix_off + (int64_t)lp.row * v.ncol + lp.col;
+    const float yv = images[pix];
+    if (yv == 0.0f) return;
+    if (kDataMask && !data_mask[pix]) return;
+    RayState r;
+    if (!ray_setup(g, v, lp.col, lp.row, r)) return;
+    const auto rc = make_rsrc(cube + (int64_t)v.frame * g.nvox, (uint32_t)(g.nvox * 4));
+    const double wy = (double)yv * r.dn;
+    if constexpr (kMapMask) {
+        const auto rm = make_rsrc(map_mask, (uint32_t)g.nvox);
+        ray_walk(r, maxit, [&](int32_t off, double dl) {
+            if (buf_load_u8(rm, (uint32_t)off)) buf_atomic_add_f32(rc, (uint32_t)off * 4u, (float)(dl * wy));
+        });
+    } else {
+        ray_walk(r, maxit, [&](int32_t off, double dl) {
+            buf_atomic_add_f32(rc, (uint32_t)off * 4u, (float)(dl * wy));
+        });
+    }
+}
+
+template <bool kDataMask>
+__global__ __launch_bounds__(kThreads) void k_count(GridDev g, const ViewDev *__restrict__ views,
+                                                     int32_t nviews, Bundle bun, int32_t maxit,
+                                                     const uint8_t *__restrict__ data_mask,
+                                                     unsigned long long *__restrict__ total)
+{
+    __shared__ int64_t lds[4];
+    const LanePixel lp = lane_pixel(views, nviews, block_tile(bun), bun.log2_bw);
+    const ViewDev &v = views[lp.view];
+    int64_t cnt = 0;
+    if (lp.col < v.ncol && lp.row < v.nrow) {
+        const int64_t pix = v.pix_off + (int64_t)lp.row * v.ncol + lp.col;
+        RayState r;
+        if ((!kDataMask || data_mask[pix]) && ray_setup(g, v, lp.col, lp.row, r))
+            ray_walk(r, maxit, [&](int32_t, double dl) { cnt += dl * r.dn > 0.0; });
+    }
+    const int64_t s = block_sum_i64(cnt, lds);
+    if (threadIdx.x == 0) atomicAdd(total, (unsigned long long)s);
+}
+
+__global__ void k_trace(GridDev g, const ViewDev *__restrict__ views, int32_t view, int32_t col,
+                        int32_t row, int32_t maxit, int32_t cap, int32_t *__restrict__ idx,
+                        double *__restrict__ len, double *__restrict__ dpar,
+                        int32_t *__restrict__ n_out)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    RayState r;
+    int n = 0;
+    if (ray_setup(g, views[view], col, row, r)) {
+        ray_walk(r, maxit, [&](int32_t off, double dl) {
+            const double l = dl * r.dn;
+            if (l > 0.0) {
+                if (n < cap) {
+                    idx[n] = off;
+                    len[n] = l;
+                    dpar[n] = dl;
+                }
+                ++n;
+            }
+        });
+    }
+    *n_out = n;
+}
+
+__global__ __launch_bounds__(kThreads) void k_fill(float *__restrict__ x, int64_t n, float v)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        x[i] = v;
+}
+
+// ------------------------------------------------------------ launchers
+
+static Bundle default_bundle() { return Bundle{3, 1}; }
+
+static int64_t grid_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
+
+int launch_fill(float *x, int64_t n, float v, hipStream_t s)
+{
+    if (n <= 0) return TOMO_OK;
+    int64_t nb = grid_blocks(n);
+    if (nb > 4096) nb = 4096;
+    hipLaunchKernelGGL(k_fill, dim3((unsigned)nb), dim3(kThreads), 0, s, x, n, v);
+    return hip_fail(hipGetLastError(), "fill kernel launch");
+}
+
+static int launch_project_impl(const Plan &p, const tomo_geometry *g, const float *cube,
+                               float *images, bool use_map_mask, hipStream_t s,
+                               const int *done_flag)
+{
+    const Bundle b = default_bundle();
+    const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;
+    const dim3 grid((unsigned)p.ntiles), blk(kThreads);
+#define TOMO_LAUNCH_P(M, D)                                                                         \
+    hipLaunchKernelGGL((k_project<M, D>), grid, blk, 0, s, p.grid, p.views_d, p.nviews, b,           \
+                       p.max_steps, cube, g->map_mask, g->data_mask, images, done_flag)
+    if (mm && dm) TOMO_LAUNCH_P(true, true);
+    else if (mm) TOMO_LAUNCH_P(true, false);
+    else if (dm) TOMO_LAUNCH_P(false, true);
+    else TOMO_LAUNCH_P(false, false);
+#undef TOMO_LAUNCH_P
+    return hip_fail(hipGetLastError(), "projection kernel launch");
+}
+
+int launch_project(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
+                   bool use_map_mask, hipStream_t s)
+{
+    return launch_project_impl(p, g, cube, images, use_map_mask, s, nullptr);
+}
+
+int launch_project_flagged(const Plan &p, const tomo_geometry *g, const float *cube,
+                           float *images, hipStream_t s, const int *done_flag)
+{
+    return launch_project_impl(p, g, cube, images, false, s, done_flag);
+}
+
+int launch_backproject(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
+                       bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
+                       const int *done_flag)
+{
+    (void)strategy;  // only the atomic strategy exists so far
+    if (!accumulate) {
+        int rc = launch_fill(cube, p.grid.nvox * p.grid.nframes, 0.0f, s);
+        if (rc) return rc;
+    }
+    const Bundle b = default_bundle();
+    const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;
+    const dim3 grid((unsigned)p.ntiles), blk(kThreads);
+#define TOMO_LAUNCH_BP(M, D)                                                                        \
+    hipLaunchKernelGGL((k_backproject_atomic<M, D>), grid, blk, 0, s, p.grid, p.views_d, p.nviews,  \
+                       b, p.max_steps, images, g->map_mask, g->data_mask, cube, done_flag)
+    if (mm && dm) TOMO_LAUNCH_BP(true, true);
+    else if (mm) TOMO_LAUNCH_BP(true, false);
+    else if (dm) TOMO_LAUNCH_BP(false, true);
+    else TOMO_LAUNCH_BP(false, false);
+#undef TOMO_LAUNCH_BP
+    return hip_fail(hipGetLastError(), "back-projection kernel launch");
+}
+
+}  // namespace tomo
+
+using namespace tomo;
+
+extern "C" int tomo_count_crossings(const tomo_geometry *g, int64_t *total_h, tomo_stream stream)
+{
+    if (!total_h) return set_error(TOMO_EINVAL, "tomo_count_crossings: total_h is NULL");
+    int st = TOMO_OK;
+    PlanRef p = get_plan(g, &st);
+    if (!p) return st;
+    hipStream_t s = (hipStream_t)stream;
+    unsigned long long *d = nullptr;
+    if (hipMallocAsync((void **)&d, sizeof(*d), s) != hipSuccess)
+        return set_error(TOMO_ENOMEM, "tomo_count_crossings: device allocation failed");
+    (void)hipMemsetAsync(d, 0, sizeof(*d), s);
+    const Bundle b = default_bundle();
+    if (g->data_mask)
+        hipLaunchKernelGGL((k_count<true>), dim3((unsigned)p->ntiles), dim3(kThreads), 0, s, p->grid,
+                           p->views_d, p->nviews, b, p->max_steps, g->data_mask, d);
+    else
+        hipLaunchKernelGGL((k_count<false>), dim3((unsigned)p->ntiles), dim3(kThreads), 0, s,
+                           p->grid, p->views_d, p->nviews, b, p->max_steps, g->data_mask, d);
+    int rc = hip_fail(hipGetLastError(), "count kernel launch");
+    unsigned long long h = 0;
+    if (!rc) rc = hip_fail(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s), "copy count");
+    if (!rc) rc = hip_fail(hipStreamSynchronize(s), "count synchronise");
+    (void)hipFreeAsync(d, s);
+    if (!rc) *total_h = (int64_t)h;
+    return rc;
+}
+
+extern "C" int tomo_trace_ray(const tomo_geometry *g, int32_t view, int32_t col, int32_t row,
+                              int32_t *idx_h, double *len_h, double *dpar_h, int32_t cap,
+                              int32_t *n_out)
+{
+    if (!idx_h || !len_h || !n_out || cap < 0)
+        return set_error(TOMO_EINVAL, "tomo_trace_ray: NULL output or negative capacity");
+    int st = TOMO_OK;
+    PlanRef p = get_plan(g, &st);
+    if (!p) return st;
+    if (view < 0 || view >= g->nviews || col < 0 || row < 0 || col >= g->views[view].ncol ||
+        row >= g->views[view].nrow)
+        return set_error(TOMO_EINVAL, "tomo_trace_ray: pixel (%d, %d, %d) out of range", view, col,
+                         row);
+    const int32_t need = p->max_steps;
+    int32_t *di = nullptr, *dn = nullptr;
+    double *dl = nullptr, *dp = nullptr;
+    int rc = TOMO_OK;
+    if (hipMalloc((void **)&di, sizeof(int32_t) * need) != hipSuccess ||
+        hipMalloc((void **)&dl, sizeof(double) * need) != hipSuccess ||
+        hipMalloc((void **)&dp, sizeof(double) * need) != hipSuccess ||
+        hipMalloc((void **)&dn, sizeof(int32_t)) != hipSuccess) {
+        rc = set_error(TOMO_ENOMEM, "tomo_trace_ray: device allocation failed");
+    } else {
+        hipLaunchKernelGGL(k_trace, dim3(1), dim3(64), 0, 0, p->grid, p->views_d, view, col, row,
+                           p->max_steps, need, di, dl, dp, dn);
+        rc = hip_fail(hipGetLastError(), "trace kernel launch");
+        int32_t n = 0;
+        if (!rc) rc = hip_fail(hipMemcpy(&n, dn, sizeof(n), hipMemcpyDeviceToHost), "copy count");
+        if (!rc) {
+            *n_out = n;
+            if (n > cap) {
+                rc = set_error(TOMO_EINVAL, "tomo_trace_ray: %d segments exceed capacity %d", n, cap);
+            } else if (n > 0) {
+                rc = hip_fail(hipMemcpy(idx_h, di, sizeof(int32_t) * n, hipMemcpyDeviceToHost), "copy idx");
+                if (!rc)
+                    rc = hip_fail(hipMemcpy(len_h, dl, sizeof(double) * n, hipMemcpyDeviceToHost), "copy len");
+                if (!rc && dpar_h)
+                    rc = hip_fail(hipMemcpy(dpar_h, dp, sizeof(double) * n, hipMemcpyDeviceToHost), "copy dpar");
+            }
+        }
+    }
+    (void)hipFree(di);
+    (void)hipFree(dl);
+    (void)hipFree(dp);
+    (void)hipFree(dn);
+    return rc;
+}

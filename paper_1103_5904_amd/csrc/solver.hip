@@ -1,0 +1,532 @@
+// Regularised inversion: the prior D^T D (+ D_t^T D_t) and conjugate
+// gradient on the normal equations of TomograPy's criterion (Eq. criterion,
+// Eq. stsrt):  A x = b,  A = M (P^T P + lambda_r D^T D + lambda_t D_t^T D_t) M,
+// b = M P^T y.
+//
+// GPU design: FP32 vectors, FP64 dot products and scalars.  Every scalar of
+// the recurrence (alpha, beta, residual norms) lives in device memory and is
+// produced by the last workgroup of the kernel that reduces it, in a fixed
+// order (deterministic).  A device "done" flag, raised when the residual
+// target or the iteration limit is reached, makes every later kernel of the
+// iteration return at once, so the host enqueues iterations in chunks and
+// synchronises only between chunks.  The vector updates are fused into
+// three streaming passes per iteration around one P and one P^T.
+#include <math.h>
+#include <string.h>
+
+#include <vector>
+
+#include "common.h"
+
+namespace tomo {
+
+constexpr int kRedBlocks = 1024;  // workgroups of every reducing vector kernel
+
+struct CgState {
+    double rr;        // r.r (plain CG) or z.r (flexible CG) of the current iterate
+    double pq;        // p.A p
+    double alpha, beta;
+    double bb;        // b.b
+    double thresh2;   // (rtol ||b||)^2, or -1 when no residual target
+    double res2;      // r.r of the current iterate
+    double aux;       // scratch result of the last reduction
+    int32_t iter;     // iterations completed
+    int32_t max_iter; // iteration limit
+    int32_t done;     // 1: stop (converged, limit reached or non-finite)
+    int32_t nonfinite;
+};
+
+struct Workspace {
+    double *partials;   // [kRedBlocks][2]
+    unsigned *counter;  // last-block detection
+    CgState *st;
+    double *hist;       // [max_iter + 1]
+};
+
+// ------------------------------------------------------------ stencils
+
+struct Dims {
+    int32_t nx, ny, nz, nf;
+    int64_t nvox;   // per frame
+    int64_t total;  // nvox * nf
+};
+
+// lambda_r (D^T D x)_v + lambda_t (D_t^T D_t x)_v: forward differences
+// between in-range neighbours only (free ends).
+__device__ inline float prior_at(const float *__restrict__ x, const Dims &d, int64_t idx, float lr,
+                                 float lt)
+{
+    const int64_t f = idx / d.nvox;
+    const int64_t rem = idx - f * d.nvox;
+    const int32_t i = (int32_t)(rem % d.nx);
+    const int64_t jk = rem / d.nx;
+    const int32_t j = (int32_t)(jk % d.ny);
+    const int32_t k = (int32_t)(jk / d.ny);
+    const float c = x[idx];
+    float s = 0.0f;
+    if (i > 0) s += c - x[idx - 1];
+    if (i < d.nx - 1) s += c - x[idx + 1];
+    if (j > 0) s += c - x[idx - d.nx];
+    if (j < d.ny - 1) s += c - x[idx + d.nx];
+    const int64_t pl = (int64_t)d.nx * d.ny;
+    if (k > 0) s += c - x[idx - pl];
+    if (k < d.nz - 1) s += c - x[idx + pl];
+    float out = lr * s;
+    if (lt != 0.0f) {
+        float t = 0.0f;
+        if (f > 0) t += c - x[idx - d.nvox];
+        if (f < d.nf - 1) t += c - x[idx + d.nvox];
+        out += lt * t;
+    }
+    return out;
+}
+
+__global__ __launch_bounds__(kThreads) void k_prior(const float *__restrict__ x,
+                                                    float *__restrict__ out, Dims d, float lr,
+                                                    float lt, int accumulate)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
+         i += (int64_t)gridDim.x * kThreads) {
+        const float v = prior_at(x, d, i, lr, lt);
+        out[i] = accumulate ? out[i] + v : v;
+    }
+}
+
+// --------------------------------------------------------- reductions
+
+// Reduce two doubles per thread over the whole grid.  Returns true in the
+// last workgroup to finish, whose thread 0 then holds the grid totals in
+// (t0, t1).  The partials are summed in block order: deterministic.
+__device__ inline bool grid_reduce2(double a, double b, const Workspace &ws, double &t0, double &t1)
+{
+    __shared__ double lds[4];
+    __shared__ int last;
+    const double sa = block_sum(a, lds);
+    const double sb = block_sum(b, lds);
+    if (threadIdx.x == 0) {
+        ws.partials[2 * blockIdx.x] = sa;
+        ws.partials[2 * blockIdx.x + 1] = sb;
+        __threadfence();
+        const unsigned prev = atomicAdd(ws.counter, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (!last) return false;
+    __threadfence();
+    double pa = 0.0, pb = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads) {
+        pa += __builtin_nontemporal_load(&ws.partials[2 * i]);
+        pb += __builtin_nontemporal_load(&ws.partials[2 * i + 1]);
+    }
+    t0 = block_sum(pa, lds);
+    t1 = block_sum(pb, lds);
+    if (threadIdx.x == 0) *ws.counter = 0u;
+    return true;
+}
+
+__device__ inline bool bad(double v) { return !isfinite(v); }
+
+// r = b - q (or r = b), p = r, q = 0; state from r.r and b.b.
+__global__ __launch_bounds__(kThreads) void k_cg_start(const float *__restrict__ b,
+                                                       float *__restrict__ r, float *__restrict__ p,
+                                                       float *__restrict__ q, int64_t n,
+                                                       int subtract_q, Workspace ws, double rtol,
+                                                       int32_t max_iter, int32_t iter0)
+{
+    double rr = 0.0, bb = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const float bv = b[i];
+        const float rv = subtract_q ? (float)((double)bv - (double)q[i]) : bv;
+        r[i] = rv;
+        p[i] = rv;
+        q[i] = 0.0f;
+        rr += (double)rv * rv;
+        bb += (double)bv * bv;
+    }
+    double trr, tbb;
+    if (grid_reduce2(rr, bb, ws, trr, tbb) && threadIdx.x == 0) {
+        CgState &s = *ws.st;
+        s.rr = trr;
+        s.res2 = trr;
+        s.bb = tbb;
+        s.thresh2 = rtol > 0.0 ? rtol * rtol * tbb : -1.0;
+        s.iter = iter0;
+        s.max_iter = max_iter;
+        s.nonfinite = bad(trr) || bad(tbb);
+        s.done = s.nonfinite || tbb == 0.0 || trr <= s.thresh2 || iter0 >= max_iter;
+        ws.hist[iter0] = tbb > 0.0 ? sqrt(trr / tbb) : 0.0;
+    }
+}
+
+// q = M (q + prior(p)); pq = p.q; alpha = rr / pq.
+__global__ __launch_bounds__(kThreads) void k_cg_q(const float *__restrict__ p,
+                                                   float *__restrict__ q,
+                                                   const uint8_t *__restrict__ map_mask, Dims d,
+                                                   float lr, float lt, Workspace ws)
+{
+    if (ws.st->done) return;
+    double pq = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
+         i += (int64_t)gridDim.x * kThreads) {
+        float v = q[i] + prior_at(p, d, i, lr, lt);
+        if (map_mask && !map_mask[i % d.nvox]) v = 0.0f;
+        q[i] = v;
+        pq += (double)p[i] * v;
+    }
+    double tpq, unused;
+    if (grid_reduce2(pq, 0.0, ws, tpq, unused) && threadIdx.x == 0) {
+        CgState &s = *ws.st;
+        s.pq = tpq;
+        s.alpha = s.rr / tpq;
+        if (bad(s.alpha) || !(tpq > 0.0)) {
+            s.nonfinite = 1;
+            s.done = 1;
+        }
+    }
+}
+
+// x += alpha p; r -= alpha q; q = 0; rr_new = r.r; beta = rr_new / rr.
+__global__ __launch_bounds__(kThreads) void k_cg_xr(float *__restrict__ x, float *__restrict__ r,
+                                                    const float *__restrict__ p,
+                                                    float *__restrict__ q, int64_t n, Workspace ws)
+{
+    if (ws.st->done) return;
+    const double alpha = ws.st->alpha;
+    double rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const float pv = p[i];
+        x[i] = (float)((double)x[i] + alpha * pv);
+        const float rv = (float)((double)r[i] - alpha * q[i]);
+        r[i] = rv;
+        q[i] = 0.0f;
+        rr += (double)rv * rv;
+    }
+    double trr, unused;
+    if (grid_reduce2(rr, 0.0, ws, trr, unused) && threadIdx.x == 0) {
+        CgState &s = *ws.st;
+        s.beta = trr / s.rr;
+        s.rr = trr;
+        s.res2 = trr;
+        s.iter += 1;
+        ws.hist[s.iter] = sqrt(trr / s.bb);
+        if (bad(trr) || bad(s.beta)) s.nonfinite = 1;
+        s.done = s.nonfinite || trr <= s.thresh2 || s.iter >= s.max_iter;
+    }
+}
+
+// p = r + beta p.
+__global__ __launch_bounds__(kThreads) void k_cg_p(const float *__restrict__ r,
+                                                   float *__restrict__ p, int64_t n,
+                                                   const CgState *__restrict__ st)
+{
+    if (st->done) return;
+    const double beta = st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        p[i] = (float)((double)r[i] + beta * p[i]);
+}
+
+// q = M (q + prior(x)); aux = |b - q|^2 (true residual of x).
+__global__ __launch_bounds__(kThreads) void k_true_res(const float *__restrict__ x,
+                                                       float *__restrict__ q,
+                                                       const float *__restrict__ b,
+                                                       const uint8_t *__restrict__ map_mask,
+                                                       Dims d, float lr, float lt, Workspace ws)
+{
+    double rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
+         i += (int64_t)gridDim.x * kThreads) {
+        float v = q[i] + prior_at(x, d, i, lr, lt);
+        if (map_mask && !map_mask[i % d.nvox]) v = 0.0f;
+        q[i] = v;
+        const double e = (double)b[i] - v;
+        rr += e * e;
+    }
+    double t, unused;
+    if (grid_reduce2(rr, 0.0, ws, t, unused) && threadIdx.x == 0) ws.st->aux = t;
+}
+
+// x = M x (masked start point).
+__global__ __launch_bounds__(kThreads) void k_mask(float *__restrict__ x,
+                                                   const uint8_t *__restrict__ map_mask, Dims d)
+{
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
+         i += (int64_t)gridDim.x * kThreads)
+        if (!map_mask[i % d.nvox]) x[i] = 0.0f;
+}
+
+// ------------------------------------------------------------ host side
+
+static Dims dims_of(const tomo_cube &c)
+{
+    Dims d;
+    d.nx = c.nx;
+    d.ny = c.ny;
+    d.nz = c.nz;
+    d.nf = c.nframes;
+    d.nvox = (int64_t)c.nx * c.ny * c.nz;
+    d.total = d.nvox * c.nframes;
+    return d;
+}
+
+static unsigned elem_blocks(int64_t n)
+{
+    int64_t nb = (n + kThreads - 1) / kThreads;
+    return (unsigned)(nb > kRedBlocks ? kRedBlocks : (nb < 1 ? 1 : nb));
+}
+
+// Device allocations of one solve, released on every exit path.
+struct SolveBuffers {
+    hipStream_t s = nullptr;
+    std::vector<void *> ptrs;
+    void *alloc(size_t bytes)
+    {
+        void *p = nullptr;
+        if (hipMallocAsync(&p, bytes, s) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return p;
+    }
+    ~SolveBuffers()
+    {
+        for (void *p : ptrs) (void)hipFreeAsync(p, s);
+    }
+};
+
+struct EventPool {
+    std::vector<hipEvent_t> ev;
+    hipEvent_t get()
+    {
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        ev.push_back(e);
+        return e;
+    }
+    ~EventPool()
+    {
+        for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    }
+};
+
+}  // namespace tomo
+
+using namespace tomo;
+
+extern "C" {
+
+void tomo_cg_default_params(tomo_cg_params *p)
+{
+    if (!p) return;
+    memset(p, 0, sizeof(*p));
+    p->lambda_r = 1e-2;
+    p->max_iter = 50;
+    p->check_every = 10;
+    p->fallback_window = 3;
+    p->min_drop = 1e-6;
+}
+
+int tomo_apply_prior(const tomo_cube *cube, double lambda_r, double lambda_t, const float *x_d,
+                     float *out_d, int accumulate, tomo_stream stream)
+{
+    int rc = validate_cube(cube);
+    if (rc) return rc;
+    if (!x_d || !out_d) return set_error(TOMO_EINVAL, "tomo_apply_prior: NULL array");
+    if (!(lambda_r >= 0) || !(lambda_t >= 0) || !isfinite(lambda_r) || !isfinite(lambda_t))
+        return set_error(TOMO_EINVAL, "tomo_apply_prior: weights must be finite and >= 0");
+    if (x_d == out_d) return set_error(TOMO_EINVAL, "tomo_apply_prior: x and out must differ");
+    const Dims d = dims_of(*cube);
+    hipLaunchKernelGGL(k_prior, dim3(elem_blocks(d.total)), dim3(kThreads), 0,
+                       (hipStream_t)stream, x_d, out_d, d, (float)lambda_r, (float)lambda_t,
+                       accumulate);
+    return hip_fail(hipGetLastError(), "prior kernel launch");
+}
+
+int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const tomo_cg_params *prm,
+                  tomo_cg_report *rep, tomo_stream stream)
+{
+    if (!y_d || !x_d || !prm || !rep) return set_error(TOMO_EINVAL, "tomo_cg_solve: NULL argument");
+    if (!(prm->lambda_r >= 0) || !(prm->lambda_t >= 0) || !isfinite(prm->lambda_r) ||
+        !isfinite(prm->lambda_t) || prm->max_iter < 0 || !(prm->rtol >= 0) ||
+        !isfinite(prm->rtol) || prm->check_every < 1)
+        return set_error(TOMO_EINVAL, "tomo_cg_solve: invalid parameters");
+    if (prm->precond)
+        return set_error(TOMO_EUNSUPPORTED, "tomo_cg_solve: preconditioner not available");
+    int st = TOMO_OK;
+    PlanRef plan = get_plan(g, &st);
+    if (!plan) return st;
+    if (prm->lambda_t > 0 && g->cube.nframes < 2)
+        return set_error(TOMO_EINVAL, "tomo_cg_solve: lambda_t needs nframes >= 2");
+    hipStream_t s = (hipStream_t)stream;
+    const Dims d = dims_of(g->cube);
+    const int64_t n = d.total;
+    const float lr = (float)prm->lambda_r, lt = (float)prm->lambda_t;
+    const int maxit = prm->max_iter;
+
+    SolveBuffers buf;
+    buf.s = s;
+    float *b = (float *)buf.alloc(sizeof(float) * n);
+    float *r = (float *)buf.alloc(sizeof(float) * n);
+    float *p = (float *)buf.alloc(sizeof(float) * n);
+    float *q = (float *)buf.alloc(sizeof(float) * n);
+    float *img = (float *)buf.alloc(sizeof(float) * plan->npix);
+    Workspace ws;
+    ws.partials = (double *)buf.alloc(sizeof(double) * 2 * kRedBlocks);
+    ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
+    ws.st = (CgState *)buf.alloc(sizeof(CgState));
+    ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)maxit + 1));
+    if (!b || !r || !p || !q || !img || !ws.partials || !ws.counter || !ws.st || !ws.hist)
+        return set_error(TOMO_ENOMEM, "tomo_cg_solve: device allocation failed");
+    int rc = hip_fail(hipMemsetAsync(ws.counter, 0, sizeof(unsigned), s), "counter init");
+    if (rc) return rc;
+    CgState *hst = nullptr;
+    if (hipHostMalloc((void **)&hst, sizeof(CgState)) != hipSuccess)
+        return set_error(TOMO_ENOMEM, "tomo_cg_solve: pinned allocation failed");
+    struct PinnedFree {
+        CgState *p;
+        ~PinnedFree() { (void)hipHostFree(p); }
+    } pin_guard{hst};
+
+    const unsigned eb = elem_blocks(n);
+    int n_proj = 0, n_bp = 0;
+    const bool timed = rep->time_kernels != 0;
+    EventPool evp;
+    std::vector<hipEvent_t> evP, evB;  // start/stop pairs
+
+    // b = M P^T y
+    rc = launch_backproject(*plan, g, y_d, b, false, true, prm->bp_strategy, s);
+    if (rc) return rc;
+    ++n_bp;
+    if (g->map_mask && prm->x0_given) {
+        hipLaunchKernelGGL(k_mask, dim3(eb), dim3(kThreads), 0, s, x_d, g->map_mask, d);
+    }
+    auto apply_A_to = [&](const float *v) -> int {  // q = M (P^T P + prior) v, excluding the prior
+        int e = launch_project(*plan, g, v, img, false, s);
+        if (!e) e = launch_backproject(*plan, g, img, q, false, false, prm->bp_strategy, s);
+        n_proj++;
+        n_bp++;
+        return e;
+    };
+    if (prm->x0_given) {
+        rc = apply_A_to(x_d);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_true_res, dim3(eb), dim3(kThreads), 0, s, x_d, q, b, g->map_mask, d,
+                           lr, lt, ws);
+    } else {
+        rc = launch_fill(x_d, n, 0.0f, s);
+        if (rc) return rc;
+    }
+    hipLaunchKernelGGL(k_cg_start, dim3(eb), dim3(kThreads), 0, s, b, r, p, q, n,
+                       prm->x0_given ? 1 : 0, ws, prm->rtol, maxit, 0);
+    rc = hip_fail(hipGetLastError(), "cg start");
+    if (rc) return rc;
+
+    auto enqueue_iteration = [&]() -> int {
+        hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
+        if (timed) {
+            e0 = evp.get();
+            e1 = evp.get();
+            e2 = evp.get();
+            (void)hipEventRecord(e0, s);
+        }
+        int e = launch_project_flagged(*plan, g, p, img, s, &ws.st->done);
+        if (timed) (void)hipEventRecord(e1, s);
+        if (!e) e = launch_backproject(*plan, g, img, q, true, false, prm->bp_strategy, s, &ws.st->done);
+        if (timed) {
+            (void)hipEventRecord(e2, s);
+            evP.push_back(e0);
+            evP.push_back(e1);
+            evB.push_back(e1);
+            evB.push_back(e2);
+        }
+        if (e) return e;
+        hipLaunchKernelGGL(k_cg_q, dim3(eb), dim3(kThreads), 0, s, p, q, g->map_mask, d, lr, lt, ws);
+        hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
+        hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, s, r, p, n, ws.st);
+        return hip_fail(hipGetLastError(), "cg iteration launch");
+    };
+
+    int done_iters = 0;
+    double true_rel = -1.0;
+    int restarts = 0;
+    for (;;) {
+        // run chunks until the device says stop
+        int enq = 0;
+        while (done_iters + enq < maxit) {
+            const int chunk = prm->rtol > 0 ? prm->check_every : maxit;
+            const int todo = chunk < maxit - done_iters - enq ? chunk : maxit - done_iters - enq;
+            for (int k = 0; k < todo; ++k) {
+                rc = enqueue_iteration();
+                if (rc) return rc;
+            }
+            enq += todo;
+            rc = hip_fail(hipMemcpyAsync(hst, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s), "state copy");
+            if (!rc) rc = hip_fail(hipStreamSynchronize(s), "cg synchronise");
+            if (rc) return rc;
+            if (hst->done) break;
+        }
+        rc = hip_fail(hipMemcpyAsync(hst, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s), "state copy");
+        if (!rc) rc = hip_fail(hipStreamSynchronize(s), "cg synchronise");
+        if (rc) return rc;
+        const int it_now = hst->iter;
+        n_proj += it_now - done_iters;
+        n_bp += it_now - done_iters;
+        done_iters = it_now;
+        if (hst->nonfinite) break;
+        // true residual of x
+        rc = apply_A_to(x_d);
+        if (rc) return rc;
+        hipLaunchKernelGGL(k_true_res, dim3(eb), dim3(kThreads), 0, s, x_d, q, b, g->map_mask, d,
+                           lr, lt, ws);
+        rc = hip_fail(hipMemcpyAsync(hst, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s), "state copy");
+        if (!rc) rc = hip_fail(hipStreamSynchronize(s), "cg synchronise");
+        if (rc) return rc;
+        true_rel = hst->bb > 0 ? sqrt(hst->aux / hst->bb) : 0.0;
+        const bool unconfirmed = prm->rtol > 0 && true_rel > 1.1 * prm->rtol;
+        if (!unconfirmed || done_iters >= maxit || restarts >= 8) break;
+        // restart from the true residual
+        ++restarts;
+        hipLaunchKernelGGL(k_cg_start, dim3(eb), dim3(kThreads), 0, s, b, r, p, q, n, 1, ws,
+                           prm->rtol, maxit, done_iters);
+        rc = hip_fail(hipGetLastError(), "cg restart");
+        if (rc) return rc;
+    }
+
+    // report
+    rc = hip_fail(hipMemcpyAsync(hst, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s), "state copy");
+    if (!rc) rc = hip_fail(hipStreamSynchronize(s), "cg synchronise");
+    if (rc) return rc;
+    rep->iters = hst->iter;
+    rep->fell_back = -1;
+    rep->n_project = n_proj;
+    rep->n_backproject = n_bp;
+    rep->bnorm = sqrt(hst->bb);
+    rep->rel_res = hst->bb > 0 ? sqrt(hst->res2 / hst->bb) : 0.0;
+    rep->true_rel_res = true_rel;
+    if (hst->nonfinite) rep->status = TOMO_ENONFINITE;
+    else if (prm->rtol > 0 && !(true_rel <= 1.1 * prm->rtol)) rep->status = TOMO_ENOCONV;
+    else rep->status = TOMO_OK;
+    rep->history_len = 0;
+    if (rep->history && rep->history_cap > 0) {
+        const int nh = hst->iter + 1 < rep->history_cap ? hst->iter + 1 : rep->history_cap;
+        rc = hip_fail(hipMemcpy(rep->history, ws.hist, sizeof(double) * nh, hipMemcpyDeviceToHost),
+                      "history copy");
+        if (rc) return rc;
+        rep->history_len = nh;
+    }
+    rep->ms_project = rep->ms_backproject = 0.0;
+    if (timed) {
+        const size_t np = evP.size() / 2;
+        const size_t use = (size_t)hst->iter < np ? (size_t)hst->iter : np;
+        for (size_t k = 0; k < use; ++k) {
+            float a = 0.f, bms = 0.f;
+            (void)hipEventElapsedTime(&a, evP[2 * k], evP[2 * k + 1]);
+            (void)hipEventElapsedTime(&bms, evB[2 * k], evB[2 * k + 1]);
+            rep->ms_project += a;
+            rep->ms_backproject += bms;
+        }
+    }
+    return TOMO_OK;
+}
+
+}  // extern "C"

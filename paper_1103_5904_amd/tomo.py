@@ -1,0 +1,290 @@
+"""ctypes binding of libtomo (include/tomo.h): argument marshalling only.
+
+Every numeric step runs in the HIP library; PyTorch supplies device memory
+and the current stream.  If libtomo.so has not been built, importing the
+functions works but every call raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_double, c_int32, c_int64, c_void_p
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtomo.so")
+
+TOMO_OK = 0
+TOMO_EINVAL = -1
+TOMO_EHIP = -2
+TOMO_ENONFINITE = -3
+TOMO_ENOCONV = -4
+TOMO_ENOMEM = -5
+TOMO_EUNSUPPORTED = -6
+
+BP_AUTO, BP_ATOMIC, BP_BINNED = 0, 1, 2
+
+
+class TomoError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"libtomo status {status}: {message}")
+        self.status = status
+
+
+class TomoCube(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("nframes", c_int32),
+                ("box_min", c_double * 3), ("box_max", c_double * 3)]
+
+
+class TomoView(ctypes.Structure):
+    _fields_ = [("obs", c_double * 3), ("w", c_double * 3), ("u", c_double * 3),
+                ("v", c_double * 3), ("cdelt", c_double * 2), ("crpix", c_double * 2),
+                ("ncol", c_int32), ("nrow", c_int32), ("frame", c_int32), ("reserved", c_int32)]
+
+
+class TomoGeometry(ctypes.Structure):
+    _fields_ = [("cube", TomoCube), ("nviews", c_int32), ("reserved", c_int32),
+                ("views", POINTER(TomoView)), ("data_mask", c_void_p), ("map_mask", c_void_p)]
+
+
+class CgParams(ctypes.Structure):
+    _fields_ = [("lambda_r", c_double), ("lambda_t", c_double), ("max_iter", c_int32),
+                ("x0_given", c_int32), ("rtol", c_double), ("check_every", c_int32),
+                ("use_graph", c_int32), ("precond", c_void_p), ("fallback_window", c_int32),
+                ("bp_strategy", c_int32), ("min_drop", c_double)]
+
+
+class CgReport(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("status", c_int32), ("fell_back", c_int32),
+                ("n_project", c_int32), ("n_backproject", c_int32), ("reserved", c_int32),
+                ("rel_res", c_double), ("true_rel_res", c_double), ("bnorm", c_double),
+                ("ms_project", c_double), ("ms_backproject", c_double),
+                ("history", POINTER(c_double)), ("history_cap", c_int32),
+                ("history_len", c_int32), ("time_kernels", c_int32), ("reserved2", c_int32)]
+
+
+EXPORTS = [
+    "tomo_project", "tomo_backproject", "tomo_backproject_ex", "tomo_count_crossings",
+    "tomo_trace_ray", "tomo_apply_prior", "tomo_cg_solve", "tomo_cg_default_params",
+    "tomo_view_from_wcs", "tomo_validate_geometry", "tomo_geometry_pixels",
+    "tomo_release_cache", "tomo_status_string", "tomo_last_error",
+]
+
+_lib = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        L.tomo_status_string.restype = ctypes.c_char_p
+        L.tomo_last_error.restype = ctypes.c_char_p
+        L.tomo_geometry_pixels.restype = c_int64
+        L.tomo_project.argtypes = [POINTER(TomoGeometry), c_void_p, c_void_p, c_void_p]
+        L.tomo_backproject.argtypes = [POINTER(TomoGeometry), c_void_p, c_void_p, ctypes.c_int,
+                                       c_void_p]
+        L.tomo_backproject_ex.argtypes = [POINTER(TomoGeometry), c_void_p, c_void_p, ctypes.c_int,
+                                          ctypes.c_int, c_void_p]
+        L.tomo_count_crossings.argtypes = [POINTER(TomoGeometry), POINTER(c_int64), c_void_p]
+        L.tomo_trace_ray.argtypes = [POINTER(TomoGeometry), c_int32, c_int32, c_int32,
+                                     POINTER(c_int32), POINTER(c_double), POINTER(c_double),
+                                     c_int32, POINTER(c_int32)]
+        L.tomo_apply_prior.argtypes = [POINTER(TomoCube), c_double, c_double, c_void_p, c_void_p,
+                                       ctypes.c_int, c_void_p]
+        L.tomo_cg_solve.argtypes = [POINTER(TomoGeometry), c_void_p, c_void_p, POINTER(CgParams),
+                                    POINTER(CgReport), c_void_p]
+        L.tomo_cg_default_params.argtypes = [POINTER(CgParams)]
+        L.tomo_view_from_wcs.argtypes = [c_double] * 10 + [c_int32, c_int32, POINTER(TomoView)]
+        L.tomo_validate_geometry.argtypes = [POINTER(TomoGeometry)]
+        L.tomo_geometry_pixels.argtypes = [POINTER(TomoGeometry)]
+        _lib = L
+    return _lib
+
+
+def _check(rc):
+    if rc != TOMO_OK:
+        raise TomoError(rc, lib().tomo_last_error().decode())
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev_f32(t, numel, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or not t.is_cuda:
+        raise ValueError(f"{name} must be a float32 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return c_void_p(t.data_ptr())
+
+
+class DeviceGeometry:
+    """Marshals a geometry description (box, views, masks) into a
+    tomo_geometry.  ``geom`` needs the attributes n, lo, hi, views (V x 16:
+    obs, w, u, v, cdelt, crpix), npix (V x 2), view_frame (or None), nframes,
+    data_mask (or None) and map_mask (or None); masks are copied to the
+    device once."""
+
+    def __init__(self, geom, device="cuda"):
+        self.n = tuple(int(k) for k in geom.n)
+        self.nframes = int(getattr(geom, "nframes", 1) or 1)
+        views = np.asarray(geom.views, dtype=np.float64)
+        npix = np.asarray(geom.npix, dtype=np.int64)
+        vf = getattr(geom, "view_frame", None)
+        self.nviews = views.shape[0]
+        arr = (TomoView * self.nviews)()
+        for k in range(self.nviews):
+            row = views[k]
+            tv = arr[k]
+            for a in range(3):
+                tv.obs[a], tv.w[a], tv.u[a], tv.v[a] = row[a], row[3 + a], row[6 + a], row[9 + a]
+            tv.cdelt[0], tv.cdelt[1] = row[12], row[13]
+            tv.crpix[0], tv.crpix[1] = row[14], row[15]
+            tv.ncol, tv.nrow = int(npix[k, 0]), int(npix[k, 1])
+            tv.frame = 0 if vf is None else int(vf[k])
+        self._views = arr
+        self.npix = int(np.sum(npix[:, 0] * npix[:, 1]))
+        self.nvox = self.n[0] * self.n[1] * self.n[2]
+        self.data_mask = self._mask(getattr(geom, "data_mask", None), self.npix, device)
+        self.map_mask = self._mask(getattr(geom, "map_mask", None), self.nvox, device)
+        cube = TomoCube(self.n[0], self.n[1], self.n[2], self.nframes,
+                        (c_double * 3)(*np.asarray(geom.lo, dtype=np.float64)),
+                        (c_double * 3)(*np.asarray(geom.hi, dtype=np.float64)))
+        self.g = TomoGeometry(cube, self.nviews, 0, arr,
+                              None if self.data_mask is None else self.data_mask.data_ptr(),
+                              None if self.map_mask is None else self.map_mask.data_ptr())
+
+    @staticmethod
+    def _mask(m, numel, device):
+        if m is None:
+            return None
+        t = torch.as_tensor(np.ascontiguousarray(m).astype(np.uint8).ravel()).to(device)
+        if t.numel() != numel:
+            raise ValueError(f"mask has {t.numel()} entries, expected {numel}")
+        return t
+
+    @property
+    def cube_shape(self):
+        nx, ny, nz = self.n
+        return (self.nframes, nz, ny, nx) if self.nframes > 1 else (nz, ny, nx)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self.g)
+
+    def validate(self):
+        _check(lib().tomo_validate_geometry(self.ref))
+
+
+def project(geom: DeviceGeometry, cube: torch.Tensor, out: torch.Tensor | None = None):
+    """Images = P M cube (one value per pixel, views concatenated)."""
+    if out is None:
+        out = torch.empty(geom.npix, dtype=torch.float32, device=cube.device)
+    c = _dev_f32(cube, geom.nvox * geom.nframes, "cube")
+    o = _dev_f32(out, geom.npix, "out")
+    _check(lib().tomo_project(geom.ref, c, o, _stream()))
+    return out
+
+
+def backproject(geom: DeviceGeometry, images: torch.Tensor, out: torch.Tensor | None = None,
+                accumulate: bool = False, strategy: int = BP_AUTO):
+    """Cube = M P^T images (or += with accumulate)."""
+    if out is None:
+        out = torch.empty(geom.cube_shape, dtype=torch.float32, device=images.device)
+    y = _dev_f32(images, geom.npix, "images")
+    o = _dev_f32(out, geom.nvox * geom.nframes, "out")
+    _check(lib().tomo_backproject_ex(geom.ref, y, o, int(bool(accumulate)), int(strategy), _stream()))
+    return out
+
+
+def count_crossings(geom: DeviceGeometry) -> int:
+    tot = c_int64(0)
+    _check(lib().tomo_count_crossings(geom.ref, ctypes.byref(tot), _stream()))
+    return int(tot.value)
+
+
+def trace_ray(geom: DeviceGeometry, view: int, col: int, row: int):
+    """Segments of one pixel's ray from the GPU walk: (flat voxel index,
+    length, parametric length)."""
+    cap = sum(geom.n) + 3
+    idx = (c_int32 * cap)()
+    ln = (c_double * cap)()
+    dp = (c_double * cap)()
+    n = c_int32(0)
+    _check(lib().tomo_trace_ray(geom.ref, view, col, row, idx, ln, dp, cap, ctypes.byref(n)))
+    k = n.value
+    return (np.ctypeslib.as_array(idx)[:k].copy(), np.ctypeslib.as_array(ln)[:k].copy(),
+            np.ctypeslib.as_array(dp)[:k].copy())
+
+
+def apply_prior(geom: DeviceGeometry, x: torch.Tensor, lam_r: float, lam_t: float = 0.0,
+                out: torch.Tensor | None = None, accumulate: bool = False):
+    """out (+)= lam_r D^T D x + lam_t D_t^T D_t x."""
+    if out is None:
+        out = torch.empty_like(x)
+    n = geom.nvox * geom.nframes
+    _check(lib().tomo_apply_prior(ctypes.byref(geom.g.cube), lam_r, lam_t, _dev_f32(x, n, "x"),
+                                  _dev_f32(out, n, "out"), int(bool(accumulate)), _stream()))
+    return out
+
+
+def cg_solve(geom: DeviceGeometry, y: torch.Tensor, x0: torch.Tensor | None = None, *,
+             lam_r: float = 1e-2, lam_t: float = 0.0, max_iter: int = 50, rtol: float = 0.0,
+             check_every: int = 10, use_graph: bool = False, precond: torch.Tensor | None = None,
+             fallback_window: int = 3, min_drop: float = 1e-6, bp_strategy: int = BP_AUTO,
+             time_kernels: bool = False, out: torch.Tensor | None = None):
+    """Solve M (P^T P + lam_r D^T D + lam_t D_t^T D_t) M x = M P^T y.
+    Returns (x, report dict)."""
+    p = CgParams()
+    lib().tomo_cg_default_params(ctypes.byref(p))
+    p.lambda_r, p.lambda_t, p.max_iter, p.rtol = lam_r, lam_t, int(max_iter), rtol
+    p.check_every, p.use_graph = int(check_every), int(bool(use_graph))
+    p.fallback_window, p.min_drop, p.bp_strategy = int(fallback_window), min_drop, int(bp_strategy)
+    if precond is not None:
+        p.precond = _dev_f32(precond, precond.numel(), "precond")
+    if out is None:
+        out = torch.empty(geom.cube_shape, dtype=torch.float32, device=y.device)
+    if x0 is not None:
+        out.copy_(x0.reshape(out.shape))
+        p.x0_given = 1
+    hist = (c_double * (int(max_iter) + 1))()
+    rep = CgReport()
+    rep.history = hist
+    rep.history_cap = int(max_iter) + 1
+    rep.time_kernels = int(bool(time_kernels))
+    _check(lib().tomo_cg_solve(geom.ref, _dev_f32(y, geom.npix, "y"),
+                               _dev_f32(out, geom.nvox * geom.nframes, "x"), ctypes.byref(p),
+                               ctypes.byref(rep), _stream()))
+    report = {k: getattr(rep, k) for k in ("iters", "status", "fell_back", "n_project",
+                                          "n_backproject", "rel_res", "true_rel_res", "bnorm",
+                                          "ms_project", "ms_backproject")}
+    report["history"] = np.ctypeslib.as_array(hist)[:rep.history_len].copy()
+    return out, report
+
+
+def view_from_wcs(dsun, hgln_deg, hglt_deg, crval1_as, crval2_as, crota_deg, cdelt1_as,
+                  cdelt2_as, crpix1, crpix2, ncol, nrow):
+    """View row (16 numbers) and (ncol, nrow) from helioprojective TAN WCS keywords."""
+    tv = TomoView()
+    _check(lib().tomo_view_from_wcs(dsun, hgln_deg, hglt_deg, crval1_as, crval2_as, crota_deg,
+                                    cdelt1_as, cdelt2_as, crpix1, crpix2, ncol, nrow,
+                                    ctypes.byref(tv)))
+    row = np.array(list(tv.obs) + list(tv.w) + list(tv.u) + list(tv.v) + list(tv.cdelt)
+                   + list(tv.crpix))
+    return row, np.array([tv.ncol, tv.nrow], dtype=np.int32)
+
+
+def validate(geom: DeviceGeometry) -> int:
+    """Status code of the library's geometry check (no GPU work)."""
+    return int(lib().tomo_validate_geometry(geom.ref))
+
+
+def status_string(status: int) -> str:
+    return lib().tomo_status_string(int(status)).decode()

@@ -1,0 +1,193 @@
+"""GPU parity of P and P^T (through the C ABI) against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import tomo_synth as ts
+from _gpu_common import (assert_p_close, flat_index, need_gpu, oracle_pixels, sample_pixels,
+                         to_dev, to_host)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def tomo():
+    return need_gpu()
+
+
+def _parity_full(tomo, ora, g, x, y):
+    dg = tomo.DeviceGeometry(g)
+    img = to_host(tomo.project(dg, to_dev(x)))
+    xm = x if g.map_mask is None else x * (g.map_mask if g.nframes == 1 else g.map_mask[None])
+    assert_p_close(img, ora.project(g, x), ora.project(g, np.abs(xm)))
+    bp = to_host(tomo.backproject(dg, to_dev(y)))
+    assert_p_close(bp, ora.backproject(g, y), ora.backproject(g, np.abs(y)), rtol=1e-4, what="P^T")
+
+
+def test_tiny_projection_and_transpose(tomo, ora):
+    wl = ts.tiny()
+    y = np.random.default_rng(1).normal(size=wl.geom.nrays)
+    _parity_full(tomo, ora, wl.geom, wl.x, y)
+
+
+def test_masks(tomo, ora):
+    wl = ts.tiny()
+    g = wl.geom
+    rng = np.random.default_rng(7)
+    dm = (rng.uniform(size=g.nrays) > 0.3).astype(np.uint8)
+    mm = (rng.uniform(size=g.cube_shape()) > 0.2).astype(np.uint8)
+    gm = ts.Geometry(g.n, g.lo, g.hi, g.views, g.npix, data_mask=dm, map_mask=mm)
+    _parity_full(tomo, ora, gm, wl.x, rng.normal(size=g.nrays))
+
+
+def test_frames(tomo, ora):
+    wl = ts.tiny()
+    g = wl.geom
+    vf = (np.arange(g.nviews) % 3).astype(np.int32)
+    gf = ts.Geometry(g.n, g.lo, g.hi, g.views, g.npix, vf, 3)
+    x = np.stack([wl.x * (f + 1) for f in range(3)])
+    _parity_full(tomo, ora, gf, x, np.random.default_rng(2).normal(size=g.nrays))
+
+
+def test_ragged_views_and_box(tomo, ora):
+    """Non-cubic grid in an off-centre box, views whose sizes leave partial
+    16x16 tiles, a one-pixel view, and an observer inside the box."""
+    n, lo, hi = (20, 13, 9), np.array([-1.3, -0.6, -0.9]), np.array([1.7, 1.1, 0.45])
+    rows, pix = [], []
+    for lon, (nc, nr), fov in [(10.0, (37, 23), 3.0), (123.0, (5, 70), 2.5), (250.0, (1, 1), 1.0)]:
+        r, p = ts.pinhole_view(ts.observer(lon, 12.0, 40.0), npix=(nc, nr), fov=fov)
+        rows.append(r)
+        pix.append([nc, nr])
+    r, p = ts.pinhole_view(np.array([0.2, 0.1, -0.1]), target=(1.0, 0.3, 0.2), npix=(24, 24), fov=8.0)
+    rows.append(r)
+    pix.append([24, 24])
+    g = ts.Geometry(n, lo, hi, np.array(rows), np.array(pix, dtype=np.int32))
+    x = np.random.default_rng(3).uniform(size=g.cube_shape())
+    _parity_full(tomo, ora, g, x, np.random.default_rng(4).normal(size=g.nrays))
+
+
+def test_euvi_two_views_full(tomo, ora):
+    """EUVI-like 128^3 cube with the unit sphere masked, two of the 28 views at
+    512x512: every pixel and every voxel compared."""
+    wl = ts.euvi()
+    g = wl.geom.subset([0, 13])
+    y = np.random.default_rng(5).normal(size=g.nrays)
+    _parity_full(tomo, ora, g, wl.x, y)
+
+
+def test_euvi_full_size_sampled(tomo, ora):
+    """All 28 views at 512x512 in one launch (the benchmark's configuration):
+    P compared on 4000 sampled pixels, P^T on an image that is non-zero on
+    300 sampled pixels only (so the oracle needs only those rays)."""
+    wl = ts.euvi()
+    g = wl.geom
+    dg = tomo.DeviceGeometry(g)
+    img = to_host(tomo.project(dg, to_dev(wl.x)))
+    pix = sample_pixels(g, 4000, 11)
+    val, absv = oracle_pixels(ora, g, wl.x, pix)
+    got = np.array([img[flat_index(g, *p)] for p in pix])
+    assert_p_close(got, val, absv)
+    sel = sample_pixels(g, 300, 12)
+    y = np.zeros(g.nrays)
+    rng = np.random.default_rng(13)
+    for p in sel:
+        y[flat_index(g, *p)] = rng.normal()
+    bp = to_host(tomo.backproject(dg, to_dev(y)))
+    # oracle P^T from the selected rays only
+    ref = np.zeros(g.nvox)
+    refa = np.zeros(g.nvox)
+    for p in sel:
+        yv = y[flat_index(g, *p)]
+        d = ora.pixel_direction(g.views[p[0]], g.npix[p[0]], p[1], p[2])
+        idx, ln, _ = ora.trace_ray(g.n, g.lo, g.hi, g.views[p[0]][0:3], d)
+        keep = g.map_mask.reshape(-1)[idx] == 1
+        np.add.at(ref, idx[keep], ln[keep] * yv)
+        np.add.at(refa, idx[keep], ln[keep] * abs(yv))
+    assert_p_close(bp, ref, refa, rtol=1e-4, what="P^T")
+
+
+def _dyadic_geometry():
+    """Box [-1, 1]^3, N = 16; an observer looking along +x with axis-aligned
+    detector vectors and cdelt 1/64, so pixel offsets of 0, +-1, +-2, +-4, +-8
+    from crpix give directions whose components are powers of two."""
+    row = np.concatenate([[-3.0, 0.25, -0.375], [1, 0, 0], [0, 1, 0], [0, 0, 1],
+                          [1 / 64, 1 / 64], [8.0, 8.0]])
+    row2 = np.concatenate([[0.125, -2.5, 0.0625], [0, 1, 0], [0, 0, 1], [1, 0, 0],
+                           [1 / 16, 1 / 32], [8.0, 8.0]])
+    views = np.array([row, row2])
+    return ts.Geometry((16, 16, 16), np.full(3, -1.0), np.full(3, 1.0), views,
+                       np.array([[17, 17], [17, 17]], dtype=np.int32))
+
+
+def test_trace_dyadic_bit_exact(tomo, ora):
+    """On dyadic rays every crossing is exact on both sides: voxel index
+    sequences and parametric segment lengths agree bit for bit, and lengths
+    to the last bit of |d|."""
+    g = _dyadic_geometry()
+    dg = tomo.DeviceGeometry(g)
+    offs = [0, 1, -1, 2, -2, 4, -4, 8, -8]
+    checked = 0
+    for v in range(2):
+        for dc in offs:
+            for dr in offs:
+                col, row = 8 + dc, 8 + dr
+                gi, gl, gp = tomo.trace_ray(dg, v, col, row)
+                d = ora.pixel_direction(g.views[v], g.npix[v], col, row)
+                oi, ol, ot = ora.trace_ray(g.n, g.lo, g.hi, g.views[v][0:3], d)
+                assert gi.tolist() == oi.tolist(), (v, col, row)
+                if len(ot) > 1:  # parametric lengths between interior boundaries
+                    assert np.array_equal(gp[:-1], np.diff(ot)), (v, col, row)
+                np.testing.assert_allclose(gl, ol, rtol=4e-16, atol=0)
+                checked += len(gi)
+    assert checked > 500
+
+
+def test_trace_generic_rays(tomo, ora):
+    """Generic rays of the tiny geometry.  Its 45-degree views make x and y
+    crossings coincide to within an ulp (cos 45 and sin 45 differ in the last
+    bit), and the two sides may order such a near-tie differently with a
+    segment of ~1e-16 in between: after dropping segments shorter than 1e-12
+    of the box, the voxel sequences must agree exactly, and the length inside
+    every voxel to 1e-12."""
+    wl = ts.tiny()
+    g = wl.geom
+    dg = tomo.DeviceGeometry(g)
+    tiny = 1e-12 * 3.0
+    for v, col, row in sample_pixels(g, 300, 3):
+        gi, gl, _ = tomo.trace_ray(dg, v, col, row)
+        d = ora.pixel_direction(g.views[v], g.npix[v], col, row)
+        oi, ol, _ = ora.trace_ray(g.n, g.lo, g.hi, g.views[v][0:3], d)
+        assert gi[gl > tiny].tolist() == oi[ol > tiny].tolist(), (v, col, row)
+        rg, ro = np.zeros(g.nvox), np.zeros(g.nvox)
+        np.add.at(rg, gi, gl)
+        np.add.at(ro, oi, ol)
+        np.testing.assert_allclose(rg, ro, rtol=0, atol=1e-12)
+
+
+def test_crossing_counts(tomo, ora):
+    wl = ts.tiny()
+    dg = tomo.DeviceGeometry(wl.geom)
+    assert tomo.count_crossings(dg) == ora.count_crossings(wl.geom)
+    g2 = ts.euvi().geom.subset([0, 5])
+    c_gpu = tomo.count_crossings(tomo.DeviceGeometry(g2))
+    c_ora = ora.count_crossings(g2)
+    # near-ties (crossings closer than ~1e-15 of the chord) may merge on one side
+    assert abs(c_gpu - c_ora) <= 1e-8 * c_ora + 2
+
+
+def test_adjoint_identity(tomo):
+    """<P x, y> = <x, P^T y> for 100 random pairs (FP32 data, FP64 sums)."""
+    import torch
+
+    wl = ts.tiny()
+    dg = tomo.DeviceGeometry(wl.geom)
+    worst = 0.0
+    for seed in range(500, 600):
+        x, y = ts.random_pair(wl.geom.nvox, wl.geom.nrays, seed)
+        xd, yd = to_dev(x), to_dev(y)
+        px = tomo.project(dg, xd).double()
+        pty = tomo.backproject(dg, yd).double()
+        lhs = float(torch.dot(px, yd.double()))
+        rhs = float(torch.dot(xd.double().ravel(), pty.ravel()))
+        scale = float(torch.linalg.norm(px)) * float(np.linalg.norm(y))
+        worst = max(worst, abs(lhs - rhs) / scale)
+    assert worst <= 1e-5
