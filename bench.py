@@ -36,27 +36,31 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-views", type=int, default=2, help="views in the oracle's timed sample")
+    ap.add_argument("--cpu-reps", type=int, default=6,
+                    help="full P + P^T passes of the oracle in its timed sample")
+    ap.add_argument("--bp", choices=["auto", "binned", "atomic"], default="auto",
+                    help="back-projection strategy")
     return ap.parse_args()
 
 
-def cpu_baseline(wl, nviews):
-    """The FP64 oracle (as it stands) on a bounded sample: P and P^T over the
-    first `nviews` views of the same geometry, all host cores."""
+def cpu_baseline(wl, reps):
+    """The FP64 oracle (as it stands) on a bounded sample: `reps` passes of
+    P and P^T over the full geometry (the CG's operator pair), all host
+    cores."""
     import oracle as ora
 
-    g = wl.geom.subset(list(range(nviews)))
+    g = wl.geom
     cross = ora.count_crossings(g)
     y = np.random.default_rng(0).normal(size=g.nrays)
-    ora.project(g, wl.x)  # warm the page cache / thread pool
     t0 = time.perf_counter()
-    ora.project(g, wl.x)
-    ora.backproject(g, y)
+    for _ in range(reps):
+        ora.project(g, wl.x)
+        ora.backproject(g, y)
     dt = time.perf_counter() - t0
-    return {"value": 2.0 * cross / dt, "unit": "voxel-crossings/s", "cores": ora.max_threads(),
-            "kind": "oracle",
-            "sample": f"P + P^T over {nviews} of the 28 views (512x512) of the 128^3 EUVI-like cube "
-                      f"({cross} crossings each), {dt:.1f} s"}
+    return {"value": 2.0 * reps * cross / dt, "unit": "voxel-crossings/s",
+            "cores": ora.max_threads(), "kind": "oracle",
+            "sample": f"{reps} x (P + P^T) over all 28 views of 512x512 and the 128^3 EUVI-like "
+                      f"cube ({cross} crossings per application), {dt:.1f} s"}
 
 
 def main():
@@ -82,8 +86,11 @@ def main():
     crossings = tomo.count_crossings(dg)
     x = torch.empty(dg.cube_shape, dtype=torch.float32, device="cuda")
 
+    bp = {"auto": tomo.BP_AUTO, "binned": tomo.BP_BINNED, "atomic": tomo.BP_ATOMIC}[args.bp]
+
     def step():
-        return tomo.cg_solve(dg, y, lam_r=wl.lam_r, max_iter=wl.cg_iters, time_kernels=True, out=x)
+        return tomo.cg_solve(dg, y, lam_r=wl.lam_r, max_iter=wl.cg_iters, time_kernels=True, out=x,
+                             bp_strategy=bp)
 
     for _ in range(args.warmup):
         step()
@@ -106,7 +113,8 @@ def main():
     bytes_p = 4.0 * crossings + 4.0 * nrays
     bytes_bp = 8.0 * crossings + 4.0 * nrays
     if ms_bp >= ms_p:
-        dom, ms_dom, b_dom = "k_backproject_atomic", ms_bp, bytes_bp
+        dom = "k_backproject_atomic" if args.bp == "atomic" else "k_backproject_binned"
+        ms_dom, b_dom = ms_bp, bytes_bp
     else:
         dom, ms_dom, b_dom = "k_project", ms_p, bytes_p
     achieved = b_dom / (ms_dom * 1e-3) / 1e9
@@ -128,7 +136,7 @@ def main():
                                "iterations, lambda 1e-2",
                    "crossings_per_application": crossings, "applications_per_step": apps,
                    "rays": nrays, "storage": "f32", "walk": "f64",
-                   "final_rel_res": reps[-1]["rel_res"]},
+                   "final_rel_res": reps[-1]["rel_res"], "backprojection": args.bp},
         "kernels": {"k_project_ms": ms_p, "k_backproject_ms": ms_bp,
                     "project_crossings_per_s": crossings / (ms_p * 1e-3),
                     "backproject_crossings_per_s": crossings / (ms_bp * 1e-3)},
@@ -136,7 +144,7 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_views)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_reps)
     print(json.dumps(out), flush=True)
 
 

@@ -150,6 +150,41 @@ int tomo_trace_ray(const tomo_geometry *g, int32_t view, int32_t col,
                    int32_t cap, int32_t *n_out);
 
 /*
+ * Launch tuning, process-wide (read by every later launch).  The defaults
+ * suit MI355X; tomo_autotune() (or a caller) may change them.
+ *   p_bundle, bp_bundle: shape of the pixel bundle one 64-lane wavefront
+ *     walks inside a 16x16 workgroup tile: 2 = 4x16, 3 = 8x8, 4 = 16x4 pixels,
+ *     0 = the 64 lanes interleaved at a 2-pixel pitch over the whole tile.
+ *   p_xcd_remap, bp_xcd_remap: 1 = give each XCD a contiguous run of tiles.
+ *   bp_lds_bins: 64-bit LDS bins per workgroup of the binned
+ *     back-projection (512..8192, i.e. 4..64 KiB; larger boxes mean fewer
+ *     flushes but fewer resident workgroups).
+ *   bp_default: strategy used for TOMO_BP_AUTO (TOMO_BP_BINNED or
+ *     TOMO_BP_ATOMIC).
+ * tomo_set_tuning returns TOMO_EINVAL (and changes nothing) for values out
+ * of range.  Not synchronised with launches in flight on other threads.
+ */
+typedef struct tomo_tuning {
+    int32_t p_bundle;
+    int32_t p_xcd_remap;
+    int32_t bp_bundle;
+    int32_t bp_xcd_remap;
+    int32_t bp_lds_bins;
+    int32_t bp_default;
+} tomo_tuning;
+
+int tomo_get_tuning(tomo_tuning *out);
+int tomo_set_tuning(const tomo_tuning *in);
+
+/*
+ * Diagnostic export: number of binned back-projection writes that fell
+ * outside their workgroup's LDS box since the last call (each one is a lost
+ * contribution, so anything but 0 is a library bug).  Synchronises the
+ * device and resets the counter; *count_h is host memory.
+ */
+int tomo_binning_spills(const tomo_geometry *g, int64_t *count_h);
+
+/*
  * Prior term (Sec. "Single Spacecraft Static Tomography"; Eq. stsrt):
  *   out = [out if accumulate] + lambda_r D^T D x + lambda_t D_t^T D_t x
  * with D the forward differences between in-cube neighbours along x, y and
@@ -208,7 +243,9 @@ typedef struct tomo_cg_report {
  * Eq. stsrt,  A x = b  with  A = M (P^T P + lambda_r D^T D + lambda_t D_t^T
  * D_t) M  and  b = M P^T y  (the map mask M restricts the unknowns).
  * Textbook CG (FP32 vectors, FP64 dot products and scalars, kept on the
- * device); with a preconditioner network, flexible CG with z = ||r|| N(r/||r||)
+ * device).  Non-finite values in y (unmasked pixels) are reported as
+ * status TOMO_ENONFINITE without iterating.  With a preconditioner network,
+ * flexible CG with z = ||r|| N(r/||r||)
  * and the Polak-Ribiere beta, falling back to plain CG after
  * fallback_window non-decreasing iterations or when z.r <= 0.
  *   y_d: DEVICE float [total pixels]

@@ -17,6 +17,16 @@ namespace tomo {
 
 static thread_local std::string g_last_error;
 
+// Process-wide launch tuning (see tomo_set_tuning).
+static std::mutex g_tuning_mu;
+static tomo_tuning g_tuning = {2, 1, 3, 1, 4096, TOMO_BP_BINNED};
+
+tomo_tuning current_tuning()
+{
+    std::lock_guard<std::mutex> lock(g_tuning_mu);
+    return g_tuning;
+}
+
 int set_error(int status, const char *fmt, ...)
 {
     char buf[512];
@@ -164,11 +174,11 @@ static int build_plan(const tomo_geometry *g, int64_t npix, Plan &p)
     hipError_t e = hipMalloc((void **)&p.views_d, sizeof(ViewDev) * hv.size());
     if (e != hipSuccess) return set_error(TOMO_ENOMEM, "view table allocation: %s", hipGetErrorString(e));
     e = hipMemcpy(p.views_d, hv.data(), sizeof(ViewDev) * hv.size(), hipMemcpyHostToDevice);
-    if (e != hipSuccess) {
-        hipFree(p.views_d);
-        p.views_d = nullptr;
-        return hip_fail(e, "view table upload");
-    }
+    if (e != hipSuccess) return hip_fail(e, "view table upload");
+    e = hipMalloc((void **)&p.spill_d, sizeof(unsigned));
+    if (e != hipSuccess) return set_error(TOMO_ENOMEM, "counter allocation: %s", hipGetErrorString(e));
+    e = hipMemset(p.spill_d, 0, sizeof(unsigned));
+    if (e != hipSuccess) return hip_fail(e, "counter init");
     return TOMO_OK;
 }
 
@@ -238,6 +248,44 @@ const char *tomo_status_string(int status)
 }
 
 const char *tomo_last_error(void) { return g_last_error.c_str(); }
+
+int tomo_get_tuning(tomo_tuning *out)
+{
+    if (!out) return set_error(TOMO_EINVAL, "tomo_get_tuning: out is NULL");
+    *out = current_tuning();
+    return TOMO_OK;
+}
+
+int tomo_set_tuning(const tomo_tuning *in)
+{
+    if (!in) return set_error(TOMO_EINVAL, "tomo_set_tuning: in is NULL");
+    auto bundle_ok = [](int b) { return b == 0 || b == 2 || b == 3 || b == 4; };
+    if (!bundle_ok(in->p_bundle) || !bundle_ok(in->bp_bundle))
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: bundle must be 0, 2, 3 or 4");
+    if ((in->p_xcd_remap != 0 && in->p_xcd_remap != 1) || (in->bp_xcd_remap != 0 && in->bp_xcd_remap != 1))
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: xcd_remap must be 0 or 1");
+    if (in->bp_lds_bins < 512 || in->bp_lds_bins > 8192)
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_lds_bins must be in [512, 8192]");
+    if (in->bp_default != TOMO_BP_BINNED && in->bp_default != TOMO_BP_ATOMIC)
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_default must be BINNED or ATOMIC");
+    std::lock_guard<std::mutex> lock(g_tuning_mu);
+    g_tuning = *in;
+    return TOMO_OK;
+}
+
+int tomo_binning_spills(const tomo_geometry *g, int64_t *count_h)
+{
+    if (!count_h) return set_error(TOMO_EINVAL, "tomo_binning_spills: count_h is NULL");
+    int st = TOMO_OK;
+    PlanRef p = get_plan(g, &st);
+    if (!p) return st;
+    unsigned h = 0;
+    int rc = hip_fail(hipDeviceSynchronize(), "synchronise");
+    if (!rc) rc = hip_fail(hipMemcpy(&h, p->spill_d, sizeof(h), hipMemcpyDeviceToHost), "copy counter");
+    if (!rc) rc = hip_fail(hipMemset(p->spill_d, 0, sizeof(unsigned)), "reset counter");
+    if (!rc) *count_h = (int64_t)h;
+    return rc;
+}
 
 int tomo_project(const tomo_geometry *g, const float *cube_d, float *images_d, tomo_stream stream)
 {

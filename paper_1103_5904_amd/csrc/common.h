@@ -41,9 +41,10 @@ struct GridDev {
 
 // Wave-level ray bundle inside a 16x16 tile: each 64-lane wavefront takes a
 // bw x bh block of pixels (bw * bh == 64), and the four wavefronts tile the
-// 16x16 workgroup tile.
+// 16x16 workgroup tile; or (log2_bw == 0) each wavefront takes every other
+// pixel of the tile in both directions, offset by its index.
 struct Bundle {
-    int32_t log2_bw;    // 3 -> 8x8, 4 -> 16x4, 2 -> 4x16
+    int32_t log2_bw;    // 3 -> 8x8, 4 -> 16x4, 2 -> 4x16, 0 -> interleaved
     int32_t xcd_remap;  // 1: give each XCD a contiguous range of tiles
 };
 
@@ -64,6 +65,10 @@ __device__ inline uint32_t buf_load_u8(__amdgpu_buffer_rsrc_t r, uint32_t byte_o
 {
     return (uint32_t)__builtin_amdgcn_raw_buffer_load_b8(r, (int)byte_off, 0, 0);
 }
+
+// "v is not +-0", decided on the bit pattern: true for NaN even in code
+// built without NaN semantics, so NaN data keeps propagating.
+__device__ inline bool nonzero_bits(float v) { return (__builtin_bit_cast(uint32_t, v) << 1) != 0u; }
 
 __device__ inline void buf_atomic_add_f32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, float v)
 {
@@ -117,10 +122,15 @@ struct Plan {
     int64_t ntiles = 0;          // 16x16 tiles over all views
     int64_t npix = 0;            // total pixels
     int32_t max_steps = 0;       // bound on segments per ray
+    unsigned *spill_d = nullptr; // device counter: binned writes that missed their LDS box
     Plan() = default;
     Plan(const Plan &) = delete;
     Plan &operator=(const Plan &) = delete;
-    ~Plan() { if (views_d) (void)hipFree(views_d); }
+    ~Plan()
+    {
+        if (views_d) (void)hipFree(views_d);
+        if (spill_d) (void)hipFree(spill_d);
+    }
 };
 
 using PlanRef = std::shared_ptr<const Plan>;
@@ -133,6 +143,7 @@ PlanRef get_plan(const tomo_geometry *g, int *status);
 int set_error(int status, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int validate_cube(const tomo_cube *c);
+tomo_tuning current_tuning();
 
 // Launchers (siddon.hip)
 int launch_project(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
@@ -143,5 +154,7 @@ int launch_backproject(const Plan &p, const tomo_geometry *g, const float *image
 int launch_project_flagged(const Plan &p, const tomo_geometry *g, const float *cube,
                            float *images, hipStream_t s, const int *done_flag);
 int launch_fill(float *x, int64_t n, float v, hipStream_t s);
+int launch_backproject_binned(const Plan &p, const tomo_geometry *g, const float *images,
+                              float *cube, bool use_map_mask, hipStream_t s, const int *done_flag);
 
 }  // namespace tomo

@@ -30,162 +30,9 @@
 #include <math.h>
 #include <stdio.h>
 
-#include "common.h"
+#include "walk.h"
 
 namespace tomo {
-
-struct RayState {
-    double s[3];   // next crossing on each axis (ray parameter from the entry)
-    double ds[3];  // parameter spacing of consecutive planes on each axis
-    double send;   // exit parameter
-    double dn;     // |d|: converts parameter differences to lengths
-    int32_t off;   // flat offset of the current voxel within its frame
-    int32_t st[3]; // signed flat stride of a step on each axis
-};
-
-__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
-
-// Line of sight through pixel (col, row): gnomonic pinhole d = w + x u + y v.
-// Returns false if the half-line misses the (half-open) box.
-__device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, int row,
-                                 RayState &r)
-{
-    const double x = ((double)col - v.cp[0]) * v.cd[0];
-    const double y = ((double)row - v.cp[1]) * v.cd[1];
-    double d[3];
-#pragma unroll
-    for (int a = 0; a < 3; ++a) d[a] = v.w[a] + x * v.u[a] + y * v.v[a];
-    r.dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-
-    // slab clip of t >= 0 against the box
-    double tin = 0.0, tout = kFar;
-    bool inside = true;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (d[a] != 0.0) {
-            const double t1 = (g.lo[a] - v.o[a]) / d[a];
-            const double t2 = (g.hi[a] - v.o[a]) / d[a];
-            tin = fmax(tin, fmin(t1, t2));
-            tout = fmin(tout, fmax(t1, t2));
-        } else {
-            inside = inside && (g.lo[a] <= v.o[a]) && (v.o[a] < g.hi[a]);
-        }
-    }
-    if (!inside || !(tout > tin)) return false;
-
-    int idx[3];
-    double sf[3], ds[3], jface[3];
-    const int32_t stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        const int N = g.n[a];
-        if (d[a] != 0.0) {
-            // voxel entered first: half-open voxels, so a ray starting on a
-            // plane belongs to the voxel on the side it moves into
-            const double p = (v.o[a] + tin * d[a] - g.lo[a]) / g.delta[a];
-            const bool up = d[a] > 0.0;
-            int i = up ? clampi((int)floor(p), 0, N - 1) : clampi((int)ceil(p) - 1, 0, N - 1);
-            const double k0 = up ? (double)(i + 1) : (double)i;  // first plane ahead
-            sf[a] = (g.lo[a] + k0 * g.delta[a] - v.o[a]) / d[a] - tin;
-            ds[a] = g.delta[a] / fabs(d[a]);
-            jface[a] = up ? (double)N - k0 : k0;  // crossings to reach the far face
-            if (sf[a] <= 0.0) {  // rounding put the entry just before plane k0
-                i = clampi(i + (up ? 1 : -1), 0, N - 1);
-                sf[a] += ds[a];
-                jface[a] -= 1.0;
-            }
-            idx[a] = i;
-            r.st[a] = up ? stride[a] : -stride[a];
-        } else {
-            idx[a] = clampi((int)floor((v.o[a] - g.lo[a]) / g.delta[a]), 0, N - 1);
-            sf[a] = kFar;
-            ds[a] = 0.0;
-            jface[a] = 0.0;
-            r.st[a] = 0;
-        }
-    }
-    // Only values up to ~3 chords are ever compared: an axis whose first
-    // crossing lies beyond 2 chords is never crossed, and a spacing above
-    // 2 chords means at most one crossing, so both are capped.  Then every
-    // value the walk forms is below span = 4 chords, and a power-of-two grid
-    // q with span < 2^51 q makes all the additions exact.
-    const double chord = tout - tin, lim = 2.0 * chord;
-    int ex = 0;
-    (void)frexp(4.0 * chord, &ex);  // 4 chord < 2^ex
-    double send = kFar;
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        if (d[a] != 0.0 && sf[a] <= lim) {
-            ds[a] = ldexp(rint(ldexp(fmin(ds[a], lim), 51 - ex)), ex - 51);
-            sf[a] = ldexp(rint(ldexp(sf[a], 51 - ex)), ex - 51);
-            send = fmin(send, sf[a] + jface[a] * ds[a]);
-        } else {
-            sf[a] = kFar;
-            ds[a] = 0.0;
-        }
-        r.s[a] = sf[a];
-        r.ds[a] = ds[a];
-    }
-    if (!(send > 0.0) || !(send < kFar)) return false;
-    r.send = send;
-    r.off = (idx[2] * g.n[1] + idx[1]) * g.n[0] + idx[0];
-    return true;
-}
-
-// Walk the ray voxel by voxel.  visit(off, dl) receives the flat voxel
-// offset and the parameter length of the segment (length = dl * |d|).
-// Simultaneous crossings advance every tied axis in one step.  maxit bounds
-// the loop whatever the arithmetic does.
-template <class Visit>
-__device__ inline void ray_walk(RayState &r, int maxit, Visit &&visit)
-{
-    double scur = 0.0;
-    for (int it = 0; it < maxit; ++it) {
-        const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
-        visit(r.off, m - scur);
-        if (m >= r.send) break;
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const bool t = (r.s[a] == m);
-            r.s[a] += t ? r.ds[a] : 0.0;  // exact on the common grid
-            r.off += t ? r.st[a] : 0;
-        }
-        scur = m;
-    }
-}
-
-// Tile -> (view, pixel of this lane).  Views are sorted by tile_off.
-struct LanePixel {
-    int view;
-    int col, row;
-};
-
-__device__ inline LanePixel lane_pixel(const ViewDev *__restrict__ views, int nviews, int64_t tile,
-                                       int log2_bw)
-{
-    int lo = 0, hi = nviews - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (views[mid].tile_off <= tile) lo = mid;
-        else hi = mid - 1;
-    }
-    const int64_t t = tile - views[lo].tile_off;
-    const int tpr = views[lo].tiles_x;
-    const int tx = (int)(t % tpr), ty = (int)(t / tpr);
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int bw = 1 << log2_bw, bh = 64 >> log2_bw;
-    const int wpr = kTile >> log2_bw;  // wave bundles per tile row
-    LanePixel lp;
-    lp.view = lo;
-    lp.col = tx * kTile + (w % wpr) * bw + (l & (bw - 1));
-    lp.row = ty * kTile + (w / wpr) * bh + (l >> log2_bw);
-    return lp;
-}
-
-__device__ inline int64_t block_tile(const Bundle &b)
-{
-    return b.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-}
 
 // ------------------------------------------------------------- kernels
 
@@ -235,7 +82,7 @@ __global__ __launch_bounds__(kThreads) void k_backproject_atomic(
     if (lp.col >= v.ncol || lp.row >= v.nrow) return;
     const int64_t pix = v.pix_off + (int64_t)lp.row * v.ncol + lp.col;
     const float yv = images[pix];
-    if (yv == 0.0f) return;
+    if (!nonzero_bits(yv)) return;
     if (kDataMask && !data_mask[pix]) return;
     RayState r;
     if (!ray_setup(g, v, lp.col, lp.row, r)) return;
@@ -306,7 +153,11 @@ __global__ __launch_bounds__(kThreads) void k_fill(float *__restrict__ x, int64_
 
 // ------------------------------------------------------------ launchers
 
-static Bundle default_bundle() { return Bundle{3, 1}; }
+static Bundle p_bundle()
+{
+    const tomo_tuning t = current_tuning();
+    return Bundle{t.p_bundle, t.p_xcd_remap};
+}
 
 static int64_t grid_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
 
@@ -323,7 +174,7 @@ static int launch_project_impl(const Plan &p, const tomo_geometry *g, const floa
                                float *images, bool use_map_mask, hipStream_t s,
                                const int *done_flag)
 {
-    const Bundle b = default_bundle();
+    const Bundle b = p_bundle();
     const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;
     const dim3 grid((unsigned)p.ntiles), blk(kThreads);
 #define TOMO_LAUNCH_P(M, D)                                                                         \
@@ -353,12 +204,14 @@ int launch_backproject(const Plan &p, const tomo_geometry *g, const float *image
                        bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
                        const int *done_flag)
 {
-    (void)strategy;  // only the atomic strategy exists so far
     if (!accumulate) {
         int rc = launch_fill(cube, p.grid.nvox * p.grid.nframes, 0.0f, s);
         if (rc) return rc;
     }
-    const Bundle b = default_bundle();
+    const tomo_tuning tu = current_tuning();
+    if (strategy == TOMO_BP_BINNED || (strategy == TOMO_BP_AUTO && tu.bp_default == TOMO_BP_BINNED))
+        return launch_backproject_binned(p, g, images, cube, use_map_mask, s, done_flag);
+    const Bundle b{tu.bp_bundle, tu.bp_xcd_remap};
     const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;
     const dim3 grid((unsigned)p.ntiles), blk(kThreads);
 #define TOMO_LAUNCH_BP(M, D)                                                                        \
@@ -387,7 +240,7 @@ extern "C" int tomo_count_crossings(const tomo_geometry *g, int64_t *total_h, to
     if (hipMallocAsync((void **)&d, sizeof(*d), s) != hipSuccess)
         return set_error(TOMO_ENOMEM, "tomo_count_crossings: device allocation failed");
     (void)hipMemsetAsync(d, 0, sizeof(*d), s);
-    const Bundle b = default_bundle();
+    const Bundle b = p_bundle();
     if (g->data_mask)
         hipLaunchKernelGGL((k_count<true>), dim3((unsigned)p->ntiles), dim3(kThreads), 0, s, p->grid,
                            p->views_d, p->nviews, b, p->max_steps, g->data_mask, d);

@@ -12,6 +12,7 @@
 // synchronises only between chunks.  The vector updates are fused into
 // three streaming passes per iteration around one P and one P^T.
 #include <math.h>
+#include <stddef.h>
 #include <string.h>
 
 #include <vector>
@@ -248,6 +249,19 @@ __global__ __launch_bounds__(kThreads) void k_true_res(const float *__restrict__
     if (grid_reduce2(rr, 0.0, ws, t, unused) && threadIdx.x == 0) ws.st->aux = t;
 }
 
+// aux = number of non-finite values among the unmasked pixels of y.
+__global__ __launch_bounds__(kThreads) void k_count_nonfinite(const float *__restrict__ y, int64_t n,
+                                                              const uint8_t *__restrict__ data_mask,
+                                                              Workspace ws)
+{
+    double bad_count = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        if ((!data_mask || data_mask[i]) && !isfinite(y[i])) bad_count += 1.0;
+    double t, unused;
+    if (grid_reduce2(bad_count, 0.0, ws, t, unused) && threadIdx.x == 0) ws.st->aux = t;
+}
+
 // x = M x (masked start point).
 __global__ __launch_bounds__(kThreads) void k_mask(float *__restrict__ x,
                                                    const uint8_t *__restrict__ map_mask, Dims d)
@@ -392,6 +406,26 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     const bool timed = rep->time_kernels != 0;
     EventPool evp;
     std::vector<hipEvent_t> evP, evB;  // start/stop pairs
+
+    // non-finite data: report, do not iterate
+    hipLaunchKernelGGL(k_count_nonfinite, dim3(elem_blocks(plan->npix)), dim3(kThreads), 0, s, y_d,
+                       plan->npix, g->data_mask, ws);
+    rc = hip_fail(hipMemcpyAsync(hst, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s), "state copy");
+    if (!rc) rc = hip_fail(hipStreamSynchronize(s), "cg synchronise");
+    if (rc) return rc;
+    if (hst->aux > 0.0) {
+        if (!prm->x0_given) {
+            rc = launch_fill(x_d, n, 0.0f, s);
+            if (!rc) rc = hip_fail(hipStreamSynchronize(s), "cg synchronise");
+            if (rc) return rc;
+        }
+        memset(rep, 0, offsetof(tomo_cg_report, history));
+        rep->status = TOMO_ENONFINITE;
+        rep->fell_back = -1;
+        rep->rel_res = rep->true_rel_res = NAN;
+        rep->history_len = 0;
+        return TOMO_OK;
+    }
 
     // b = M P^T y
     rc = launch_backproject(*plan, g, y_d, b, false, true, prm->bp_strategy, s);

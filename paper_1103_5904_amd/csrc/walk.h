@@ -1,0 +1,186 @@
+// Device-side ray set-up and Siddon walk shared by every projector kernel
+// (P, the two P^T strategies, the crossing counter and the trace export), so
+// that all of them produce bit-identical segments.  See siddon.hip for the
+// design notes.
+#pragma once
+
+#include <math.h>
+
+#include "common.h"
+
+namespace tomo {
+
+struct RayState {
+    double s[3];   // next crossing on each axis (ray parameter from the entry)
+    double ds[3];  // parameter spacing of consecutive planes on each axis
+    double send;   // exit parameter
+    double dn;     // |d|: converts parameter differences to lengths
+    int32_t off;   // flat offset of the current voxel within its frame
+    int32_t st[3]; // signed flat stride of a step on each axis
+};
+
+__device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
+
+// Line of sight through pixel (col, row): gnomonic pinhole d = w + x u + y v.
+// Returns false if the half-line misses the (half-open) box.
+// Per-axis entry state, for kernels that need voxel coordinates.
+struct RayAxes {
+    int idx[3];  // entry voxel index on each axis
+    int k0[3];   // index of the first plane crossed on each axis (after the entry)
+    double tin;  // ray parameter of the entry point
+};
+
+__device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, int row,
+                                 RayState &r, RayAxes *ax = nullptr)
+{
+    const double x = ((double)col - v.cp[0]) * v.cd[0];
+    const double y = ((double)row - v.cp[1]) * v.cd[1];
+    double d[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) d[a] = v.w[a] + x * v.u[a] + y * v.v[a];
+    r.dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+
+    // slab clip of t >= 0 against the box
+    double tin = 0.0, tout = kFar;
+    bool inside = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] != 0.0) {
+            const double t1 = (g.lo[a] - v.o[a]) / d[a];
+            const double t2 = (g.hi[a] - v.o[a]) / d[a];
+            tin = fmax(tin, fmin(t1, t2));
+            tout = fmin(tout, fmax(t1, t2));
+        } else {
+            inside = inside && (g.lo[a] <= v.o[a]) && (v.o[a] < g.hi[a]);
+        }
+    }
+    if (!inside || !(tout > tin)) return false;
+
+    int idx[3];
+    double sf[3], ds[3], jface[3];
+    const int32_t stride[3] = {1, g.n[0], g.n[0] * g.n[1]};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int N = g.n[a];
+        if (d[a] != 0.0) {
+            // voxel entered first: half-open voxels, so a ray starting on a
+            // plane belongs to the voxel on the side it moves into
+            const double p = (v.o[a] + tin * d[a] - g.lo[a]) / g.delta[a];
+            const bool up = d[a] > 0.0;
+            int i = up ? clampi((int)floor(p), 0, N - 1) : clampi((int)ceil(p) - 1, 0, N - 1);
+            const double k0 = up ? (double)(i + 1) : (double)i;  // first plane ahead
+            sf[a] = (g.lo[a] + k0 * g.delta[a] - v.o[a]) / d[a] - tin;
+            ds[a] = g.delta[a] / fabs(d[a]);
+            jface[a] = up ? (double)N - k0 : k0;  // crossings to reach the far face
+            int kplane = (int)k0;
+            if (sf[a] <= 0.0) {  // rounding put the entry just before plane k0
+                i = clampi(i + (up ? 1 : -1), 0, N - 1);
+                sf[a] += ds[a];
+                jface[a] -= 1.0;
+                kplane += up ? 1 : -1;
+            }
+            idx[a] = i;
+            if (ax) ax->k0[a] = kplane;
+            r.st[a] = up ? stride[a] : -stride[a];
+        } else {
+            idx[a] = clampi((int)floor((v.o[a] - g.lo[a]) / g.delta[a]), 0, N - 1);
+            if (ax) ax->k0[a] = 0;
+            sf[a] = kFar;
+            ds[a] = 0.0;
+            jface[a] = 0.0;
+            r.st[a] = 0;
+        }
+    }
+    // Only values up to ~3 chords are ever compared: an axis whose first
+    // crossing lies beyond 2 chords is never crossed, and a spacing above
+    // 2 chords means at most one crossing, so both are capped.  Then every
+    // value the walk forms is below span = 4 chords, and a power-of-two grid
+    // q with span < 2^51 q makes all the additions exact.
+    const double chord = tout - tin, lim = 2.0 * chord;
+    int ex = 0;
+    (void)frexp(4.0 * chord, &ex);  // 4 chord < 2^ex
+    double send = kFar;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] != 0.0 && sf[a] <= lim) {
+            ds[a] = ldexp(rint(ldexp(fmin(ds[a], lim), 51 - ex)), ex - 51);
+            sf[a] = ldexp(rint(ldexp(sf[a], 51 - ex)), ex - 51);
+            send = fmin(send, sf[a] + jface[a] * ds[a]);
+        } else {
+            sf[a] = kFar;
+            ds[a] = 0.0;
+        }
+        r.s[a] = sf[a];
+        r.ds[a] = ds[a];
+    }
+    if (!(send > 0.0) || !(send < kFar)) return false;
+    r.send = send;
+    r.off = (idx[2] * g.n[1] + idx[1]) * g.n[0] + idx[0];
+    if (ax) {
+        for (int a = 0; a < 3; ++a) ax->idx[a] = idx[a];
+        ax->tin = tin;
+    }
+    return true;
+}
+
+// Walk the ray voxel by voxel.  visit(off, dl) receives the flat voxel
+// offset and the parameter length of the segment (length = dl * |d|).
+// Simultaneous crossings advance every tied axis in one step.  maxit bounds
+// the loop whatever the arithmetic does.
+template <class Visit>
+__device__ inline void ray_walk(RayState &r, int maxit, Visit &&visit)
+{
+    double scur = 0.0;
+    for (int it = 0; it < maxit; ++it) {
+        const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
+        visit(r.off, m - scur);
+        if (m >= r.send) break;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const bool t = (r.s[a] == m);
+            r.s[a] += t ? r.ds[a] : 0.0;  // exact on the common grid
+            r.off += t ? r.st[a] : 0;
+        }
+        scur = m;
+    }
+}
+
+// Tile -> (view, pixel of this lane).  Views are sorted by tile_off.
+struct LanePixel {
+    int view;
+    int col, row;
+};
+
+__device__ inline LanePixel lane_pixel(const ViewDev *__restrict__ views, int nviews, int64_t tile,
+                                       int log2_bw)
+{
+    int lo = 0, hi = nviews - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (views[mid].tile_off <= tile) lo = mid;
+        else hi = mid - 1;
+    }
+    const int64_t t = tile - views[lo].tile_off;
+    const int tpr = views[lo].tiles_x;
+    const int tx = (int)(t % tpr), ty = (int)(t / tpr);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    LanePixel lp;
+    lp.view = lo;
+    if (log2_bw == 0) {  // 8x8 lanes at a 2-pixel pitch, wavefront w offset by (w&1, w>>1)
+        lp.col = tx * kTile + (l & 7) * 2 + (w & 1);
+        lp.row = ty * kTile + (l >> 3) * 2 + (w >> 1);
+        return lp;
+    }
+    const int bw = 1 << log2_bw, bh = 64 >> log2_bw;
+    const int wpr = kTile >> log2_bw;  // wave bundles per tile row
+    lp.col = tx * kTile + (w % wpr) * bw + (l & (bw - 1));
+    lp.row = ty * kTile + (w / wpr) * bh + (l >> log2_bw);
+    return lp;
+}
+
+__device__ inline int64_t block_tile(const Bundle &b)
+{
+    return b.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+}
+
+}  // namespace tomo

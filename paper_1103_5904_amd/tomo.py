@@ -49,6 +49,11 @@ class TomoGeometry(ctypes.Structure):
                 ("views", POINTER(TomoView)), ("data_mask", c_void_p), ("map_mask", c_void_p)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("p_bundle", c_int32), ("p_xcd_remap", c_int32), ("bp_bundle", c_int32),
+                ("bp_xcd_remap", c_int32), ("bp_lds_bins", c_int32), ("bp_default", c_int32)]
+
+
 class CgParams(ctypes.Structure):
     _fields_ = [("lambda_r", c_double), ("lambda_t", c_double), ("max_iter", c_int32),
                 ("x0_given", c_int32), ("rtol", c_double), ("check_every", c_int32),
@@ -69,7 +74,8 @@ EXPORTS = [
     "tomo_project", "tomo_backproject", "tomo_backproject_ex", "tomo_count_crossings",
     "tomo_trace_ray", "tomo_apply_prior", "tomo_cg_solve", "tomo_cg_default_params",
     "tomo_view_from_wcs", "tomo_validate_geometry", "tomo_geometry_pixels",
-    "tomo_release_cache", "tomo_status_string", "tomo_last_error",
+    "tomo_release_cache", "tomo_status_string", "tomo_last_error", "tomo_binning_spills",
+    "tomo_get_tuning", "tomo_set_tuning",
 ]
 
 _lib = None
@@ -101,6 +107,9 @@ def lib():
         L.tomo_cg_default_params.argtypes = [POINTER(CgParams)]
         L.tomo_view_from_wcs.argtypes = [c_double] * 10 + [c_int32, c_int32, POINTER(TomoView)]
         L.tomo_validate_geometry.argtypes = [POINTER(TomoGeometry)]
+        L.tomo_binning_spills.argtypes = [POINTER(TomoGeometry), POINTER(c_int64)]
+        L.tomo_get_tuning.argtypes = [POINTER(Tuning)]
+        L.tomo_set_tuning.argtypes = [POINTER(Tuning)]
         L.tomo_geometry_pixels.argtypes = [POINTER(TomoGeometry)]
         _lib = L
     return _lib
@@ -202,6 +211,33 @@ def backproject(geom: DeviceGeometry, images: torch.Tensor, out: torch.Tensor | 
     o = _dev_f32(out, geom.nvox * geom.nframes, "out")
     _check(lib().tomo_backproject_ex(geom.ref, y, o, int(bool(accumulate)), int(strategy), _stream()))
     return out
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    _check(lib().tomo_get_tuning(ctypes.byref(t)))
+    return {k: getattr(t, k) for k, _ in Tuning._fields_}
+
+
+def set_tuning(**kw) -> dict:
+    """Change launch tuning fields (see tomo_tuning); returns the previous
+    settings."""
+    old = get_tuning()
+    new = dict(old)
+    for k, v in kw.items():
+        if k not in new:
+            raise KeyError(k)
+        new[k] = int(v)
+    t = Tuning(**new)
+    _check(lib().tomo_set_tuning(ctypes.byref(t)))
+    return old
+
+
+def binning_spills(geom: DeviceGeometry) -> int:
+    """Binned back-projection writes that missed their LDS box (must be 0)."""
+    n = c_int64(0)
+    _check(lib().tomo_binning_spills(geom.ref, ctypes.byref(n)))
+    return int(n.value)
 
 
 def count_crossings(geom: DeviceGeometry) -> int:

@@ -24,16 +24,27 @@ def to_host(t):
     return t.detach().cpu().numpy().astype(np.float64)
 
 
-def assert_p_close(gpu, ora_val, ora_abs, rtol=P_RTOL, what="P"):
-    """|gpu - oracle| <= rtol * (P|x|)_ray per pixel; pixels whose P|x| is 0
-    must be exactly 0 on the GPU."""
+def length_resolution(g):
+    """Absolute resolution of the oracle's FP64 segment lengths: each crossing
+    parameter t (up to |obs| + box diagonal, with |d| ~ 1) is rounded to
+    ~eps * t, so a length carries up to ~2 eps t; with a factor 2 of margin."""
+    tmax = np.max(np.linalg.norm(g.views[:, 0:3], axis=1)) + np.linalg.norm(g.hi - g.lo)
+    return 4.0 * np.finfo(np.float64).eps * tmax
+
+
+def assert_p_close(gpu, ora_val, ora_abs, rtol=P_RTOL, what="P", atol=0.0):
+    """|gpu - oracle| <= rtol * (P|x|)_ray + atol per entry; entries whose
+    P|x| is 0 must be exactly 0 on the GPU.  atol is the oracle's own
+    resolution (length_resolution x max |value|), which only matters for
+    entries built from segments too short for FP64 to resolve."""
     gpu = np.asarray(gpu, dtype=np.float64).ravel()
     ora_val = np.asarray(ora_val).ravel()
     ora_abs = np.asarray(ora_abs).ravel()
     err = np.abs(gpu - ora_val)
-    bound = rtol * ora_abs
+    bound = rtol * ora_abs + atol
     zero = ora_abs == 0
-    assert np.all(gpu[zero] == 0.0), f"{what}: {np.count_nonzero(gpu[zero])} untouched entries non-zero"
+    stray = np.abs(gpu[zero]) > atol  # a sub-resolution near-tie may show on one side only
+    assert not np.any(stray), f"{what}: {np.count_nonzero(stray)} untouched entries non-zero"
     bad = err > bound
     if np.any(bad):
         k = np.argmax(err / np.maximum(bound, 1e-300))

@@ -3,8 +3,8 @@ import numpy as np
 import pytest
 
 import tomo_synth as ts
-from _gpu_common import (assert_p_close, flat_index, need_gpu, oracle_pixels, sample_pixels,
-                         to_dev, to_host)
+from _gpu_common import (assert_p_close, flat_index, length_resolution, need_gpu, oracle_pixels,
+                         sample_pixels, to_dev, to_host)
 
 pytestmark = pytest.mark.gpu
 
@@ -14,13 +14,23 @@ def tomo():
     return need_gpu()
 
 
-def _parity_full(tomo, ora, g, x, y):
+STRATEGIES = ["binned", "atomic"]
+
+
+def _parity_full(tomo, ora, g, x, y, strategies=STRATEGIES):
+    """Every pixel of P and every voxel of P^T (each back-projection
+    strategy) against the oracle."""
     dg = tomo.DeviceGeometry(g)
+    res = length_resolution(g)
     img = to_host(tomo.project(dg, to_dev(x)))
     xm = x if g.map_mask is None else x * (g.map_mask if g.nframes == 1 else g.map_mask[None])
-    assert_p_close(img, ora.project(g, x), ora.project(g, np.abs(xm)))
-    bp = to_host(tomo.backproject(dg, to_dev(y)))
-    assert_p_close(bp, ora.backproject(g, y), ora.backproject(g, np.abs(y)), rtol=1e-4, what="P^T")
+    assert_p_close(img, ora.project(g, x), ora.project(g, np.abs(xm)), atol=res * np.abs(x).max())
+    ref, refa = ora.backproject(g, y), ora.backproject(g, np.abs(y))
+    for strat in strategies:
+        code = {"binned": tomo.BP_BINNED, "atomic": tomo.BP_ATOMIC}[strat]
+        bp = to_host(tomo.backproject(dg, to_dev(y), strategy=code))
+        assert_p_close(bp, ref, refa, rtol=1e-4, what=f"P^T ({strat})", atol=res * np.abs(y).max())
+        assert tomo.binning_spills(dg) == 0
 
 
 def test_tiny_projection_and_transpose(tomo, ora):
@@ -92,6 +102,7 @@ def test_euvi_full_size_sampled(tomo, ora):
     for p in sel:
         y[flat_index(g, *p)] = rng.normal()
     bp = to_host(tomo.backproject(dg, to_dev(y)))
+    assert tomo.binning_spills(dg) == 0
     # oracle P^T from the selected rays only
     ref = np.zeros(g.nvox)
     refa = np.zeros(g.nvox)
@@ -102,7 +113,8 @@ def test_euvi_full_size_sampled(tomo, ora):
         keep = g.map_mask.reshape(-1)[idx] == 1
         np.add.at(ref, idx[keep], ln[keep] * yv)
         np.add.at(refa, idx[keep], ln[keep] * abs(yv))
-    assert_p_close(bp, ref, refa, rtol=1e-4, what="P^T")
+    assert_p_close(bp, ref, refa, rtol=1e-4, what="P^T",
+                   atol=length_resolution(g) * np.abs(y).max())
 
 
 def _dyadic_geometry():
