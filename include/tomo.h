@@ -50,6 +50,7 @@
 #ifndef TOMO_H
 #define TOMO_H
 
+#include <stddef.h>
 #include <stdint.h>
 
 #ifdef __cplusplus
@@ -202,6 +203,37 @@ int tomo_apply_prior(const tomo_cube *cube, double lambda_r, double lambda_t,
  * w1[16][1][27], b1[16], w2[16][16][27], b2[16], w3[1][16][27], b3[1]
  * (w[cout][cin][kz*9 + ky*3 + kx], cross-correlation like torch.conv3d). */
 #define TOMO_CONVNET_NPARAMS 7809
+
+/* DEVICE workspace bytes that tomo_convnet_forward / tomo_convnet_loss_grad
+ * need for a cube of this size (one frame); 0 if the cube is invalid. */
+size_t tomo_convnet_workspace_bytes(const tomo_cube *cube);
+
+/*
+ * out = N(x) on one nx*ny*nz volume (x, out: DEVICE float, x fastest).
+ * Hidden activations are BF16 and the 16 -> 16 layer runs on MFMA (BF16
+ * inputs, FP32 accumulation); the outer layers accumulate in FP32.
+ * ws_d: DEVICE workspace of at least tomo_convnet_workspace_bytes bytes.
+ */
+int tomo_convnet_forward(const tomo_cube *cube, const float *params_d,
+                         const float *x_d, float *out_d, void *ws_d,
+                         size_t ws_bytes, tomo_stream stream);
+
+/*
+ * Training gradient of loss = mean((N(x) - target)^2) over the volume:
+ * grad_d (DEVICE float[TOMO_CONVNET_NPARAMS]) receives d loss / d params
+ * (same layout as the parameters); *loss_h (HOST, may be NULL) the loss,
+ * which makes the call synchronise the stream.
+ */
+int tomo_convnet_loss_grad(const tomo_cube *cube, const float *params_d,
+                           const float *x_d, const float *target_d,
+                           float *grad_d, double *loss_h, void *ws_d,
+                           size_t ws_bytes, tomo_stream stream);
+
+/* One Adam update (Kingma & Ba) of n parameters in place; step counts from
+ * 1; m_d, v_d are the DEVICE moment buffers (zero before the first step). */
+int tomo_adam_step(float *params_d, const float *grad_d, float *m_d, float *v_d,
+                   int32_t n, int32_t step, double lr, double beta1,
+                   double beta2, double eps, tomo_stream stream);
 
 typedef struct tomo_cg_params {
     double lambda_r;       /* spatial prior weight (>= 0)                        */

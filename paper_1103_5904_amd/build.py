@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtomo.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["api.hip", "siddon.hip", "binned.hip", "solver.hip"]
+SOURCES = ["api.hip", "siddon.hip", "binned.hip", "solver.hip", "convnet.hip"]
 
 # The projector's inputs are validated finite, so its min/max need no NaN
 # quieting; the solver keeps IEEE NaN semantics for its non-finite checks.

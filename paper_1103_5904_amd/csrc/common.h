@@ -157,4 +157,10 @@ int launch_fill(float *x, int64_t n, float v, hipStream_t s);
 int launch_backproject_binned(const Plan &p, const tomo_geometry *g, const float *images,
                               float *cube, bool use_map_mask, hipStream_t s, const int *done_flag);
 
+// Learned preconditioner network (convnet.hip)
+size_t convnet_forward_ws_bytes(int64_t nvox);
+int convnet_forward_dev(const tomo_cube &c, const float *P, const float *x, float *out,
+                        const double *norm2, const uint8_t *map_mask, void *ws, hipStream_t s,
+                        bool prep_frags, const int *skip);
+
 }  // namespace tomo

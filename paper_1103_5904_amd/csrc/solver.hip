@@ -31,14 +31,22 @@ struct CgState {
     double thresh2;   // (rtol ||b||)^2, or -1 when no residual target
     double res2;      // r.r of the current iterate
     double aux;       // scratch result of the last reduction
+    double res_prev;  // flexible CG: r.r of the previous iterate (stall test)
+    double drop2;     // flexible CG: (1 - min_drop)^2
     int32_t iter;     // iterations completed
     int32_t max_iter; // iteration limit
     int32_t done;     // 1: stop (converged, limit reached or non-finite)
     int32_t nonfinite;
+    int32_t window;   // flexible CG: stalled iterations before the fall-back
+    int32_t stall;    // consecutive iterations without a residual decrease
+    int32_t fellback; // 1 once the solver has switched to plain CG
+    int32_t fb_iter;  // iteration of the switch
+    int32_t restart;  // 1: the next direction restarts (beta = 0)
+    int32_t net_off;  // 1: skip the network (done, or fallen back)
 };
 
 struct Workspace {
-    double *partials;   // [kRedBlocks][2]
+    double *partials;   // [kRedBlocks][4]
     unsigned *counter;  // last-block detection
     CgState *st;
     double *hist;       // [max_iter + 1]
@@ -95,18 +103,20 @@ __global__ __launch_bounds__(kThreads) void k_prior(const float *__restrict__ x,
 
 // --------------------------------------------------------- reductions
 
-// Reduce two doubles per thread over the whole grid.  Returns true in the
-// last workgroup to finish, whose thread 0 then holds the grid totals in
-// (t0, t1).  The partials are summed in block order: deterministic.
-__device__ inline bool grid_reduce2(double a, double b, const Workspace &ws, double &t0, double &t1)
+// Reduce NV doubles per thread over the whole grid.  Returns true in the
+// last workgroup to finish, whose thread 0 then holds the grid totals in t.
+// The partials are summed in block order: deterministic.
+template <int NV>
+__device__ inline bool grid_reduce(const double (&a)[NV], const Workspace &ws, double (&t)[NV])
 {
     __shared__ double lds[4];
     __shared__ int last;
-    const double sa = block_sum(a, lds);
-    const double sb = block_sum(b, lds);
+    double sa[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) sa[k] = block_sum(a[k], lds);
     if (threadIdx.x == 0) {
-        ws.partials[2 * blockIdx.x] = sa;
-        ws.partials[2 * blockIdx.x + 1] = sb;
+#pragma unroll
+        for (int k = 0; k < NV; ++k) ws.partials[4 * blockIdx.x + k] = sa[k];
         __threadfence();
         const unsigned prev = atomicAdd(ws.counter, 1u);
         last = (prev == gridDim.x - 1);
@@ -114,15 +124,26 @@ __device__ inline bool grid_reduce2(double a, double b, const Workspace &ws, dou
     __syncthreads();
     if (!last) return false;
     __threadfence();
-    double pa = 0.0, pb = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads) {
-        pa += __builtin_nontemporal_load(&ws.partials[2 * i]);
-        pb += __builtin_nontemporal_load(&ws.partials[2 * i + 1]);
-    }
-    t0 = block_sum(pa, lds);
-    t1 = block_sum(pb, lds);
+    double pa[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) pa[k] = 0.0;
+    for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) pa[k] += __builtin_nontemporal_load(&ws.partials[4 * i + k]);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t[k] = block_sum(pa[k], lds);
     if (threadIdx.x == 0) *ws.counter = 0u;
     return true;
+}
+
+__device__ inline bool grid_reduce2(double a, double b, const Workspace &ws, double &t0, double &t1)
+{
+    const double in[2] = {a, b};
+    double out[2];
+    const bool last = grid_reduce<2>(in, ws, out);
+    t0 = out[0];
+    t1 = out[1];
+    return last;
 }
 
 __device__ inline bool bad(double v) { return !isfinite(v); }
@@ -227,6 +248,120 @@ __global__ __launch_bounds__(kThreads) void k_cg_p(const float *__restrict__ r,
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kThreads)
         p[i] = (float)((double)r[i] + beta * p[i]);
+}
+
+// ---- flexible CG (preconditioner network z = ||r|| N(r / ||r||))
+
+// Set-up after k_cg_start: the first direction will be p = z (beta = 0).
+__global__ void k_fcg_init(Workspace ws, int32_t window, double min_drop)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    CgState &s = *ws.st;
+    s.alpha = 0.0;
+    s.window = window;
+    s.drop2 = (1.0 - min_drop) * (1.0 - min_drop);
+    s.res_prev = s.res2;
+    s.stall = 0;
+    s.restart = 0;
+    s.net_off = s.done || s.fellback;
+}
+
+// x += alpha p; r -= alpha q (q is kept for beta); res2 = r.r; stall test.
+__global__ __launch_bounds__(kThreads) void k_fcg_xr(float *__restrict__ x, float *__restrict__ r,
+                                                     const float *__restrict__ p,
+                                                     const float *__restrict__ q, int64_t n,
+                                                     Workspace ws)
+{
+    if (ws.st->done) return;
+    const double alpha = ws.st->alpha;
+    double rr = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        x[i] = (float)((double)x[i] + alpha * p[i]);
+        const float rv = (float)((double)r[i] - alpha * q[i]);
+        r[i] = rv;
+        rr += (double)rv * rv;
+    }
+    double trr, unused;
+    if (grid_reduce2(rr, 0.0, ws, trr, unused) && threadIdx.x == 0) {
+        CgState &s = *ws.st;
+        s.res_prev = s.res2;
+        s.res2 = trr;
+        s.iter += 1;
+        ws.hist[s.iter] = sqrt(trr / s.bb);
+        if (bad(trr)) s.nonfinite = 1;
+        s.stall = trr > s.drop2 * s.res_prev ? s.stall + 1 : 0;
+        if (!s.fellback && s.stall >= s.window) {
+            s.fellback = 1;
+            s.fb_iter = s.iter;
+            s.restart = 1;
+            s.stall = 0;
+        }
+        s.done = s.nonfinite || trr <= s.thresh2 || s.iter >= s.max_iter;
+        s.net_off = s.done || s.fellback;
+    }
+}
+
+// z.r, z.q, r.r, r.q; q = 0; beta: Polak-Ribiere -alpha z.q / (z.r)_old, or
+// plain CG after the fall-back (and 0 on a restart).  A direction with
+// z.r <= 0 (or non-finite) triggers the fall-back.
+__global__ __launch_bounds__(kThreads) void k_fcg_dots(const float *__restrict__ z,
+                                                       const float *__restrict__ r,
+                                                       float *__restrict__ q, int64_t n,
+                                                       Workspace ws)
+{
+    if (ws.st->done) return;
+    const bool usez = !ws.st->fellback;
+    double a[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads) {
+        const double rv = r[i], qv = q[i];
+        const double zv = usez ? (double)z[i] : 0.0;
+        a[0] += zv * rv;
+        a[1] += zv * qv;
+        a[2] += rv * rv;
+        a[3] += rv * qv;
+        q[i] = 0.0f;
+    }
+    double t[4];
+    if (grid_reduce<4>(a, ws, t) && threadIdx.x == 0) {
+        CgState &s = *ws.st;
+        if (!s.fellback && !(t[0] > 0.0 && !bad(t[0]))) {
+            s.fellback = 1;
+            s.fb_iter = s.iter;
+            s.restart = 1;
+        }
+        double num, beta;
+        if (s.fellback) {
+            num = t[2];
+            beta = s.restart ? 0.0 : num / s.rr;
+        } else {
+            num = t[0];
+            beta = -s.alpha * t[1] / s.rr;
+        }
+        if (bad(beta) || bad(num)) {
+            s.nonfinite = 1;
+            s.done = 1;
+        }
+        s.beta = beta;
+        s.rr = num;
+        s.restart = 0;
+        s.net_off = s.done || s.fellback;
+    }
+}
+
+// p = z + beta p (or r + beta p after the fall-back).
+__global__ __launch_bounds__(kThreads) void k_fcg_p(const float *__restrict__ z,
+                                                    const float *__restrict__ r,
+                                                    float *__restrict__ p, int64_t n,
+                                                    const CgState *__restrict__ st)
+{
+    if (st->done) return;
+    const double beta = st->beta;
+    const float *src = st->fellback ? r : z;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * kThreads)
+        p[i] = (float)((double)src[i] + beta * p[i]);
 }
 
 // q = M (q + prior(x)); aux = |b - q|^2 (true residual of x).
@@ -364,13 +499,16 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         !isfinite(prm->lambda_t) || prm->max_iter < 0 || !(prm->rtol >= 0) ||
         !isfinite(prm->rtol) || prm->check_every < 1)
         return set_error(TOMO_EINVAL, "tomo_cg_solve: invalid parameters");
-    if (prm->precond)
-        return set_error(TOMO_EUNSUPPORTED, "tomo_cg_solve: preconditioner not available");
+    if (prm->precond && (prm->fallback_window < 1 || !(prm->min_drop >= 0) || !(prm->min_drop < 1)))
+        return set_error(TOMO_EINVAL, "tomo_cg_solve: fallback_window must be >= 1 and min_drop in [0, 1)");
     int st = TOMO_OK;
     PlanRef plan = get_plan(g, &st);
     if (!plan) return st;
     if (prm->lambda_t > 0 && g->cube.nframes < 2)
         return set_error(TOMO_EINVAL, "tomo_cg_solve: lambda_t needs nframes >= 2");
+    if (prm->precond && g->cube.nframes != 1)
+        return set_error(TOMO_EUNSUPPORTED, "tomo_cg_solve: the preconditioner needs nframes == 1");
+    const bool fcg = prm->precond != nullptr;
     hipStream_t s = (hipStream_t)stream;
     const Dims d = dims_of(g->cube);
     const int64_t n = d.total;
@@ -385,13 +523,17 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     float *q = (float *)buf.alloc(sizeof(float) * n);
     float *img = (float *)buf.alloc(sizeof(float) * plan->npix);
     Workspace ws;
-    ws.partials = (double *)buf.alloc(sizeof(double) * 2 * kRedBlocks);
+    ws.partials = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
     ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
     ws.st = (CgState *)buf.alloc(sizeof(CgState));
     ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)maxit + 1));
-    if (!b || !r || !p || !q || !img || !ws.partials || !ws.counter || !ws.st || !ws.hist)
+    float *z = fcg ? (float *)buf.alloc(sizeof(float) * n) : nullptr;
+    void *netws = fcg ? buf.alloc(convnet_forward_ws_bytes(d.nvox)) : nullptr;
+    if (!b || !r || !p || !q || !img || !ws.partials || !ws.counter || !ws.st || !ws.hist ||
+        (fcg && (!z || !netws)))
         return set_error(TOMO_ENOMEM, "tomo_cg_solve: device allocation failed");
     int rc = hip_fail(hipMemsetAsync(ws.counter, 0, sizeof(unsigned), s), "counter init");
+    if (!rc) rc = hip_fail(hipMemsetAsync(ws.st, 0, sizeof(CgState), s), "state init");
     if (rc) return rc;
     CgState *hst = nullptr;
     if (hipHostMalloc((void **)&hst, sizeof(CgState)) != hipSuccess)
@@ -454,6 +596,22 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
                        prm->x0_given ? 1 : 0, ws, prm->rtol, maxit, 0);
     rc = hip_fail(hipGetLastError(), "cg start");
     if (rc) return rc;
+    bool frags_ready = false;
+    // flexible CG: first direction p = z = N(r) (or r if z.r <= 0)
+    auto fcg_start = [&]() -> int {
+        hipLaunchKernelGGL(k_fcg_init, dim3(1), dim3(64), 0, s, ws, prm->fallback_window, prm->min_drop);
+        int e = convnet_forward_dev(g->cube, prm->precond, r, z, &ws.st->res2, g->map_mask, netws, s,
+                                    !frags_ready, &ws.st->net_off);
+        frags_ready = true;
+        if (e) return e;
+        hipLaunchKernelGGL(k_fcg_dots, dim3(eb), dim3(kThreads), 0, s, z, r, q, n, ws);
+        hipLaunchKernelGGL(k_fcg_p, dim3(eb), dim3(kThreads), 0, s, z, r, p, n, ws.st);
+        return hip_fail(hipGetLastError(), "fcg start");
+    };
+    if (fcg) {
+        rc = fcg_start();
+        if (rc) return rc;
+    }
 
     auto enqueue_iteration = [&]() -> int {
         hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
@@ -475,8 +633,17 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         }
         if (e) return e;
         hipLaunchKernelGGL(k_cg_q, dim3(eb), dim3(kThreads), 0, s, p, q, g->map_mask, d, lr, lt, ws);
-        hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
-        hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, s, r, p, n, ws.st);
+        if (!fcg) {
+            hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
+            hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, s, r, p, n, ws.st);
+        } else {
+            hipLaunchKernelGGL(k_fcg_xr, dim3(eb), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
+            e = convnet_forward_dev(g->cube, prm->precond, r, z, &ws.st->res2, g->map_mask, netws, s,
+                                    false, &ws.st->net_off);
+            if (e) return e;
+            hipLaunchKernelGGL(k_fcg_dots, dim3(eb), dim3(kThreads), 0, s, z, r, q, n, ws);
+            hipLaunchKernelGGL(k_fcg_p, dim3(eb), dim3(kThreads), 0, s, z, r, p, n, ws.st);
+        }
         return hip_fail(hipGetLastError(), "cg iteration launch");
     };
 
@@ -524,6 +691,10 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
                            prm->rtol, maxit, done_iters);
         rc = hip_fail(hipGetLastError(), "cg restart");
         if (rc) return rc;
+        if (fcg) {
+            rc = fcg_start();
+            if (rc) return rc;
+        }
     }
 
     // report
@@ -531,7 +702,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     if (!rc) rc = hip_fail(hipStreamSynchronize(s), "cg synchronise");
     if (rc) return rc;
     rep->iters = hst->iter;
-    rep->fell_back = -1;
+    rep->fell_back = hst->fellback ? hst->fb_iter : -1;
     rep->n_project = n_proj;
     rep->n_backproject = n_bp;
     rep->bnorm = sqrt(hst->bb);

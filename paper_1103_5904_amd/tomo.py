@@ -75,8 +75,10 @@ EXPORTS = [
     "tomo_trace_ray", "tomo_apply_prior", "tomo_cg_solve", "tomo_cg_default_params",
     "tomo_view_from_wcs", "tomo_validate_geometry", "tomo_geometry_pixels",
     "tomo_release_cache", "tomo_status_string", "tomo_last_error", "tomo_binning_spills",
-    "tomo_get_tuning", "tomo_set_tuning",
+    "tomo_get_tuning", "tomo_set_tuning", "tomo_convnet_workspace_bytes", "tomo_convnet_forward",
+    "tomo_convnet_loss_grad", "tomo_adam_step",
 ]
+NPARAMS = 7809
 
 _lib = None
 
@@ -109,6 +111,14 @@ def lib():
         L.tomo_validate_geometry.argtypes = [POINTER(TomoGeometry)]
         L.tomo_binning_spills.argtypes = [POINTER(TomoGeometry), POINTER(c_int64)]
         L.tomo_get_tuning.argtypes = [POINTER(Tuning)]
+        L.tomo_convnet_workspace_bytes.argtypes = [POINTER(TomoCube)]
+        L.tomo_convnet_workspace_bytes.restype = ctypes.c_size_t
+        L.tomo_convnet_forward.argtypes = [POINTER(TomoCube), c_void_p, c_void_p, c_void_p, c_void_p,
+                                           ctypes.c_size_t, c_void_p]
+        L.tomo_convnet_loss_grad.argtypes = [POINTER(TomoCube), c_void_p, c_void_p, c_void_p, c_void_p,
+                                             POINTER(c_double), c_void_p, ctypes.c_size_t, c_void_p]
+        L.tomo_adam_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
+                                     c_double, c_double, c_double, c_double, c_void_p]
         L.tomo_set_tuning.argtypes = [POINTER(Tuning)]
         L.tomo_geometry_pixels.argtypes = [POINTER(TomoGeometry)]
         _lib = L
@@ -303,6 +313,49 @@ def cg_solve(geom: DeviceGeometry, y: torch.Tensor, x0: torch.Tensor | None = No
                                           "ms_project", "ms_backproject")}
     report["history"] = np.ctypeslib.as_array(hist)[:rep.history_len].copy()
     return out, report
+
+
+class ConvNet:
+    """Device-side runner for the preconditioner network on one volume shape
+    (nx, ny, nz): owns the workspace; parameters are a float32 CUDA tensor of
+    NPARAMS values (w1, b1, w2, b2, w3, b3 as in include/tomo.h)."""
+
+    def __init__(self, shape_zyx, device="cuda"):
+        nz, ny, nx = (int(k) for k in shape_zyx)
+        self.cube = TomoCube(nx, ny, nz, 1, (c_double * 3)(0, 0, 0), (c_double * 3)(1, 1, 1))
+        self.shape = (nz, ny, nx)
+        self.n = nx * ny * nz
+        nbytes = lib().tomo_convnet_workspace_bytes(ctypes.byref(self.cube))
+        if nbytes == 0:
+            raise ValueError("invalid volume shape")
+        self.ws = torch.empty(nbytes, dtype=torch.uint8, device=device)
+
+    def forward(self, params, x, out=None):
+        if out is None:
+            out = torch.empty(self.shape, dtype=torch.float32, device=x.device)
+        _check(lib().tomo_convnet_forward(ctypes.byref(self.cube), _dev_f32(params, NPARAMS, "params"),
+                                          _dev_f32(x, self.n, "x"), _dev_f32(out, self.n, "out"),
+                                          c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream()))
+        return out
+
+    def loss_grad(self, params, x, target, grad=None, want_loss=True):
+        """grad of mean((N(x) - target)^2) w.r.t. params; returns (loss or None, grad)."""
+        if grad is None:
+            grad = torch.empty(NPARAMS, dtype=torch.float32, device=x.device)
+        loss = c_double(0.0)
+        _check(lib().tomo_convnet_loss_grad(ctypes.byref(self.cube), _dev_f32(params, NPARAMS, "params"),
+                                            _dev_f32(x, self.n, "x"), _dev_f32(target, self.n, "target"),
+                                            _dev_f32(grad, NPARAMS, "grad"),
+                                            ctypes.byref(loss) if want_loss else None,
+                                            c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream()))
+        return (loss.value if want_loss else None), grad
+
+
+def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    n = params.numel()
+    _check(lib().tomo_adam_step(_dev_f32(params, n, "params"), _dev_f32(grad, n, "grad"),
+                                _dev_f32(m, n, "m"), _dev_f32(v, n, "v"), n, int(step), lr, beta1,
+                                beta2, eps, _stream()))
 
 
 def view_from_wcs(dsun, hgln_deg, hglt_deg, crval1_as, crval2_as, crota_deg, cdelt1_as,
