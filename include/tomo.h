@@ -204,7 +204,7 @@ int tomo_apply_prior(const tomo_cube *cube, double lambda_r, double lambda_t,
  * (w[cout][cin][kz*9 + ky*3 + kx], cross-correlation like torch.conv3d). */
 #define TOMO_CONVNET_NPARAMS 7809
 
-/* DEVICE workspace bytes that tomo_convnet_forward / tomo_convnet_loss_grad
+/* DEVICE workspace bytes that tomo_convnet_forward / _loss_grad / _backward
  * need for a cube of this size (one frame); 0 if the cube is invalid. */
 size_t tomo_convnet_workspace_bytes(const tomo_cube *cube);
 
@@ -229,6 +229,19 @@ int tomo_convnet_loss_grad(const tomo_cube *cube, const float *params_d,
                            float *grad_d, double *loss_h, void *ws_d,
                            size_t ws_bytes, tomo_stream stream);
 
+/*
+ * Parameter gradient for a caller-given output gradient: grad_d receives
+ * sum_v dout[v] * d N(x)[v] / d params, i.e. the gradient of any loss whose
+ * derivative with respect to the network output is dout_d (DEVICE float, one
+ * value per voxel of x).  The preconditioner is trained this way on the
+ * energy-norm error 0.5 (N(r) - e)^T A (N(r) - e), for which dout = A (N(r) - e)
+ * comes from tomo_project, tomo_backproject and tomo_apply_prior.  Same
+ * activations and precision as tomo_convnet_loss_grad; does not synchronise.
+ */
+int tomo_convnet_backward(const tomo_cube *cube, const float *params_d,
+                          const float *x_d, const float *dout_d, float *grad_d,
+                          void *ws_d, size_t ws_bytes, tomo_stream stream);
+
 /* One Adam update (Kingma & Ba) of n parameters in place; step counts from
  * 1; m_d, v_d are the DEVICE moment buffers (zero before the first step). */
 int tomo_adam_step(float *params_d, const float *grad_d, float *m_d, float *v_d,
@@ -249,6 +262,11 @@ typedef struct tomo_cg_params {
     int32_t bp_strategy;   /* TOMO_BP_*                                          */
     double min_drop;       /* FCG: a residual "decreases" if it falls below
                               (1 - min_drop) times the previous one              */
+    float *record_x;       /* DEVICE [record_count][voxels] or NULL: iterate x_k,
+                              k = 0..record_count-1 (training data)              */
+    float *record_r;       /* DEVICE [record_count][voxels] or NULL: residual r_k */
+    int32_t record_count;  /* iterates to record (>= 0)                          */
+    int32_t reserved;
 } tomo_cg_params;
 
 typedef struct tomo_cg_report {

@@ -508,18 +508,15 @@ int tomo_convnet_forward(const tomo_cube *cube, const float *params_d, const flo
                                (hipStream_t)stream, true, nullptr);
 }
 
-int tomo_convnet_loss_grad(const tomo_cube *cube, const float *params_d, const float *x_d,
-                           const float *target_d, float *grad_d, double *loss_h, void *ws_d,
-                           size_t ws_bytes, tomo_stream stream)
+// Forward pass that keeps the activations, then back-propagation of the
+// output gradient g_d (d loss / d out, one value per voxel) into grad_d.  With
+// target_d set, g_d is ignored and replaced by the MSE gradient
+// 2 (out - target) / n, whose per-block loss partials land in w.loss_part.
+static int convnet_train_pass(const tomo_cube *cube, const float *params_d, const float *x_d,
+                              const float *target_d, const float *g_d, float *grad_d, void *ws_d,
+                              hipStream_t s)
 {
-    int rc = check_net_cube(cube);
-    if (rc) return rc;
-    if (!params_d || !x_d || !target_d || !grad_d || !ws_d)
-        return set_error(TOMO_EINVAL, "tomo_convnet_loss_grad: NULL argument");
     const int64_t n = (int64_t)cube->nx * cube->ny * cube->nz;
-    if (ws_bytes < ws_layout(n, nullptr, nullptr))
-        return set_error(TOMO_EINVAL, "tomo_convnet_loss_grad: workspace too small");
-    hipStream_t s = (hipStream_t)stream;
     NetWs w;
     ws_layout(n, &w, (char *)ws_d);
     const Vol d{cube->nx, cube->ny, cube->nz, n};
@@ -533,14 +530,18 @@ int tomo_convnet_loss_grad(const tomo_cube *cube, const float *params_d, const f
                        (const double *)nullptr, w.a1, noskip);
     hipLaunchKernelGGL(k_conv16, rowgrid, dim3(kThreads), 0, s, w.a1, w.frag, params_d + OB2, d, 1,
                        (const uint16_t *)nullptr, w.a2, noskip);
-    hipLaunchKernelGGL(k_conv3, dim3(vox_blocks(n)), dim3(kThreads), 0, s, params_d, w.a2, d,
-                       (const double *)nullptr, (const uint8_t *)nullptr, w.out, noskip);
-    // loss and d loss / d out
-    hipLaunchKernelGGL(k_mse, dim3(kLossBlocks), dim3(kThreads), 0, s, w.out, target_d, n, w.g, w.loss_part);
+    if (target_d) {
+        hipLaunchKernelGGL(k_conv3, dim3(vox_blocks(n)), dim3(kThreads), 0, s, params_d, w.a2, d,
+                           (const double *)nullptr, (const uint8_t *)nullptr, w.out, noskip);
+        // loss and d loss / d out
+        hipLaunchKernelGGL(k_mse, dim3(kLossBlocks), dim3(kThreads), 0, s, w.out, target_d, n, w.g,
+                           w.loss_part);
+        g_d = w.g;
+    }
     // layer 3
-    hipLaunchKernelGGL(k_wgrad3, dim3(kWgBlocks), dim3(448), 0, s, w.g, w.a2, d, w.part);
+    hipLaunchKernelGGL(k_wgrad3, dim3(kWgBlocks), dim3(448), 0, s, g_d, w.a2, d, w.part);
     hipLaunchKernelGGL(k_reduce_parts, dim3(2), dim3(256), 0, s, w.part, kWgBlocks, 433, grad_d, OW3);
-    hipLaunchKernelGGL(k_conv3_bwd, dim3(vox_blocks(n)), dim3(kThreads), 0, s, params_d, w.g, w.a2, d, w.gh);
+    hipLaunchKernelGGL(k_conv3_bwd, dim3(vox_blocks(n)), dim3(kThreads), 0, s, params_d, g_d, w.a2, d, w.gh);
     // layer 2 (gh = d loss / d h2)
     hipLaunchKernelGGL(k_wgrad2, dim3(kWgBlocks), dim3(kThreads), 0, s, w.gh, w.a1, d, w.part);
     hipLaunchKernelGGL(k_reduce_parts, dim3((6928 + 255) / 256), dim3(256), 0, s, w.part, kWgBlocks, 6928,
@@ -551,9 +552,26 @@ int tomo_convnet_loss_grad(const tomo_cube *cube, const float *params_d, const f
     // layer 1
     hipLaunchKernelGGL(k_wgrad1, dim3(kWgBlocks), dim3(448), 0, s, w.a2, x_d, d, w.part);
     hipLaunchKernelGGL(k_reduce_parts, dim3(2), dim3(256), 0, s, w.part, kWgBlocks, 448, grad_d, OW1);
-    rc = hip_fail(hipGetLastError(), "convnet backward launch");
+    return hip_fail(hipGetLastError(), "convnet backward launch");
+}
+
+int tomo_convnet_loss_grad(const tomo_cube *cube, const float *params_d, const float *x_d,
+                           const float *target_d, float *grad_d, double *loss_h, void *ws_d,
+                           size_t ws_bytes, tomo_stream stream)
+{
+    int rc = check_net_cube(cube);
+    if (rc) return rc;
+    if (!params_d || !x_d || !target_d || !grad_d || !ws_d)
+        return set_error(TOMO_EINVAL, "tomo_convnet_loss_grad: NULL argument");
+    const int64_t n = (int64_t)cube->nx * cube->ny * cube->nz;
+    if (ws_bytes < ws_layout(n, nullptr, nullptr))
+        return set_error(TOMO_EINVAL, "tomo_convnet_loss_grad: workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    rc = convnet_train_pass(cube, params_d, x_d, target_d, nullptr, grad_d, ws_d, s);
     if (rc) return rc;
     if (loss_h) {
+        NetWs w;
+        ws_layout(n, &w, (char *)ws_d);
         double parts[kLossBlocks];
         rc = hip_fail(hipMemcpyAsync(parts, w.loss_part, sizeof(parts), hipMemcpyDeviceToHost, s), "loss copy");
         if (!rc) rc = hip_fail(hipStreamSynchronize(s), "loss synchronise");
@@ -563,6 +581,20 @@ int tomo_convnet_loss_grad(const tomo_cube *cube, const float *params_d, const f
         *loss_h = acc / (double)n;
     }
     return TOMO_OK;
+}
+
+int tomo_convnet_backward(const tomo_cube *cube, const float *params_d, const float *x_d,
+                          const float *dout_d, float *grad_d, void *ws_d, size_t ws_bytes,
+                          tomo_stream stream)
+{
+    int rc = check_net_cube(cube);
+    if (rc) return rc;
+    if (!params_d || !x_d || !dout_d || !grad_d || !ws_d)
+        return set_error(TOMO_EINVAL, "tomo_convnet_backward: NULL argument");
+    const int64_t n = (int64_t)cube->nx * cube->ny * cube->nz;
+    if (ws_bytes < ws_layout(n, nullptr, nullptr))
+        return set_error(TOMO_EINVAL, "tomo_convnet_backward: workspace too small");
+    return convnet_train_pass(cube, params_d, x_d, nullptr, dout_d, grad_d, ws_d, (hipStream_t)stream);
 }
 
 int tomo_adam_step(float *params_d, const float *grad_d, float *m_d, float *v_d, int32_t n,

@@ -497,7 +497,8 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     if (!y_d || !x_d || !prm || !rep) return set_error(TOMO_EINVAL, "tomo_cg_solve: NULL argument");
     if (!(prm->lambda_r >= 0) || !(prm->lambda_t >= 0) || !isfinite(prm->lambda_r) ||
         !isfinite(prm->lambda_t) || prm->max_iter < 0 || !(prm->rtol >= 0) ||
-        !isfinite(prm->rtol) || prm->check_every < 1)
+        !isfinite(prm->rtol) || prm->check_every < 1 || prm->record_count < 0 ||
+        (prm->record_count > 0 && !prm->record_x && !prm->record_r))
         return set_error(TOMO_EINVAL, "tomo_cg_solve: invalid parameters");
     if (prm->precond && (prm->fallback_window < 1 || !(prm->min_drop >= 0) || !(prm->min_drop < 1)))
         return set_error(TOMO_EINVAL, "tomo_cg_solve: fallback_window must be >= 1 and min_drop in [0, 1)");
@@ -535,13 +536,14 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     int rc = hip_fail(hipMemsetAsync(ws.counter, 0, sizeof(unsigned), s), "counter init");
     if (!rc) rc = hip_fail(hipMemsetAsync(ws.st, 0, sizeof(CgState), s), "state init");
     if (rc) return rc;
-    CgState *hst = nullptr;
-    if (hipHostMalloc((void **)&hst, sizeof(CgState)) != hipSuccess)
+    // pinned host copy of the device state, one per calling thread, kept
+    // until the process ends (a pinned allocation per call costs more than a
+    // short solve's iterations)
+    thread_local CgState *hst = nullptr;
+    if (!hst && hipHostMalloc((void **)&hst, sizeof(CgState)) != hipSuccess) {
+        hst = nullptr;
         return set_error(TOMO_ENOMEM, "tomo_cg_solve: pinned allocation failed");
-    struct PinnedFree {
-        CgState *p;
-        ~PinnedFree() { (void)hipHostFree(p); }
-    } pin_guard{hst};
+    }
 
     const unsigned eb = elem_blocks(n);
     int n_proj = 0, n_bp = 0;
@@ -612,6 +614,20 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         rc = fcg_start();
         if (rc) return rc;
     }
+    int enqueued = 0;  // iterations enqueued so far (recording index)
+    auto record = [&](int k) -> int {
+        if (k >= prm->record_count) return TOMO_OK;
+        int e = TOMO_OK;
+        if (prm->record_x)
+            e = hip_fail(hipMemcpyAsync(prm->record_x + (int64_t)k * n, x_d, sizeof(float) * n,
+                                        hipMemcpyDeviceToDevice, s), "record x");
+        if (!e && prm->record_r)
+            e = hip_fail(hipMemcpyAsync(prm->record_r + (int64_t)k * n, r, sizeof(float) * n,
+                                        hipMemcpyDeviceToDevice, s), "record r");
+        return e;
+    };
+    rc = record(0);
+    if (rc) return rc;
 
     auto enqueue_iteration = [&]() -> int {
         hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr;
@@ -658,6 +674,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
             const int todo = chunk < maxit - done_iters - enq ? chunk : maxit - done_iters - enq;
             for (int k = 0; k < todo; ++k) {
                 rc = enqueue_iteration();
+                if (!rc) rc = record(++enqueued);
                 if (rc) return rc;
             }
             enq += todo;

@@ -58,7 +58,8 @@ class CgParams(ctypes.Structure):
     _fields_ = [("lambda_r", c_double), ("lambda_t", c_double), ("max_iter", c_int32),
                 ("x0_given", c_int32), ("rtol", c_double), ("check_every", c_int32),
                 ("use_graph", c_int32), ("precond", c_void_p), ("fallback_window", c_int32),
-                ("bp_strategy", c_int32), ("min_drop", c_double)]
+                ("bp_strategy", c_int32), ("min_drop", c_double), ("record_x", c_void_p),
+                ("record_r", c_void_p), ("record_count", c_int32), ("reserved", c_int32)]
 
 
 class CgReport(ctypes.Structure):
@@ -76,7 +77,7 @@ EXPORTS = [
     "tomo_view_from_wcs", "tomo_validate_geometry", "tomo_geometry_pixels",
     "tomo_release_cache", "tomo_status_string", "tomo_last_error", "tomo_binning_spills",
     "tomo_get_tuning", "tomo_set_tuning", "tomo_convnet_workspace_bytes", "tomo_convnet_forward",
-    "tomo_convnet_loss_grad", "tomo_adam_step",
+    "tomo_convnet_loss_grad", "tomo_convnet_backward", "tomo_adam_step",
 ]
 NPARAMS = 7809
 
@@ -117,6 +118,8 @@ def lib():
                                            ctypes.c_size_t, c_void_p]
         L.tomo_convnet_loss_grad.argtypes = [POINTER(TomoCube), c_void_p, c_void_p, c_void_p, c_void_p,
                                              POINTER(c_double), c_void_p, ctypes.c_size_t, c_void_p]
+        L.tomo_convnet_backward.argtypes = [POINTER(TomoCube), c_void_p, c_void_p, c_void_p, c_void_p,
+                                            c_void_p, ctypes.c_size_t, c_void_p]
         L.tomo_adam_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                      c_double, c_double, c_double, c_double, c_void_p]
         L.tomo_set_tuning.argtypes = [POINTER(Tuning)]
@@ -285,7 +288,8 @@ def cg_solve(geom: DeviceGeometry, y: torch.Tensor, x0: torch.Tensor | None = No
              lam_r: float = 1e-2, lam_t: float = 0.0, max_iter: int = 50, rtol: float = 0.0,
              check_every: int = 10, use_graph: bool = False, precond: torch.Tensor | None = None,
              fallback_window: int = 3, min_drop: float = 1e-6, bp_strategy: int = BP_AUTO,
-             time_kernels: bool = False, out: torch.Tensor | None = None):
+             time_kernels: bool = False, out: torch.Tensor | None = None,
+             record_x: torch.Tensor | None = None, record_r: torch.Tensor | None = None):
     """Solve M (P^T P + lam_r D^T D + lam_t D_t^T D_t) M x = M P^T y.
     Returns (x, report dict)."""
     p = CgParams()
@@ -295,6 +299,14 @@ def cg_solve(geom: DeviceGeometry, y: torch.Tensor, x0: torch.Tensor | None = No
     p.fallback_window, p.min_drop, p.bp_strategy = int(fallback_window), min_drop, int(bp_strategy)
     if precond is not None:
         p.precond = _dev_f32(precond, precond.numel(), "precond")
+    if record_x is not None or record_r is not None:
+        count = (record_x if record_x is not None else record_r).shape[0]
+        nv = geom.nvox * geom.nframes
+        p.record_count = int(count)
+        if record_x is not None:
+            p.record_x = _dev_f32(record_x, count * nv, "record_x")
+        if record_r is not None:
+            p.record_r = _dev_f32(record_r, count * nv, "record_r")
     if out is None:
         out = torch.empty(geom.cube_shape, dtype=torch.float32, device=y.device)
     if x0 is not None:
@@ -349,6 +361,16 @@ class ConvNet:
                                             ctypes.byref(loss) if want_loss else None,
                                             c_void_p(self.ws.data_ptr()), self.ws.numel(), _stream()))
         return (loss.value if want_loss else None), grad
+
+    def backward(self, params, x, dout, grad=None):
+        """grad of sum(dout * N(x)) w.r.t. params (dout: d loss / d N(x))."""
+        if grad is None:
+            grad = torch.empty(NPARAMS, dtype=torch.float32, device=x.device)
+        _check(lib().tomo_convnet_backward(ctypes.byref(self.cube), _dev_f32(params, NPARAMS, "params"),
+                                           _dev_f32(x, self.n, "x"), _dev_f32(dout, self.n, "dout"),
+                                           _dev_f32(grad, NPARAMS, "grad"), c_void_p(self.ws.data_ptr()),
+                                           self.ws.numel(), _stream()))
+        return grad
 
 
 def adam_step(params, grad, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -81,6 +81,22 @@ def test_loss_gradient_matches_oracle(tomo, ora):
         assert np.linalg.norm(gg - rr) <= 5e-2 * np.linalg.norm(rr) + 1e-7, f"tensor {k}"
 
 
+def test_backward_with_given_output_gradient(tomo, ora):
+    """tomo_convnet_backward with an arbitrary d loss / d out against the
+    oracle's back-propagation of the same gradient (same bound as above)."""
+    shape = (9, 14, 21)
+    params = rand_params(11)
+    rng = np.random.default_rng(12)
+    x = rng.normal(size=shape)
+    gout = rng.normal(size=shape)
+    net = tomo.ConvNet(shape)
+    got = unflat(to_host(net.backward(to_dev(flat(params)), to_dev(x), to_dev(gout))))
+    _, acts = ora.convnet_forward(params, x, keep=True)
+    ref = ora.convnet_backward(params, acts, gout)
+    for k, (gg, rr) in enumerate(zip(got, ref)):
+        assert np.linalg.norm(gg - rr) <= 5e-2 * np.linalg.norm(rr) + 1e-7, f"tensor {k}"
+
+
 def test_adam_matches_oracle(tomo, ora):
     import torch
 
