@@ -40,10 +40,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-reps", type=int, default=6,
                     help="full P + P^T passes of the oracle in its timed sample")
-    ap.add_argument("--bp", choices=["auto", "binned", "atomic"], default="auto",
+    ap.add_argument("--bp", choices=["auto", "blocked", "binned", "atomic"], default="auto",
                     help="back-projection strategy")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain time to relative residual 1e-3")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="before the timed steps, run 3 device-to-device copies of MIB MiB: the "
+                         "known-size kernel that calibrates hardware byte counters")
     return ap.parse_args()
 
 
@@ -123,12 +126,20 @@ def main():
     crossings = tomo.count_crossings(dg)
     x = torch.empty(dg.cube_shape, dtype=torch.float32, device="cuda")
 
-    bp = {"auto": tomo.BP_AUTO, "binned": tomo.BP_BINNED, "atomic": tomo.BP_ATOMIC}[args.bp]
+    bp = {"auto": tomo.BP_AUTO, "binned": tomo.BP_BINNED, "atomic": tomo.BP_ATOMIC,
+          "blocked": tomo.BP_BLOCKED}[args.bp]
 
     def step():
         return tomo.cg_solve(dg, y, lam_r=wl.lam_r, max_iter=wl.cg_iters, time_kernels=True, out=x,
                              bp_strategy=bp)
 
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -149,8 +160,10 @@ def main():
     nrays = dg.npix
     bytes_p = 4.0 * crossings + 4.0 * nrays
     bytes_bp = 8.0 * crossings + 4.0 * nrays
+    bp_used = args.bp if args.bp != "auto" else \
+        {1: "atomic", 2: "binned", 3: "blocked"}[tomo.get_tuning()["bp_default"]]
     if ms_bp >= ms_p:
-        dom = "k_backproject_atomic" if args.bp == "atomic" else "k_backproject_binned"
+        dom = f"k_backproject_{bp_used}"
         ms_dom, b_dom = ms_bp, bytes_bp
     else:
         dom, ms_dom, b_dom = "k_project", ms_p, bytes_p
@@ -173,7 +186,7 @@ def main():
                                "iterations, lambda 1e-2",
                    "crossings_per_application": crossings, "applications_per_step": apps,
                    "rays": nrays, "storage": "f32", "walk": "f64",
-                   "final_rel_res": reps[-1]["rel_res"], "backprojection": args.bp},
+                   "final_rel_res": reps[-1]["rel_res"], "backprojection": bp_used},
         "kernels": {"k_project_ms": ms_p, "k_backproject_ms": ms_bp,
                     "project_crossings_per_s": crossings / (ms_p * 1e-3),
                     "backproject_crossings_per_s": crossings / (ms_bp * 1e-3)},

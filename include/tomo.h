@@ -102,7 +102,10 @@ typedef struct tomo_geometry {
 enum {
     TOMO_BP_AUTO = 0,   /* the tuned default for this geometry                  */
     TOMO_BP_ATOMIC = 1, /* one FP32 atomic add per ray/voxel segment            */
-    TOMO_BP_BINNED = 2  /* per-bundle LDS bins, one atomic per voxel per chunk  */
+    TOMO_BP_BINNED = 2, /* per-bundle LDS bins, one atomic per voxel per chunk  */
+    TOMO_BP_BLOCKED = 3 /* each workgroup owns a voxel block and walks every
+                           ray crossing it: LDS bins, one plain store per
+                           voxel, no global atomics, deterministic           */
 };
 
 /*
@@ -117,10 +120,16 @@ int tomo_project(const tomo_geometry *g, const float *cube_d, float *images_d,
 /*
  * Transpose x = M P^T y (or x += M P^T y when accumulate != 0).
  *   images_d: DEVICE float [total pixels]
- *   cube_d:   DEVICE float [nframes][nz][ny][nx]; zeroed first unless
- *             accumulate.  Sums use FP32 atomics: the order of additions,
- *             and so the last bits, may change from run to run.
- *   strategy: TOMO_BP_* (tomo_backproject uses TOMO_BP_AUTO).
+ *   cube_d:   DEVICE float [nframes][nz][ny][nx]; overwritten unless
+ *             accumulate.  TOMO_BP_ATOMIC and TOMO_BP_BINNED add with FP32
+ *             atomics, so the last bits may change from run to run;
+ *             TOMO_BP_BLOCKED gives the same bits every run.  Non-finite
+ *             image values give unspecified (possibly non-finite) results
+ *             in the voxels their rays cross.
+ *   strategy: TOMO_BP_* (tomo_backproject uses TOMO_BP_AUTO).  The blocked
+ *             strategy takes stream-ordered scratch (hipMallocAsync) of
+ *             4 * nviews * 8 bytes plus, when blocks are shared between
+ *             owners, owners * 4 * nframes * nvox bytes.
  */
 int tomo_backproject(const tomo_geometry *g, const float *images_d,
                      float *cube_d, int accumulate, tomo_stream stream);
@@ -160,8 +169,13 @@ int tomo_trace_ray(const tomo_geometry *g, int32_t view, int32_t col,
  *   bp_lds_bins: 64-bit LDS bins per workgroup of the binned
  *     back-projection (512..8192, i.e. 4..64 KiB; larger boxes mean fewer
  *     flushes but fewer resident workgroups).
- *   bp_default: strategy used for TOMO_BP_AUTO (TOMO_BP_BINNED or
- *     TOMO_BP_ATOMIC).
+ *   bp_default: strategy used for TOMO_BP_AUTO (TOMO_BP_BLOCKED,
+ *     TOMO_BP_BINNED or TOMO_BP_ATOMIC).
+ *   bp_block: voxel block (x, y, z) a workgroup of the blocked
+ *     back-projection owns (each 1..64, product <= 8192 64-bit LDS bins).
+ *   bp_splits: owners per block in the blocked back-projection, the block's
+ *     views dealt round-robin (1..64; 0 = chosen from the block count so
+ *     that the launch has about 2048 workgroups).
  * tomo_set_tuning returns TOMO_EINVAL (and changes nothing) for values out
  * of range.  Not synchronised with launches in flight on other threads.
  */
@@ -172,6 +186,8 @@ typedef struct tomo_tuning {
     int32_t bp_xcd_remap;
     int32_t bp_lds_bins;
     int32_t bp_default;
+    int32_t bp_block[3];
+    int32_t bp_splits;
 } tomo_tuning;
 
 int tomo_get_tuning(tomo_tuning *out);
@@ -255,7 +271,7 @@ typedef struct tomo_cg_params {
     int32_t x0_given;      /* 1: x_d holds the starting point; 0: start at 0     */
     double rtol;           /* stop when ||b - A x|| <= rtol ||b|| (0: never)      */
     int32_t check_every;   /* host convergence check period (iterations, >= 1)   */
-    int32_t use_graph;     /* 1: replay iterations from a captured HIP graph     */
+    int32_t use_graph;     /* 1: replay each check interval from a HIP graph     */
     const float *precond;  /* DEVICE convnet parameters, or NULL for plain CG    */
     int32_t fallback_window; /* FCG: restart as plain CG after this many
                                 iterations without a residual decrease (>= 1)   */
@@ -301,6 +317,9 @@ typedef struct tomo_cg_report {
  *   y_d: DEVICE float [total pixels]
  *   x_d: DEVICE float [nframes][nz][ny][nx]: start point if x0_given, and
  *        the solution on return (masked voxels are 0).
+ * use_graph = 1 runs the solve as a batch of one (tomo_batch_cg_solve:
+ * graph-captured iterations, blocked P^T); it cannot be combined with a
+ * preconditioner or recording (TOMO_EUNSUPPORTED).
  * Synchronises the stream.  Returns TOMO_OK when the call ran (the report's
  * status says whether it converged), or an error before/while running.
  */
@@ -311,6 +330,76 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d,
 /* Default parameters: lambda_r 1e-2, max_iter 50, check_every 10,
  * fallback_window 3, min_drop 1e-6, everything else 0 / NULL. */
 void tomo_cg_default_params(tomo_cg_params *p);
+
+/*
+ * Autotuner.  Times, on this geometry with synthetic data, the P wavefront
+ * bundles with and without the XCD remap, and the P^T strategies (blocked
+ * over several block shapes, owner counts and bundles; binned; atomic), each
+ * over `reps` launches after one warm-up, and keeps the fastest P shape and
+ * P^T strategy/shape as the tuning of the geometry's size class: the cube's
+ * largest side, the pixels per view and the view count, each rounded up to
+ * a power of two, and whether the cube has frames.  Later launches on any
+ * geometry of that class use it instead of the process-wide tuning.
+ *   reps: 1..100.  out: HOST, may be NULL.  Synchronises the stream; takes
+ *   stream-ordered scratch of about the cube, the images and the largest
+ *   owner partials.
+ */
+int tomo_autotune(const tomo_geometry *g, int32_t reps, tomo_tuning *out,
+                  tomo_stream stream);
+/* Tuning in effect for g (*tuned = 1 if it comes from the autotuner). */
+int tomo_get_class_tuning(const tomo_geometry *g, tomo_tuning *out,
+                          int32_t *tuned);
+/* Forget every autotuned size class. */
+void tomo_autotune_clear(void);
+
+/*
+ * Batched persistent launches over independent systems (for instance the
+ * time-frame cubes of one time-dependent reconstruction plus independent
+ * reconstructions of other sizes).  One persistent P kernel and one
+ * persistent P^T kernel (owner-computes, as TOMO_BP_BLOCKED) drain device
+ * work queues of (system, view, pixel tile) and (system, frame, voxel
+ * block, owner) items covering every system; each system uses the launch
+ * shape of its size class (tomo_autotune) as it was when the batch was
+ * created, and its results equal the per-system calls with that tuning
+ * (tomo_project; tomo_backproject_ex with TOMO_BP_BLOCKED) bit for bit.
+ *   systems: HOST array of nsystems geometries (1..32); their masks (DEVICE)
+ *   must stay valid while the batch exists, their view arrays need not.
+ * The batch owns its device work queues and scratch: use it from one stream
+ * at a time.  tomo_batch_destroy synchronises the device.
+ */
+typedef struct tomo_batch_s *tomo_batch;
+int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems,
+                      tomo_batch *out);
+void tomo_batch_destroy(tomo_batch b);
+/* images_d[k] = P M cubes_d[k] for every system k (HOST arrays of DEVICE
+ * pointers, laid out as for tomo_project). */
+int tomo_batch_project(tomo_batch b, const float *const *cubes_d,
+                       float *const *images_d, tomo_stream stream);
+/* cubes_d[k] (+)= M P^T images_d[k] for every system k. */
+int tomo_batch_backproject(tomo_batch b, const float *const *images_d,
+                           float *const *cubes_d, int accumulate,
+                           tomo_stream stream);
+/* Writes outside a voxel block's LDS box since the last call (must be 0);
+ * synchronises the device and resets the counter. */
+int tomo_batch_binning_spills(tomo_batch b, int64_t *count_h);
+/* Launch sizes: which 0 = P items, 1 = P^T items, 2 = P workgroups,
+ * 3 = P^T workgroups (resident, persistent); -1 for a NULL batch. */
+int64_t tomo_batch_items(tomo_batch b, int32_t which);
+/*
+ * CG on every system at once (plain CG as tomo_cg_solve; each system has
+ * its own parameters, state, convergence test, true-residual confirmation
+ * and report).  One iteration is one batched P, one batched P^T and three
+ * vector kernels per system; converged systems are skipped on the device.
+ * check_every and use_graph come from params[0]: with use_graph = 1 the
+ * check_every iterations between host checks are captured once as a HIP
+ * graph and replayed.  precond and record_* must be unset
+ * (TOMO_EUNSUPPORTED); bp_strategy is ignored (always blocked).
+ *   y_d, x_d: HOST arrays of DEVICE pointers.  params, reports: HOST arrays
+ *   of nsystems.  Synchronises the stream.
+ */
+int tomo_batch_cg_solve(tomo_batch b, const float *const *y_d,
+                        float *const *x_d, const tomo_cg_params *params,
+                        tomo_cg_report *reports, tomo_stream stream);
 
 /*
  * View from helioprojective TAN WCS keywords (the paper's instrument

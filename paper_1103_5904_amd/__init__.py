@@ -3,8 +3,8 @@ line-of-sight projector P, its exact transpose P^T, and conjugate-gradient
 inversion of (P^T P + lambda D^T D) x = P^T y, as HIP kernels behind the C ABI
 in include/tomo.h.  This package is the thin Python binding."""
 from .tomo import (  # noqa: F401
-    NPARAMS, ConvNet, adam_step,
-    BP_ATOMIC, BP_AUTO, BP_BINNED, DeviceGeometry, TomoError, apply_prior, backproject,
+    NPARAMS, Batch, ConvNet, adam_step, autotune, autotune_clear, class_tuning,
+    BP_ATOMIC, BP_AUTO, BP_BINNED, BP_BLOCKED, DeviceGeometry, TomoError, apply_prior, backproject,
     binning_spills, cg_solve, get_tuning, set_tuning,
     count_crossings, lib, project, status_string, trace_ray, validate, view_from_wcs,
 )

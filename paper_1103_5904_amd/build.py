@@ -12,11 +12,13 @@ CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtomo.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
-SOURCES = ["api.hip", "siddon.hip", "binned.hip", "solver.hip", "convnet.hip"]
+SOURCES = ["api.hip", "siddon.hip", "binned.hip", "blocked.hip", "batch.hip", "tune.hip", "solver.hip",
+           "convnet.hip"]
 
 # The projector's inputs are validated finite, so its min/max need no NaN
 # quieting; the solver keeps IEEE NaN semantics for its non-finite checks.
-EXTRA_FLAGS = {"siddon.hip": ["-fno-honor-nans"], "binned.hip": ["-fno-honor-nans"]}
+EXTRA_FLAGS = {"siddon.hip": ["-fno-honor-nans"], "binned.hip": ["-fno-honor-nans"],
+               "blocked.hip": ["-fno-honor-nans"], "batch.hip": ["-fno-honor-nans"]}
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -19,7 +19,7 @@ static thread_local std::string g_last_error;
 
 // Process-wide launch tuning (see tomo_set_tuning).
 static std::mutex g_tuning_mu;
-static tomo_tuning g_tuning = {2, 1, 3, 1, 4096, TOMO_BP_BINNED};
+static tomo_tuning g_tuning = {2, 1, 3, 1, 4096, TOMO_BP_BINNED, {16, 16, 16}, 0};
 
 tomo_tuning current_tuning()
 {
@@ -171,10 +171,32 @@ static int build_plan(const tomo_geometry *g, int64_t npix, Plan &p)
     p.ntiles = tiles;
     p.npix = npix;
     p.max_steps = c.nx + c.ny + c.nz + 3;
+    p.size_class = size_class_of(g, npix);
     hipError_t e = hipMalloc((void **)&p.views_d, sizeof(ViewDev) * hv.size());
     if (e != hipSuccess) return set_error(TOMO_ENOMEM, "view table allocation: %s", hipGetErrorString(e));
     e = hipMemcpy(p.views_d, hv.data(), sizeof(ViewDev) * hv.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) return hip_fail(e, "view table upload");
+    // views grouped by frame (for owners of a frame's voxel blocks)
+    std::vector<int32_t> fv, foff((size_t)c.nframes + 1, 0);
+    for (int f = 0; f < c.nframes; ++f) {
+        foff[(size_t)f] = (int32_t)fv.size();
+        for (int k = 0; k < g->nviews; ++k)
+            if (g->views[k].frame == f) fv.push_back(k);
+    }
+    foff[(size_t)c.nframes] = (int32_t)fv.size();
+    p.min_frame_views = g->nviews;
+    for (int f = 0; f < c.nframes; ++f) {
+        const int32_t nf = foff[(size_t)f + 1] - foff[(size_t)f];
+        p.min_frame_views = nf < p.min_frame_views ? nf : p.min_frame_views;
+    }
+    if (fv.empty()) fv.push_back(0);
+    e = hipMalloc((void **)&p.frame_views_d, sizeof(int32_t) * fv.size());
+    if (e == hipSuccess) e = hipMalloc((void **)&p.frame_voff_d, sizeof(int32_t) * foff.size());
+    if (e != hipSuccess) return set_error(TOMO_ENOMEM, "frame table allocation: %s", hipGetErrorString(e));
+    e = hipMemcpy(p.frame_views_d, fv.data(), sizeof(int32_t) * fv.size(), hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+        e = hipMemcpy(p.frame_voff_d, foff.data(), sizeof(int32_t) * foff.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "frame table upload");
     e = hipMalloc((void **)&p.spill_d, sizeof(unsigned));
     if (e != hipSuccess) return set_error(TOMO_ENOMEM, "counter allocation: %s", hipGetErrorString(e));
     e = hipMemset(p.spill_d, 0, sizeof(unsigned));
@@ -266,8 +288,16 @@ int tomo_set_tuning(const tomo_tuning *in)
         return set_error(TOMO_EINVAL, "tomo_set_tuning: xcd_remap must be 0 or 1");
     if (in->bp_lds_bins < 512 || in->bp_lds_bins > 8192)
         return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_lds_bins must be in [512, 8192]");
-    if (in->bp_default != TOMO_BP_BINNED && in->bp_default != TOMO_BP_ATOMIC)
-        return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_default must be BINNED or ATOMIC");
+    if (in->bp_default != TOMO_BP_BINNED && in->bp_default != TOMO_BP_ATOMIC &&
+        in->bp_default != TOMO_BP_BLOCKED)
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_default must be BLOCKED, BINNED or ATOMIC");
+    for (int a = 0; a < 3; ++a)
+        if (in->bp_block[a] < 1 || in->bp_block[a] > 64)
+            return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_block entries must be in [1, 64]");
+    if (in->bp_block[0] * in->bp_block[1] * in->bp_block[2] > 8192)
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_block holds more than 8192 voxels");
+    if (in->bp_splits < 0 || in->bp_splits > 64)
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_splits must be in [0, 64]");
     std::lock_guard<std::mutex> lock(g_tuning_mu);
     g_tuning = *in;
     return TOMO_OK;
@@ -300,7 +330,7 @@ int tomo_backproject_ex(const tomo_geometry *g, const float *images_d, float *cu
                         int accumulate, int strategy, tomo_stream stream)
 {
     if (!cube_d || !images_d) return set_error(TOMO_EINVAL, "tomo_backproject: NULL array");
-    if (strategy < TOMO_BP_AUTO || strategy > TOMO_BP_BINNED)
+    if (strategy < TOMO_BP_AUTO || strategy > TOMO_BP_BLOCKED)
         return set_error(TOMO_EINVAL, "tomo_backproject: unknown strategy %d", strategy);
     int st = TOMO_OK;
     PlanRef p = get_plan(g, &st);

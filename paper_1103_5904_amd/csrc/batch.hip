@@ -1,0 +1,373 @@
+// Batched persistent launches over several independent systems (time-frame
+// cubes and independent reconstructions of uneven sizes).
+//
+// * One persistent P kernel and one persistent P^T kernel cover every
+//   system.  Their grids hold as many workgroups as the chip keeps resident;
+//   each workgroup pulls work items - (system, view, 16x16 pixel tile) for P,
+//   (system, frame, voxel block, owner) for the owner-computes P^T - from
+//   device work queues until they are empty, so systems of very different
+//   sizes share the machine without one launch per system and without tail
+//   effects between them.  The item list is cut into eight contiguous
+//   queues, one per XCD: a workgroup drains the queue of its own XCD first
+//   (neighbouring tiles share cube lines in that XCD's L2) and then takes
+//   from the others.  The last workgroup to leave resets the queues, so a
+//   launch needs no host-side clearing and can be captured in a graph.
+// * Each item runs the same device code as the single-geometry launches
+//   (project_tile, blocked_item) with the system's own tuned shape, so a
+//   batched result equals the per-system one bit for bit.
+// * The batched CG keeps one state (scalars, done flag) per system on the
+//   device.  An iteration is one batched P, one batched P^T and three vector
+//   kernels per system; a system that has converged is skipped by every
+//   kernel through its done flag.  With use_graph, the iterations of one
+//   check interval are captured once as a HIP graph and replayed.
+#include <math.h>
+#include <stddef.h>
+#include <string.h>
+
+#include <vector>
+
+#include "batch.h"
+#include "blocked.h"
+
+namespace tomo {
+
+// Next item for this workgroup (thread 0), or -1 when every queue is empty.
+__device__ inline int64_t next_item(unsigned long long *q, int64_t total, int &visited)
+{
+    const int home = (int)(blockIdx.x % kQueues);
+    while (visited < kQueues) {
+        const int qx = (home + visited) % kQueues;
+        const int64_t lo = total * qx / kQueues, hi = total * (qx + 1) / kQueues;
+        const unsigned long long k = atomicAdd(&q[qx], 1ull);
+        if ((int64_t)k < hi - lo) return lo + (int64_t)k;
+        ++visited;
+    }
+    return -1;
+}
+
+// The last workgroup out clears the queues for the next launch.
+__device__ inline void leave_queues(unsigned long long *q)
+{
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned long long prev = atomicAdd(&q[kQueues], 1ull);
+        if (prev == gridDim.x - 1) {
+            for (int k = 0; k <= kQueues; ++k) atomicExch(&q[k], 0ull);
+            __threadfence();
+        }
+    }
+}
+
+// Largest k with begin(k) <= t (begin ascending, begin(0) == 0).
+template <class F>
+__device__ inline int find_system(int nsys, int64_t t, F begin)
+{
+    int lo = 0, hi = nsys - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (begin(mid) <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_project(const SysDev *__restrict__ sys, int32_t nsys,
+                                                            Operands ops, int64_t ntiles,
+                                                            unsigned long long *q)
+{
+    __shared__ int64_t s_item;
+    int visited = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = next_item(q, ntiles, visited);
+        __syncthreads();
+        const int64_t t = s_item;
+        __syncthreads();
+        if (t < 0) break;
+        const int k = find_system(nsys, t, [&](int i) { return sys[i].tile_begin; });
+        if (ops.done[k] && *ops.done[k]) continue;
+        const SysDev &sd = sys[k];
+        const int64_t lt = t - sd.tile_begin;
+        const bool mm = ops.map && sd.map_mask, dm = sd.data_mask != nullptr;
+        if (mm && dm)
+            project_tile<true, true>(sd.grid, sd.views, sd.nviews, sd.p_log2_bw, lt, sd.maxit, ops.src[k],
+                                     sd.map_mask, sd.data_mask, ops.dst[k]);
+        else if (mm)
+            project_tile<true, false>(sd.grid, sd.views, sd.nviews, sd.p_log2_bw, lt, sd.maxit, ops.src[k],
+                                      sd.map_mask, sd.data_mask, ops.dst[k]);
+        else if (dm)
+            project_tile<false, true>(sd.grid, sd.views, sd.nviews, sd.p_log2_bw, lt, sd.maxit, ops.src[k],
+                                      sd.map_mask, sd.data_mask, ops.dst[k]);
+        else
+            project_tile<false, false>(sd.grid, sd.views, sd.nviews, sd.p_log2_bw, lt, sd.maxit, ops.src[k],
+                                       sd.map_mask, sd.data_mask, ops.dst[k]);
+    }
+    leave_queues(q);
+}
+
+// max |y| per view share for every view of every system.
+__global__ __launch_bounds__(kThreads) void k_batch_absmax(const SysDev *__restrict__ sys, int32_t nsys,
+                                                           Operands ops, uint32_t *__restrict__ ymax)
+{
+    __shared__ uint32_t red[kThreads / 64];
+    const int gv = blockIdx.x / kYmaxParts, part = blockIdx.x % kYmaxParts;
+    const int k = find_system(nsys, gv, [&](int i) { return (int64_t)sys[i].view_begin; });
+    if (ops.done[k] && *ops.done[k]) return;
+    const SysDev &sd = sys[k];
+    const ViewDev &v = sd.views[gv - sd.view_begin];
+    const uint32_t m = sd.data_mask ? view_absmax_part<true>(v, part, ops.src[k], sd.data_mask, red)
+                                    : view_absmax_part<false>(v, part, ops.src[k], sd.data_mask, red);
+    if (threadIdx.x == 0) ymax[blockIdx.x] = m;
+}
+
+__global__ __launch_bounds__(kThreads) void k_batch_backproject(const SysDev *__restrict__ sys, int32_t nsys,
+                                                                Operands ops, int64_t nitems,
+                                                                const uint32_t *__restrict__ ymax,
+                                                                unsigned long long *q,
+                                                                unsigned *__restrict__ spill)
+{
+    extern __shared__ unsigned long long bins[];
+    __shared__ BlockedShared sh;
+    __shared__ int64_t s_item;
+    int visited = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_item = next_item(q, nitems, visited);
+        __syncthreads();
+        const int64_t t = s_item;
+        __syncthreads();
+        if (t < 0) break;
+        const int k = find_system(nsys, t, [&](int i) { return sys[i].item_begin; });
+        if (ops.done[k] && *ops.done[k]) continue;
+        const SysDev &sd = sys[k];
+        const int64_t li = t - sd.item_begin;
+        float *out = sd.bd.splits == 1 ? ops.dst[k] : sd.part;
+        const uint32_t *ym = ymax + (int64_t)sd.view_begin * kYmaxParts;
+        const bool mm = ops.map && sd.map_mask, dm = sd.data_mask != nullptr;
+        if (mm && dm)
+            blocked_item<true, true>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, sd.bp_log2_bw, li,
+                                     ops.src[k], sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh);
+        else if (mm)
+            blocked_item<true, false>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, sd.bp_log2_bw, li,
+                                      ops.src[k], sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh);
+        else if (dm)
+            blocked_item<false, true>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, sd.bp_log2_bw, li,
+                                      ops.src[k], sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh);
+        else
+            blocked_item<false, false>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, sd.bp_log2_bw, li,
+                                       ops.src[k], sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh);
+    }
+    leave_queues(q);
+}
+
+// Systems whose blocks have several owners: dst = M (sum of the owners'
+// partials, in owner order) (+ dst).
+__global__ __launch_bounds__(kThreads) void k_batch_sum_owners(const SysDev *__restrict__ sys, int32_t nsys,
+                                                               Operands ops)
+{
+    for (int k = 0; k < nsys; ++k) {
+        const SysDev &sd = sys[k];
+        if (sd.bd.splits <= 1 || (ops.done[k] && *ops.done[k])) continue;
+        float *dst = ops.dst[k];
+        const bool mm = ops.map && sd.map_mask;
+        for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < sd.ntot;
+             i += (int64_t)gridDim.x * kThreads) {
+            float s = 0.0f;
+            for (int o = 0; o < sd.bd.splits; ++o) s += sd.part[(int64_t)o * sd.ntot + i];
+            if (mm && !sd.map_mask[i % sd.grid.nvox]) s = 0.0f;
+            dst[i] = ops.acc ? dst[i] + s : s;
+        }
+    }
+}
+
+}  // namespace tomo
+
+using namespace tomo;
+
+
+tomo_batch_s::~tomo_batch_s()
+{
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    (void)hipDeviceSynchronize();
+    if (sys_d) (void)hipFree(sys_d);
+    if (q) (void)hipFree(q);
+    if (ymax) (void)hipFree(ymax);
+    if (part) (void)hipFree(part);
+    if (spill) (void)hipFree(spill);
+    (void)hipSetDevice(cur);
+}
+
+namespace tomo {
+
+int batch_project_ops(tomo_batch b, const Operands &ops, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_project, dim3(b->grid_p), dim3(kThreads), 0, s, b->sys_d, b->nsys, ops,
+                       b->ntiles, b->q);
+    return hip_fail(hipGetLastError(), "batched projection launch");
+}
+
+int batch_backproject_ops(tomo_batch b, const Operands &ops, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_absmax, dim3((unsigned)(b->nviews * kYmaxParts)), dim3(kThreads), 0, s,
+                       b->sys_d, b->nsys, ops, b->ymax);
+    hipLaunchKernelGGL(k_batch_backproject, dim3(b->grid_b), dim3(kThreads), b->lds_bytes, s, b->sys_d,
+                       b->nsys, ops, b->nitems, b->ymax, b->q + (kQueues + 1), b->spill);
+    bool owners = false;
+    for (const auto &sd : b->sys_h) owners = owners || sd.bd.splits > 1;
+    if (owners) {
+        int64_t most = 0;
+        for (const auto &sd : b->sys_h) most = sd.ntot > most ? sd.ntot : most;
+        int64_t nb = (most + kThreads - 1) / kThreads;
+        nb = nb > 2048 ? 2048 : (nb < 1 ? 1 : nb);
+        hipLaunchKernelGGL(k_batch_sum_owners, dim3((unsigned)nb), dim3(kThreads), 0, s, b->sys_d, b->nsys, ops);
+    }
+    return hip_fail(hipGetLastError(), "batched back-projection launch");
+}
+
+}  // namespace tomo
+
+extern "C" {
+
+int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch *out)
+{
+    if (!out) return set_error(TOMO_EINVAL, "tomo_batch_create: out is NULL");
+    *out = nullptr;
+    if (!systems || nsystems < 1 || nsystems > kMaxSys)
+        return set_error(TOMO_EINVAL, "tomo_batch_create: 1 to %d systems", kMaxSys);
+    auto b = new (std::nothrow) tomo_batch_s;
+    if (!b) return set_error(TOMO_ENOMEM, "tomo_batch_create: host allocation failed");
+    (void)hipGetDevice(&b->device);
+    b->nsys = nsystems;
+    int64_t part_floats = 0;
+    for (int k = 0; k < nsystems; ++k) {
+        int st = TOMO_OK;
+        PlanRef p = get_plan(&systems[k], &st);
+        if (!p) {
+            delete b;
+            return st;
+        }
+        const tomo_tuning tu = tuning_for(*p);
+        const BlockedShape bs = blocked_shape(*p, tu);
+        SysDev sd;
+        memset(&sd, 0, sizeof(sd));
+        sd.grid = p->grid;
+        sd.views = p->views_d;
+        sd.frame_views = p->frame_views_d;
+        sd.frame_voff = p->frame_voff_d;
+        sd.map_mask = systems[k].map_mask;
+        sd.data_mask = systems[k].data_mask;
+        for (int a = 0; a < 3; ++a) {
+            sd.bd.b[a] = bs.b[a];
+            sd.bd.nb[a] = bs.nb[a];
+        }
+        sd.bd.splits = bs.splits;
+        sd.bd.maxit = bs.b[0] + bs.b[1] + bs.b[2] + 3;
+        sd.nviews = p->nviews;
+        sd.p_log2_bw = tu.p_bundle;
+        sd.bp_log2_bw = tu.bp_bundle;
+        sd.maxit = p->max_steps;
+        sd.view_begin = b->nviews;
+        sd.tile_begin = b->ntiles;
+        sd.item_begin = b->nitems;
+        sd.ntot = p->grid.nvox * p->grid.nframes;
+        b->ntiles += p->ntiles;
+        b->nitems += bs.items;
+        b->nviews += p->nviews;
+        if (bs.splits > 1) part_floats += (int64_t)bs.splits * sd.ntot;
+        const size_t lds = sizeof(unsigned long long) * (size_t)bs.b[0] * bs.b[1] * bs.b[2];
+        b->lds_bytes = lds > b->lds_bytes ? lds : b->lds_bytes;
+        b->plans.push_back(p);
+        b->geoms.push_back(systems[k]);
+        b->sys_h.push_back(sd);
+    }
+    if (b->ntiles >= ((int64_t)1 << 40) || b->nitems >= ((int64_t)1 << 40)) {
+        delete b;
+        return set_error(TOMO_EINVAL, "tomo_batch_create: too much work for one batch");
+    }
+    hipError_t e = hipMalloc((void **)&b->q, sizeof(unsigned long long) * 2 * (kQueues + 1));
+    if (e == hipSuccess) e = hipMemset(b->q, 0, sizeof(unsigned long long) * 2 * (kQueues + 1));
+    if (e == hipSuccess) e = hipMalloc((void **)&b->ymax, sizeof(uint32_t) * (size_t)b->nviews * kYmaxParts);
+    if (e == hipSuccess) e = hipMalloc((void **)&b->spill, sizeof(unsigned));
+    if (e == hipSuccess) e = hipMemset(b->spill, 0, sizeof(unsigned));
+    if (e == hipSuccess && part_floats > 0) e = hipMalloc((void **)&b->part, sizeof(float) * (size_t)part_floats);
+    if (e != hipSuccess) {
+        delete b;
+        return set_error(TOMO_ENOMEM, "tomo_batch_create: device allocation failed (%s)", hipGetErrorString(e));
+    }
+    int64_t off = 0;
+    for (auto &sd : b->sys_h)
+        if (sd.bd.splits > 1) {
+            sd.part = b->part + off;
+            off += (int64_t)sd.bd.splits * sd.ntot;
+        }
+    e = hipMalloc((void **)&b->sys_d, sizeof(SysDev) * b->sys_h.size());
+    if (e == hipSuccess) e = hipMemcpy(b->sys_d, b->sys_h.data(), sizeof(SysDev) * b->sys_h.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        delete b;
+        return set_error(TOMO_ENOMEM, "tomo_batch_create: system table upload failed (%s)", hipGetErrorString(e));
+    }
+    // persistent grids: as many workgroups as stay resident, at most one per item
+    int cus = 0, per_p = 0, per_b = 0;
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_p, k_batch_project, kThreads, 0);
+    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_b, k_batch_backproject, kThreads, b->lds_bytes);
+    cus = cus > 0 ? cus : 256;
+    per_p = per_p > 0 ? per_p : 1;
+    per_b = per_b > 0 ? per_b : 1;
+    const int64_t gp = (int64_t)cus * per_p, gb = (int64_t)cus * per_b;
+    b->grid_p = (unsigned)(gp < b->ntiles ? gp : (b->ntiles > 0 ? b->ntiles : 1));
+    b->grid_b = (unsigned)(gb < b->nitems ? gb : (b->nitems > 0 ? b->nitems : 1));
+    *out = b;
+    return TOMO_OK;
+}
+
+void tomo_batch_destroy(tomo_batch b) { delete b; }
+
+int tomo_batch_project(tomo_batch b, const float *const *cubes_d, float *const *images_d, tomo_stream stream)
+{
+    if (!b || !cubes_d || !images_d) return set_error(TOMO_EINVAL, "tomo_batch_project: NULL argument");
+    Operands ops;
+    memset(&ops, 0, sizeof(ops));
+    for (int k = 0; k < b->nsys; ++k) {
+        if (!cubes_d[k] || !images_d[k]) return set_error(TOMO_EINVAL, "tomo_batch_project: NULL array");
+        ops.src[k] = cubes_d[k];
+        ops.dst[k] = images_d[k];
+    }
+    ops.map = 1;
+    return batch_project_ops(b, ops, (hipStream_t)stream);
+}
+
+int tomo_batch_backproject(tomo_batch b, const float *const *images_d, float *const *cubes_d, int accumulate,
+                           tomo_stream stream)
+{
+    if (!b || !cubes_d || !images_d) return set_error(TOMO_EINVAL, "tomo_batch_backproject: NULL argument");
+    Operands ops;
+    memset(&ops, 0, sizeof(ops));
+    for (int k = 0; k < b->nsys; ++k) {
+        if (!cubes_d[k] || !images_d[k]) return set_error(TOMO_EINVAL, "tomo_batch_backproject: NULL array");
+        ops.src[k] = images_d[k];
+        ops.dst[k] = cubes_d[k];
+    }
+    ops.map = 1;
+    ops.acc = accumulate ? 1 : 0;
+    return batch_backproject_ops(b, ops, (hipStream_t)stream);
+}
+
+int tomo_batch_binning_spills(tomo_batch b, int64_t *count_h)
+{
+    if (!b || !count_h) return set_error(TOMO_EINVAL, "tomo_batch_binning_spills: NULL argument");
+    unsigned h = 0;
+    int rc = hip_fail(hipDeviceSynchronize(), "synchronise");
+    if (!rc) rc = hip_fail(hipMemcpy(&h, b->spill, sizeof(h), hipMemcpyDeviceToHost), "copy counter");
+    if (!rc) rc = hip_fail(hipMemset(b->spill, 0, sizeof(unsigned)), "reset counter");
+    if (!rc) *count_h = (int64_t)h;
+    return rc;
+}
+
+int64_t tomo_batch_items(tomo_batch b, int32_t which)
+{
+    if (!b) return -1;
+    return which == 0 ? b->ntiles : (which == 1 ? b->nitems : (which == 2 ? b->grid_p : b->grid_b));
+}
+
+}  // extern "C"

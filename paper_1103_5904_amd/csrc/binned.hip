@@ -290,9 +290,9 @@ __global__ __launch_bounds__(kThreads) void k_backproject_binned(
 }
 
 int launch_backproject_binned(const Plan &p, const tomo_geometry *g, const float *images,
-                              float *cube, bool use_map_mask, hipStream_t s, const int *done_flag)
+                              float *cube, bool use_map_mask, hipStream_t s, const int *done_flag,
+                              const tomo_tuning &tu)
 {
-    const tomo_tuning tu = current_tuning();
     const Bundle b{tu.bp_bundle, tu.bp_xcd_remap};
     const int cap = tu.bp_lds_bins;
     const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;

@@ -1,0 +1,256 @@
+// Device code of the owner-computes P^T shared by its single-geometry
+// launch (blocked.hip) and the batched persistent launch (batch.hip).
+#pragma once
+
+#include "walk.h"
+
+namespace tomo {
+
+constexpr int kYmaxParts = 8;  // partial maxima per view
+
+// max |y| over the share `part` of view v's unmasked pixels, as an FP32 bit
+// pattern (bit patterns of magnitudes order like the magnitudes; anything
+// >= 0x7f800000 is non-finite).  Valid in thread 0.
+template <bool kDataMask>
+__device__ inline uint32_t view_absmax_part(const ViewDev &v, int part, const float *__restrict__ images,
+                                            const uint8_t *__restrict__ data_mask, uint32_t *red /* LDS [4] */)
+{
+    const int64_t np = (int64_t)v.ncol * v.nrow;
+    uint32_t m = 0u;
+    for (int64_t i = (int64_t)part * kThreads + threadIdx.x; i < np; i += (int64_t)kYmaxParts * kThreads) {
+        const int64_t pix = v.pix_off + i;
+        const uint32_t b = __builtin_bit_cast(uint32_t, images[pix]) & 0x7fffffffu;
+        if (!kDataMask || data_mask[pix]) m = b > m ? b : m;
+    }
+    for (int o = 32; o > 0; o >>= 1) {
+        const uint32_t t = (uint32_t)__shfl_down((int)m, o, 64);
+        m = t > m ? t : m;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    uint32_t r = 0u;
+    if (threadIdx.x == 0) {
+        r = red[0];
+        for (int k = 1; k < kThreads / 64; ++k) r = red[k] > r ? red[k] : r;
+    }
+    __syncthreads();
+    return r;
+}
+
+// Offsets (dc, dr) of this lane's pixel inside a 16x16 pixel tile, by the
+// same wave bundles as the tile kernels.
+__device__ inline void tile_lane(int log2_bw, int &dc, int &dr)
+{
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (log2_bw == 0) {
+        dc = (l & 7) * 2 + (w & 1);
+        dr = (l >> 3) * 2 + (w >> 1);
+        return;
+    }
+    const int bw = 1 << log2_bw, bh = 64 >> log2_bw, wpr = kTile >> log2_bw;
+    dc = (w % wpr) * bw + (l & (bw - 1));
+    dr = (w / wpr) * bh + (l >> log2_bw);
+}
+
+// Shared-memory scratch of one item besides the bins.
+struct BlockedShared {
+    double cc[8], cr[8];  // detector coordinates of the block's corners
+    int bad;              // a corner lies behind the observer
+};
+
+// One owner item of the blocked P^T: (frame, block, split) from the item
+// index, every ray of the owner's views that can cross the block walked
+// inside it, and the block written once.  bins: nbins 64-bit LDS words.
+// Called by all threads of the workgroup.
+template <bool kMapMask, bool kDataMask>
+__device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict__ views,
+                                    const int32_t *__restrict__ frame_views,
+                                    const int32_t *__restrict__ frame_voff, const BlockDev &bd,
+                                    int log2_bw, int64_t item, const float *__restrict__ images,
+                                    const uint8_t *__restrict__ map_mask,
+                                    const uint8_t *__restrict__ data_mask,
+                                    const uint32_t *__restrict__ ymax_parts, float *__restrict__ out,
+                                    int32_t accumulate, unsigned *__restrict__ spill,
+                                    unsigned long long *bins, BlockedShared &sh)
+{
+    // ---- item -> (frame, block, split)
+    const int64_t nblk = (int64_t)bd.nb[0] * bd.nb[1] * bd.nb[2];
+    const int split = (int)(item % bd.splits);
+    const int64_t fb = item / bd.splits;
+    const int frame = (int)(fb / nblk);
+    const int64_t blk = fb % nblk;
+    const int bi = (int)(blk % bd.nb[0]), bj = (int)((blk / bd.nb[0]) % bd.nb[1]),
+              bk = (int)(blk / ((int64_t)bd.nb[0] * bd.nb[1]));
+    const int blo[3] = {bi * bd.b[0], bj * bd.b[1], bk * bd.b[2]};
+    const int bhi[3] = {min(blo[0] + bd.b[0], g.n[0]), min(blo[1] + bd.b[1], g.n[1]),
+                        min(blo[2] + bd.b[2], g.n[2])};
+    const int nbins = bd.b[0] * bd.b[1] * bd.b[2];
+    const int32_t lstride[3] = {1, bd.b[0], bd.b[0] * bd.b[1]};
+
+    const int v0 = frame_voff[frame], v1 = frame_voff[frame + 1];
+
+    // ---- fixed-point scale from the views this owner handles (uniform)
+    uint32_t ybits = 0u;
+    double rays = 0.0;
+    for (int k = v0 + split; k < v1; k += bd.splits) {
+        const int vi = frame_views[k];
+        for (int p = 0; p < kYmaxParts; ++p) {
+            const uint32_t b = ymax_parts[vi * kYmaxParts + p];
+            ybits = b > ybits ? b : ybits;
+        }
+        rays += (double)views[vi].ncol * (double)views[vi].nrow;
+    }
+    const bool finite = ybits < 0x7f800000u;
+    const double ymax = (double)__builtin_bit_cast(float, ybits);
+    const double vdiag = sqrt(g.delta[0] * g.delta[0] + g.delta[1] * g.delta[1] + g.delta[2] * g.delta[2]);
+    int eb = 0;
+    (void)frexp(fmax(rays, 1.0) * vdiag * ymax * 1.0000001, &eb);  // bound on any bin < 2^eb
+    const double fx_scale = ldexp(1.0, 61 - eb), fx_inv = ldexp(1.0, eb - 61);
+    float *fbins = reinterpret_cast<float *>(bins);
+
+    __syncthreads();  // the previous item of this workgroup is done with the bins
+    for (int i = threadIdx.x; i < nbins; i += kThreads) bins[i] = 0ull;
+
+    int dc = 0, dr = 0;
+    tile_lane(log2_bw, dc, dr);
+    for (int k = v0 + split; k < v1; k += bd.splits) {
+        const ViewDev &v = views[frame_views[k]];
+        // ---- footprint of the block on this view's detector
+        __syncthreads();  // previous view's rectangle no longer in use
+        if (threadIdx.x == 0) sh.bad = 0;
+        __syncthreads();
+        if (threadIdx.x < 8) {
+            const int c = threadIdx.x;
+            const int ci[3] = {(c & 1) ? bhi[0] : blo[0], (c & 2) ? bhi[1] : blo[1], (c & 4) ? bhi[2] : blo[2]};
+            double d[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) d[a] = g.lo[a] + (double)ci[a] * g.delta[a] - v.o[a];
+            const double dep = d[0] * v.w[0] + d[1] * v.w[1] + d[2] * v.w[2];
+            const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+            if (!(dep > 1e-6 * nd)) {
+                atomicOr(&sh.bad, 1);
+                sh.cc[c] = sh.cr[c] = 0.0;
+            } else {
+                const double x = (d[0] * v.u[0] + d[1] * v.u[1] + d[2] * v.u[2]) / dep;
+                const double y = (d[0] * v.v[0] + d[1] * v.v[1] + d[2] * v.v[2]) / dep;
+                sh.cc[c] = v.cp[0] + x / v.cd[0];
+                sh.cr[c] = v.cp[1] + y / v.cd[1];
+            }
+        }
+        __syncthreads();
+        int c0 = 0, c1 = v.ncol - 1, r0 = 0, r1 = v.nrow - 1;
+        if (!sh.bad) {
+            double cmn = sh.cc[0], cmx = sh.cc[0], rmn = sh.cr[0], rmx = sh.cr[0];
+#pragma unroll
+            for (int c = 1; c < 8; ++c) {
+                cmn = fmin(cmn, sh.cc[c]);
+                cmx = fmax(cmx, sh.cc[c]);
+                rmn = fmin(rmn, sh.cr[c]);
+                rmx = fmax(rmx, sh.cr[c]);
+            }
+            // clamp in double before converting: far-off corners stay finite
+            c0 = (int)fmax(floor(cmn) - 1.0, 0.0);
+            c1 = (int)fmin(ceil(cmx) + 1.0, (double)(v.ncol - 1));
+            r0 = (int)fmax(floor(rmn) - 1.0, 0.0);
+            r1 = (int)fmin(ceil(rmx) + 1.0, (double)(v.nrow - 1));
+        }
+        if (c0 > c1 || r0 > r1) continue;  // uniform
+
+        // ---- rays of the rectangle, a 16x16 tile per pass
+        const int tx = (c1 - c0) / kTile + 1, ty = (r1 - r0) / kTile + 1;
+        for (int t = 0; t < tx * ty; ++t) {
+            const int col = c0 + (t % tx) * kTile + dc, row = r0 + (t / tx) * kTile + dr;
+            if (col > c1 || row > r1) continue;
+            const int64_t pix = v.pix_off + (int64_t)row * v.ncol + col;
+            const float yv = images[pix];
+            if (!nonzero_bits(yv) || (kDataMask && !data_mask[pix])) continue;
+            RayState r;
+            RayAxes ax;
+            if (!ray_setup(g, v, col, row, r, &ax)) continue;
+            // parameter interval [E, X) inside the block, exact on the ray's grid
+            double E = 0.0, X = r.send;
+            bool hit = true;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                if (r.ds[a] == 0.0) {  // index constant along the ray
+                    hit = hit && ax.idx[a] >= blo[a] && ax.idx[a] < bhi[a];
+                    continue;
+                }
+                const bool up = r.st[a] > 0;
+                const int J = up ? blo[a] - ax.idx[a] : ax.idx[a] - (bhi[a] - 1);  // crossings to enter
+                const int K = up ? bhi[a] - ax.idx[a] : ax.idx[a] - blo[a] + 1;    // crossings to leave
+                hit = hit && K > 0;
+                if (J > 0) E = fmax(E, r.s[a] + (double)(J - 1) * r.ds[a]);
+                X = fmin(X, r.s[a] + (double)(K - 1) * r.ds[a]);
+            }
+            if (!hit || !(X > E)) continue;
+            // walk state at E: crossings with parameter <= E are done
+            int32_t loc = 0;
+            int32_t lst[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                int idx = ax.idx[a];
+                if (r.ds[a] != 0.0) {
+                    int j = 0;
+                    if (E >= r.s[a]) {
+                        // the quotient is within one of the count; settle it
+                        // with exact comparisons on the grid
+                        j = max((int)floor((E - r.s[a]) / r.ds[a]) + 1, 1);
+#pragma unroll
+                        for (int fix = 0; fix < 2; ++fix) {
+                            j -= (j > 1 && r.s[a] + (double)(j - 1) * r.ds[a] > E) ? 1 : 0;
+                            j += (r.s[a] + (double)j * r.ds[a] <= E) ? 1 : 0;
+                        }
+                    }
+                    r.s[a] += (double)j * r.ds[a];
+                    idx += r.st[a] > 0 ? j : -j;
+                    lst[a] = r.st[a] > 0 ? lstride[a] : -lstride[a];
+                } else {
+                    lst[a] = 0;
+                }
+                loc += (idx - blo[a]) * lstride[a];
+            }
+            const double wys = (double)yv * r.dn * (finite ? fx_scale : 1.0);
+            double scur = E;
+            for (int it = 0; it < bd.maxit; ++it) {
+                const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
+                if ((uint32_t)loc < (uint32_t)nbins) {
+                    if (finite) atomicAdd(&bins[loc], (unsigned long long)(long long)rint((m - scur) * wys));
+                    else atomicAdd(&fbins[loc], (float)((m - scur) * wys));
+                } else {
+                    atomicAdd(spill, 1u);
+                }
+                if (m >= X) break;
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const bool tie = (r.s[a] == m);
+                    r.s[a] += tie ? r.ds[a] : 0.0;
+                    loc += tie ? lst[a] : 0;
+                }
+                scur = m;
+            }
+        }
+    }
+    __syncthreads();
+
+    // ---- write the block once
+    const int ex = bhi[0] - blo[0], ey = bhi[1] - blo[1], ez = bhi[2] - blo[2];
+    const int nin = ex * ey * ez;
+    const int64_t fbase = (int64_t)frame * g.nvox;
+    const int64_t total = g.nvox * g.nframes;
+    for (int e = threadIdx.x; e < nin; e += kThreads) {
+        const int lx = e % ex, ly = (e / ex) % ey, lz = e / (ex * ey);
+        const int l = (lz * bd.b[1] + ly) * bd.b[0] + lx;
+        const float val = finite ? (float)((double)(long long)bins[l] * fx_inv) : fbins[l];
+        const int64_t off = ((int64_t)(blo[2] + lz) * g.n[1] + (blo[1] + ly)) * g.n[0] + (blo[0] + lx);
+        if (bd.splits == 1) {
+            float o = (!kMapMask || map_mask[off]) ? val : 0.0f;
+            if (accumulate) o += out[fbase + off];
+            out[fbase + off] = o;
+        } else {
+            out[(int64_t)split * total + fbase + off] = val;
+        }
+    }
+}
+
+}  // namespace tomo

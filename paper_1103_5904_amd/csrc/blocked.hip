@@ -1,0 +1,174 @@
+// Owner-computes transpose P^T for gfx950 (TOMO_BP_BLOCKED).
+//
+// On MI355X a device-scope FP32 atomic to global memory is performed past
+// the XCD's L2 and costs a memory transaction of its own, so any P^T that
+// adds into the cube with atomics is bound by the number of atomics, not by
+// its walk.  Here the cube is cut into blocks of bx x by x bz voxels and each
+// workgroup owns one block (optionally one share of the block's views, see
+// below):
+//
+// * For every view, the pixels whose rays can cross the block lie in the
+//   bounding rectangle of the block's eight corners projected through the
+//   pinhole (plus one pixel of margin); corners behind the observer widen it
+//   to the whole detector.
+// * Each lane takes one of those rays, sets it up exactly as P does and
+//   walks only its part inside the block.  The walk's crossing parameters
+//   live on a power-of-two grid on which every sum the walk forms is exact:
+//   the k-th crossing of axis a is s_a + k ds_a whatever the order of
+//   additions.  So the parameter interval [E, X) in which the ray is inside
+//   the block and the walk state at E (crossings done on each axis, current
+//   voxel) follow in closed form from integers, and the in-block walk
+//   reproduces P's segments bit for bit: the matrix stays the transpose of
+//   P's.
+// * Contributions go to 64-bit fixed-point LDS bins (integer LDS atomics;
+//   sums are exact and order-independent).  The scale is a power of two from
+//   the largest |y| of the views involved and the number of their pixels, a
+//   bound on the rays that can reach one voxel, so no bin can overflow.
+//   Items whose views hold a non-finite value accumulate in FP32 LDS bins
+//   instead.
+// * At the end the block is written once with plain stores: the cube itself
+//   (map mask and accumulate applied) when the block has one owner, else the
+//   owner's slice of a partial buffer [splits][frames * nvox] that a second
+//   kernel sums in a fixed order.  No global atomics anywhere, and the
+//   result is deterministic.
+#include <limits.h>
+
+#include "blocked.h"
+
+namespace tomo {
+
+template <bool kDataMask>
+__global__ __launch_bounds__(kThreads) void k_view_absmax(const ViewDev *__restrict__ views,
+                                                          const float *__restrict__ images,
+                                                          const uint8_t *__restrict__ data_mask,
+                                                          uint32_t *__restrict__ ymax,
+                                                          const int *__restrict__ done_flag)
+{
+    __shared__ uint32_t red[kThreads / 64];
+    if (done_flag && *done_flag) return;
+    const int vi = blockIdx.x / kYmaxParts, part = blockIdx.x % kYmaxParts;
+    const uint32_t m = view_absmax_part<kDataMask>(views[vi], part, images, data_mask, red);
+    if (threadIdx.x == 0) ymax[blockIdx.x] = m;
+}
+
+template <bool kMapMask, bool kDataMask>
+__global__ __launch_bounds__(kThreads) void k_backproject_blocked(
+    GridDev g, const ViewDev *__restrict__ views, const int32_t *__restrict__ frame_views,
+    const int32_t *__restrict__ frame_voff, BlockDev bd, Bundle bun, const float *__restrict__ images,
+    const uint8_t *__restrict__ map_mask, const uint8_t *__restrict__ data_mask,
+    const uint32_t *__restrict__ ymax_parts, float *__restrict__ out, int32_t accumulate,
+    const int *__restrict__ done_flag, unsigned *__restrict__ spill)
+{
+    extern __shared__ unsigned long long bins[];  // bx*by*bz fixed-point (or FP32) sums
+    __shared__ BlockedShared sh;
+    if (done_flag && *done_flag) return;
+    const int64_t nitems = (int64_t)bd.nb[0] * bd.nb[1] * bd.nb[2] * g.nframes * bd.splits;
+    const int64_t item = bun.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    if (item >= nitems) return;
+    blocked_item<kMapMask, kDataMask>(g, views, frame_views, frame_voff, bd, bun.log2_bw, item, images,
+                                      map_mask, data_mask, ymax_parts, out, accumulate, spill, bins, sh);
+}
+
+// out[i] = M (sum over owners of part[s][i]) (+ out[i]), owners in order.
+template <bool kMapMask>
+__global__ __launch_bounds__(kThreads) void k_sum_owners(const float *__restrict__ part, int32_t splits,
+                                                         int64_t total, int64_t nvox,
+                                                         const uint8_t *__restrict__ map_mask,
+                                                         float *__restrict__ out, int32_t accumulate,
+                                                         const int *__restrict__ done_flag)
+{
+    if (done_flag && *done_flag) return;
+    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < total;
+         i += (int64_t)gridDim.x * kThreads) {
+        float s = 0.0f;
+        for (int k = 0; k < splits; ++k) s += part[(int64_t)k * total + i];
+        if (kMapMask && !map_mask[i % nvox]) s = 0.0f;
+        out[i] = accumulate ? out[i] + s : s;
+    }
+}
+
+BlockedShape blocked_shape(const Plan &p, const tomo_tuning &tu)
+{
+    BlockedShape bs;
+    bs.b[0] = tu.bp_block[0];
+    bs.b[1] = tu.bp_block[1];
+    bs.b[2] = tu.bp_block[2];
+    int64_t nblk = 1;
+    for (int a = 0; a < 3; ++a) {
+        bs.nb[a] = (p.grid.n[a] + bs.b[a] - 1) / bs.b[a];
+        nblk *= bs.nb[a];
+    }
+    nblk *= p.grid.nframes;
+    int s = tu.bp_splits;
+    if (s <= 0) {  // enough owners for ~8 workgroups per CU
+        const int64_t want = 2048;
+        s = (int)((want + nblk - 1) / nblk);
+        s = s < 1 ? 1 : (s > 8 ? 8 : s);
+    }
+    if (s > p.min_frame_views && p.min_frame_views >= 1) s = p.min_frame_views;
+    bs.splits = s < 1 ? 1 : s;
+    bs.items = nblk * bs.splits;
+    return bs;
+}
+
+size_t blocked_scratch_bytes(const Plan &p, const BlockedShape &bs)
+{
+    size_t bytes = sizeof(uint32_t) * (size_t)p.nviews * kYmaxParts;
+    bytes = (bytes + 255) & ~(size_t)255;
+    if (bs.splits > 1) bytes += sizeof(float) * (size_t)bs.splits * (size_t)(p.grid.nvox * p.grid.nframes);
+    return bytes;
+}
+
+int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
+                               bool accumulate, bool use_map_mask, hipStream_t s, const int *done_flag,
+                               void *scratch, size_t scratch_bytes, const tomo_tuning &tu)
+{
+    const BlockedShape bs = blocked_shape(p, tu);
+    const size_t need = blocked_scratch_bytes(p, bs);
+    if (!scratch || scratch_bytes < need)
+        return set_error(TOMO_EINVAL, "blocked back-projection: scratch of %zu bytes needed", need);
+    if (bs.items >= ((int64_t)1 << 31)) return set_error(TOMO_EINVAL, "blocked back-projection: too many blocks");
+    uint32_t *ymax = (uint32_t *)scratch;
+    float *part = (float *)((char *)scratch + ((sizeof(uint32_t) * (size_t)p.nviews * kYmaxParts + 255) & ~(size_t)255));
+    const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;
+    if (dm)
+        hipLaunchKernelGGL(k_view_absmax<true>, dim3((unsigned)(p.nviews * kYmaxParts)), dim3(kThreads), 0, s,
+                           p.views_d, images, g->data_mask, ymax, done_flag);
+    else
+        hipLaunchKernelGGL(k_view_absmax<false>, dim3((unsigned)(p.nviews * kYmaxParts)), dim3(kThreads), 0, s,
+                           p.views_d, images, g->data_mask, ymax, done_flag);
+    BlockDev bd;
+    for (int a = 0; a < 3; ++a) {
+        bd.b[a] = bs.b[a];
+        bd.nb[a] = bs.nb[a];
+    }
+    bd.splits = bs.splits;
+    bd.maxit = bs.b[0] + bs.b[1] + bs.b[2] + 3;
+    const Bundle bun{tu.bp_bundle, tu.bp_xcd_remap};
+    const size_t lds = sizeof(unsigned long long) * (size_t)bs.b[0] * bs.b[1] * bs.b[2];
+    float *dst = bs.splits == 1 ? cube : part;
+    const int acc = accumulate ? 1 : 0;
+#define TOMO_LAUNCH_BK(M, D)                                                                            \
+    hipLaunchKernelGGL((k_backproject_blocked<M, D>), dim3((unsigned)bs.items), dim3(kThreads), lds, s, \
+                       p.grid, p.views_d, p.frame_views_d, p.frame_voff_d, bd, bun, images,            \
+                       g->map_mask, g->data_mask, ymax, dst, acc, done_flag, p.spill_d)
+    if (mm && dm) TOMO_LAUNCH_BK(true, true);
+    else if (mm) TOMO_LAUNCH_BK(true, false);
+    else if (dm) TOMO_LAUNCH_BK(false, true);
+    else TOMO_LAUNCH_BK(false, false);
+#undef TOMO_LAUNCH_BK
+    int rc = hip_fail(hipGetLastError(), "blocked back-projection kernel launch");
+    if (rc || bs.splits == 1) return rc;
+    const int64_t total = p.grid.nvox * p.grid.nframes;
+    int64_t nb = (total + kThreads - 1) / kThreads;
+    nb = nb > 4096 ? 4096 : nb;
+    if (mm)
+        hipLaunchKernelGGL(k_sum_owners<true>, dim3((unsigned)nb), dim3(kThreads), 0, s, part, bs.splits, total,
+                           p.grid.nvox, g->map_mask, cube, acc, done_flag);
+    else
+        hipLaunchKernelGGL(k_sum_owners<false>, dim3((unsigned)nb), dim3(kThreads), 0, s, part, bs.splits, total,
+                           p.grid.nvox, g->map_mask, cube, acc, done_flag);
+    return hip_fail(hipGetLastError(), "owner sum kernel launch");
+}
+
+}  // namespace tomo

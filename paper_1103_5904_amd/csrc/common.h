@@ -48,6 +48,14 @@ struct Bundle {
     int32_t xcd_remap;  // 1: give each XCD a contiguous range of tiles
 };
 
+// Owner-computes P^T launch shape (device copy).
+struct BlockDev {
+    int32_t b[3];     // block dimensions (voxels)
+    int32_t nb[3];    // blocks per axis
+    int32_t splits;   // owners per block (views dealt round-robin)
+    int32_t maxit;    // bound on in-block segments per ray
+};
+
 // Raw buffer resource over [base, base + bytes): loads outside the range
 // return 0 and stores/atomics outside it are dropped by the hardware.
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const void *base, uint32_t bytes)
@@ -123,6 +131,10 @@ struct Plan {
     int64_t npix = 0;            // total pixels
     int32_t max_steps = 0;       // bound on segments per ray
     unsigned *spill_d = nullptr; // device counter: binned writes that missed their LDS box
+    int32_t *frame_views_d = nullptr;  // device [nviews]: view indices grouped by frame
+    int32_t *frame_voff_d = nullptr;   // device [nframes + 1]: offsets into frame_views_d
+    int32_t min_frame_views = 0;       // fewest views any frame has
+    uint64_t size_class = 0;           // key of the autotuner's cache (size_class_of)
     Plan() = default;
     Plan(const Plan &) = delete;
     Plan &operator=(const Plan &) = delete;
@@ -130,6 +142,8 @@ struct Plan {
     {
         if (views_d) (void)hipFree(views_d);
         if (spill_d) (void)hipFree(spill_d);
+        if (frame_views_d) (void)hipFree(frame_views_d);
+        if (frame_voff_d) (void)hipFree(frame_voff_d);
     }
 };
 
@@ -144,18 +158,47 @@ int set_error(int status, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
 int validate_cube(const tomo_cube *c);
 tomo_tuning current_tuning();
+uint64_t size_class_of(const tomo_geometry *g, int64_t npix);
+// The tuning launches on this plan use: its size class's autotuned entry if
+// there is one, else the process-wide tuning.
+tomo_tuning tuning_for(const Plan &p);
 
 // Launchers (siddon.hip)
 int launch_project(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
                    bool use_map_mask, hipStream_t s);
+// scratch: blocked strategy only; when null the launcher takes stream-ordered
+// scratch from the pool for this launch.
 int launch_backproject(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
                        bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
-                       const int *done_flag = nullptr);
+                       const int *done_flag = nullptr, void *scratch = nullptr,
+                       size_t scratch_bytes = 0);
 int launch_project_flagged(const Plan &p, const tomo_geometry *g, const float *cube,
                            float *images, hipStream_t s, const int *done_flag);
+int launch_project_tuned(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
+                         bool use_map_mask, hipStream_t s, const int *done_flag, const tomo_tuning &tu);
+int launch_backproject_tuned(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
+                             bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
+                             const int *done_flag, void *scratch, size_t scratch_bytes,
+                             const tomo_tuning &tu);
 int launch_fill(float *x, int64_t n, float v, hipStream_t s);
 int launch_backproject_binned(const Plan &p, const tomo_geometry *g, const float *images,
-                              float *cube, bool use_map_mask, hipStream_t s, const int *done_flag);
+                              float *cube, bool use_map_mask, hipStream_t s, const int *done_flag,
+                              const tomo_tuning &tu);
+
+// Owner-computes back-projection (blocked.hip)
+struct BlockedShape {
+    int32_t b[3];    // block dimensions
+    int32_t nb[3];   // blocks per axis
+    int32_t splits;  // owners per block
+    int64_t items;   // workgroups of one launch
+};
+BlockedShape blocked_shape(const Plan &p, const tomo_tuning &tu);
+size_t blocked_scratch_bytes(const Plan &p, const BlockedShape &bs);
+int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
+                               bool accumulate, bool use_map_mask, hipStream_t s, const int *done_flag,
+                               void *scratch, size_t scratch_bytes, const tomo_tuning &tu);
+// Strategy a TOMO_BP_* request resolves to under the plan's tuning.
+int resolve_bp_strategy(const Plan &p, int strategy);
 
 // Learned preconditioner network (convnet.hip)
 size_t convnet_forward_ws_bytes(int64_t nvox);

@@ -44,29 +44,8 @@ __global__ __launch_bounds__(kThreads) void k_project(
     const int *__restrict__ done_flag)
 {
     if (done_flag && *done_flag) return;
-    const LanePixel lp = lane_pixel(views, nviews, block_tile(bun), bun.log2_bw);
-    const ViewDev &v = views[lp.view];
-    if (lp.col >= v.ncol || lp.row >= v.nrow) return;
-    const int64_t pix = v.pix_off + (int64_t)lp.row * v.ncol + lp.col;
-    float out = 0.0f;
-    RayState r;
-    if ((!kDataMask || data_mask[pix]) && ray_setup(g, v, lp.col, lp.row, r)) {
-        const auto rc = make_rsrc(cube + (int64_t)v.frame * g.nvox, (uint32_t)(g.nvox * 4));
-        double acc = 0.0;
-        if constexpr (kMapMask) {
-            const auto rm = make_rsrc(map_mask, (uint32_t)g.nvox);
-            ray_walk(r, maxit, [&](int32_t off, double dl) {
-                const float x = buf_load_f32(rc, (uint32_t)off * 4u);
-                acc = fma(dl, buf_load_u8(rm, (uint32_t)off) ? (double)x : 0.0, acc);
-            });
-        } else {
-            ray_walk(r, maxit, [&](int32_t off, double dl) {
-                acc = fma(dl, (double)buf_load_f32(rc, (uint32_t)off * 4u), acc);
-            });
-        }
-        out = (float)(acc * r.dn);
-    }
-    images[pix] = out;
+    project_tile<kMapMask, kDataMask>(g, views, nviews, bun.log2_bw, block_tile(bun), maxit, cube, map_mask,
+                                      data_mask, images);
 }
 
 template <bool kMapMask, bool kDataMask>
@@ -153,12 +132,6 @@ __global__ __launch_bounds__(kThreads) void k_fill(float *__restrict__ x, int64_
 
 // ------------------------------------------------------------ launchers
 
-static Bundle p_bundle()
-{
-    const tomo_tuning t = current_tuning();
-    return Bundle{t.p_bundle, t.p_xcd_remap};
-}
-
 static int64_t grid_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
 
 int launch_fill(float *x, int64_t n, float v, hipStream_t s)
@@ -170,11 +143,10 @@ int launch_fill(float *x, int64_t n, float v, hipStream_t s)
     return hip_fail(hipGetLastError(), "fill kernel launch");
 }
 
-static int launch_project_impl(const Plan &p, const tomo_geometry *g, const float *cube,
-                               float *images, bool use_map_mask, hipStream_t s,
-                               const int *done_flag)
+int launch_project_tuned(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
+                         bool use_map_mask, hipStream_t s, const int *done_flag, const tomo_tuning &tu)
 {
-    const Bundle b = p_bundle();
+    const Bundle b{tu.p_bundle, tu.p_xcd_remap};
     const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;
     const dim3 grid((unsigned)p.ntiles), blk(kThreads);
 #define TOMO_LAUNCH_P(M, D)                                                                         \
@@ -191,26 +163,53 @@ static int launch_project_impl(const Plan &p, const tomo_geometry *g, const floa
 int launch_project(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
                    bool use_map_mask, hipStream_t s)
 {
-    return launch_project_impl(p, g, cube, images, use_map_mask, s, nullptr);
+    return launch_project_tuned(p, g, cube, images, use_map_mask, s, nullptr, tuning_for(p));
 }
 
 int launch_project_flagged(const Plan &p, const tomo_geometry *g, const float *cube,
                            float *images, hipStream_t s, const int *done_flag)
 {
-    return launch_project_impl(p, g, cube, images, false, s, done_flag);
+    return launch_project_tuned(p, g, cube, images, false, s, done_flag, tuning_for(p));
+}
+
+int resolve_bp_strategy(const Plan &p, int strategy)
+{
+    return strategy == TOMO_BP_AUTO ? tuning_for(p).bp_default : strategy;
 }
 
 int launch_backproject(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
                        bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
-                       const int *done_flag)
+                       const int *done_flag, void *scratch, size_t scratch_bytes)
 {
+    return launch_backproject_tuned(p, g, images, cube, accumulate, use_map_mask, strategy, s, done_flag,
+                                    scratch, scratch_bytes, tuning_for(p));
+}
+
+int launch_backproject_tuned(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
+                             bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
+                             const int *done_flag, void *scratch, size_t scratch_bytes,
+                             const tomo_tuning &tu)
+{
+    if (strategy == TOMO_BP_AUTO) strategy = tu.bp_default;
+    if (strategy == TOMO_BP_BLOCKED) {
+        if (scratch)
+            return launch_backproject_blocked(p, g, images, cube, accumulate, use_map_mask, s, done_flag,
+                                              scratch, scratch_bytes, tu);
+        const size_t need = blocked_scratch_bytes(p, blocked_shape(p, tu));
+        void *tmp = nullptr;
+        if (hipMallocAsync(&tmp, need, s) != hipSuccess)
+            return set_error(TOMO_ENOMEM, "back-projection scratch of %zu bytes", need);
+        const int rc = launch_backproject_blocked(p, g, images, cube, accumulate, use_map_mask, s,
+                                                  done_flag, tmp, need, tu);
+        (void)hipFreeAsync(tmp, s);
+        return rc;
+    }
     if (!accumulate) {
         int rc = launch_fill(cube, p.grid.nvox * p.grid.nframes, 0.0f, s);
         if (rc) return rc;
     }
-    const tomo_tuning tu = current_tuning();
-    if (strategy == TOMO_BP_BINNED || (strategy == TOMO_BP_AUTO && tu.bp_default == TOMO_BP_BINNED))
-        return launch_backproject_binned(p, g, images, cube, use_map_mask, s, done_flag);
+    if (strategy == TOMO_BP_BINNED)
+        return launch_backproject_binned(p, g, images, cube, use_map_mask, s, done_flag, tu);
     const Bundle b{tu.bp_bundle, tu.bp_xcd_remap};
     const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;
     const dim3 grid((unsigned)p.ntiles), blk(kThreads);
@@ -240,7 +239,8 @@ extern "C" int tomo_count_crossings(const tomo_geometry *g, int64_t *total_h, to
     if (hipMallocAsync((void **)&d, sizeof(*d), s) != hipSuccess)
         return set_error(TOMO_ENOMEM, "tomo_count_crossings: device allocation failed");
     (void)hipMemsetAsync(d, 0, sizeof(*d), s);
-    const Bundle b = p_bundle();
+    const tomo_tuning tu = tuning_for(*p);
+    const Bundle b{tu.p_bundle, tu.p_xcd_remap};
     if (g->data_mask)
         hipLaunchKernelGGL((k_count<true>), dim3((unsigned)p->ntiles), dim3(kThreads), 0, s, p->grid,
                            p->views_d, p->nviews, b, p->max_steps, g->data_mask, d);

@@ -17,6 +17,7 @@
 
 #include <vector>
 
+#include "batch.h"
 #include "common.h"
 
 namespace tomo {
@@ -500,6 +501,8 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         !isfinite(prm->rtol) || prm->check_every < 1 || prm->record_count < 0 ||
         (prm->record_count > 0 && !prm->record_x && !prm->record_r))
         return set_error(TOMO_EINVAL, "tomo_cg_solve: invalid parameters");
+    if (prm->bp_strategy < TOMO_BP_AUTO || prm->bp_strategy > TOMO_BP_BLOCKED)
+        return set_error(TOMO_EINVAL, "tomo_cg_solve: unknown bp_strategy %d", prm->bp_strategy);
     if (prm->precond && (prm->fallback_window < 1 || !(prm->min_drop >= 0) || !(prm->min_drop < 1)))
         return set_error(TOMO_EINVAL, "tomo_cg_solve: fallback_window must be >= 1 and min_drop in [0, 1)");
     int st = TOMO_OK;
@@ -509,6 +512,16 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         return set_error(TOMO_EINVAL, "tomo_cg_solve: lambda_t needs nframes >= 2");
     if (prm->precond && g->cube.nframes != 1)
         return set_error(TOMO_EUNSUPPORTED, "tomo_cg_solve: the preconditioner needs nframes == 1");
+    if (prm->use_graph) {  // graph-captured iterations: a batch of one
+        if (prm->precond || prm->record_count > 0)
+            return set_error(TOMO_EUNSUPPORTED, "tomo_cg_solve: use_graph without preconditioner or recording");
+        tomo_batch bt = nullptr;
+        int e = tomo_batch_create(g, 1, &bt);
+        if (e) return e;
+        e = tomo_batch_cg_solve(bt, &y_d, &x_d, prm, rep, stream);
+        tomo_batch_destroy(bt);
+        return e;
+    }
     const bool fcg = prm->precond != nullptr;
     hipStream_t s = (hipStream_t)stream;
     const Dims d = dims_of(g->cube);
@@ -528,6 +541,15 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
     ws.st = (CgState *)buf.alloc(sizeof(CgState));
     ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)maxit + 1));
+    // back-projection strategy and its scratch, fixed for the whole solve
+    const int bps = resolve_bp_strategy(*plan, prm->bp_strategy);
+    size_t bscr_bytes = 0;
+    void *bscr = nullptr;
+    if (bps == TOMO_BP_BLOCKED) {
+        bscr_bytes = blocked_scratch_bytes(*plan, blocked_shape(*plan, tuning_for(*plan)));
+        bscr = buf.alloc(bscr_bytes);
+        if (!bscr) return set_error(TOMO_ENOMEM, "tomo_cg_solve: device allocation failed");
+    }
     float *z = fcg ? (float *)buf.alloc(sizeof(float) * n) : nullptr;
     void *netws = fcg ? buf.alloc(convnet_forward_ws_bytes(d.nvox)) : nullptr;
     if (!b || !r || !p || !q || !img || !ws.partials || !ws.counter || !ws.st || !ws.hist ||
@@ -572,7 +594,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     }
 
     // b = M P^T y
-    rc = launch_backproject(*plan, g, y_d, b, false, true, prm->bp_strategy, s);
+    rc = launch_backproject(*plan, g, y_d, b, false, true, bps, s, nullptr, bscr, bscr_bytes);
     if (rc) return rc;
     ++n_bp;
     if (g->map_mask && prm->x0_given) {
@@ -580,7 +602,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     }
     auto apply_A_to = [&](const float *v) -> int {  // q = M (P^T P + prior) v, excluding the prior
         int e = launch_project(*plan, g, v, img, false, s);
-        if (!e) e = launch_backproject(*plan, g, img, q, false, false, prm->bp_strategy, s);
+        if (!e) e = launch_backproject(*plan, g, img, q, false, false, bps, s, nullptr, bscr, bscr_bytes);
         n_proj++;
         n_bp++;
         return e;
@@ -639,7 +661,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         }
         int e = launch_project_flagged(*plan, g, p, img, s, &ws.st->done);
         if (timed) (void)hipEventRecord(e1, s);
-        if (!e) e = launch_backproject(*plan, g, img, q, true, false, prm->bp_strategy, s, &ws.st->done);
+        if (!e) e = launch_backproject(*plan, g, img, q, true, false, bps, s, &ws.st->done, bscr, bscr_bytes);
         if (timed) {
             (void)hipEventRecord(e2, s);
             evP.push_back(e0);
@@ -747,6 +769,313 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
             rep->ms_project += a;
             rep->ms_backproject += bms;
         }
+    }
+    return TOMO_OK;
+}
+
+// ------------------------------------------------------------ batched CG
+
+int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_d, const tomo_cg_params *prm,
+                        tomo_cg_report *rep, tomo_stream stream)
+{
+    if (!bt || !y_d || !x_d || !prm || !rep) return set_error(TOMO_EINVAL, "tomo_batch_cg_solve: NULL argument");
+    const int ns = bt->nsys;
+    for (int k = 0; k < ns; ++k) {
+        const tomo_cg_params &q = prm[k];
+        if (!y_d[k] || !x_d[k]) return set_error(TOMO_EINVAL, "tomo_batch_cg_solve: NULL array (system %d)", k);
+        if (!(q.lambda_r >= 0) || !(q.lambda_t >= 0) || !isfinite(q.lambda_r) || !isfinite(q.lambda_t) ||
+            q.max_iter < 0 || !(q.rtol >= 0) || !isfinite(q.rtol))
+            return set_error(TOMO_EINVAL, "tomo_batch_cg_solve: invalid parameters (system %d)", k);
+        if (q.precond || q.record_count > 0 || q.record_x || q.record_r)
+            return set_error(TOMO_EUNSUPPORTED, "tomo_batch_cg_solve: no preconditioner or recording");
+        if (q.lambda_t > 0 && bt->geoms[(size_t)k].cube.nframes < 2)
+            return set_error(TOMO_EINVAL, "tomo_batch_cg_solve: lambda_t needs nframes >= 2 (system %d)", k);
+    }
+    if (prm[0].check_every < 1) return set_error(TOMO_EINVAL, "tomo_batch_cg_solve: check_every must be >= 1");
+    const int chunk = prm[0].check_every;
+    const bool use_graph = prm[0].use_graph != 0;
+    hipStream_t s = (hipStream_t)stream;
+
+    struct Sys {
+        Dims d;
+        int64_t n, npix;
+        float *b, *r, *p, *q, *img;
+        Workspace ws;
+        float lr, lt;
+        const uint8_t *mm, *dm;
+        int maxit;
+        double rtol;
+        bool x0, skip;
+        double true_rel;
+        int restarts, n_proj, n_bp;
+    };
+    std::vector<Sys> sy((size_t)ns);
+    SolveBuffers buf;
+    buf.s = s;
+    CgState *states = (CgState *)buf.alloc(sizeof(CgState) * (size_t)ns);
+    if (!states) return set_error(TOMO_ENOMEM, "tomo_batch_cg_solve: device allocation failed");
+    for (int k = 0; k < ns; ++k) {
+        Sys &c = sy[(size_t)k];
+        const tomo_geometry &g = bt->geoms[(size_t)k];
+        c.d = dims_of(g.cube);
+        c.n = c.d.total;
+        c.npix = bt->plans[(size_t)k]->npix;
+        c.lr = (float)prm[k].lambda_r;
+        c.lt = (float)prm[k].lambda_t;
+        c.mm = g.map_mask;
+        c.dm = g.data_mask;
+        c.maxit = prm[k].max_iter;
+        c.rtol = prm[k].rtol;
+        c.x0 = prm[k].x0_given != 0;
+        c.skip = false;
+        c.true_rel = -1.0;
+        c.restarts = 0;
+        c.n_proj = c.n_bp = 0;
+        c.b = (float *)buf.alloc(sizeof(float) * c.n);
+        c.r = (float *)buf.alloc(sizeof(float) * c.n);
+        c.p = (float *)buf.alloc(sizeof(float) * c.n);
+        c.q = (float *)buf.alloc(sizeof(float) * c.n);
+        c.img = (float *)buf.alloc(sizeof(float) * c.npix);
+        c.ws.partials = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
+        c.ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
+        c.ws.st = states + k;
+        c.ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)c.maxit + 1));
+        if (!c.b || !c.r || !c.p || !c.q || !c.img || !c.ws.partials || !c.ws.counter || !c.ws.hist)
+            return set_error(TOMO_ENOMEM, "tomo_batch_cg_solve: device allocation failed");
+        int rc = hip_fail(hipMemsetAsync(c.ws.counter, 0, sizeof(unsigned), s), "counter init");
+        if (rc) return rc;
+    }
+    int rc = hip_fail(hipMemsetAsync(states, 0, sizeof(CgState) * (size_t)ns, s), "state init");
+    if (rc) return rc;
+    thread_local CgState *hst = nullptr;  // pinned, kept until the process ends
+    if (!hst && hipHostMalloc((void **)&hst, sizeof(CgState) * kMaxSys) != hipSuccess) {
+        hst = nullptr;
+        return set_error(TOMO_ENOMEM, "tomo_batch_cg_solve: pinned allocation failed");
+    }
+    auto pull_states = [&]() -> int {
+        int e = hip_fail(hipMemcpyAsync(hst, states, sizeof(CgState) * (size_t)ns, hipMemcpyDeviceToHost, s),
+                         "state copy");
+        if (!e) e = hip_fail(hipStreamSynchronize(s), "cg synchronise");
+        return e;
+    };
+
+    // non-finite data: such systems are reported and take no further part
+    for (auto &c : sy)
+        hipLaunchKernelGGL(k_count_nonfinite, dim3(elem_blocks(c.npix)), dim3(kThreads), 0, s, y_d[&c - &sy[0]],
+                           c.npix, c.dm, c.ws);
+    rc = pull_states();
+    if (rc) return rc;
+    static const int one = 1;
+    for (int k = 0; k < ns; ++k) {
+        Sys &c = sy[(size_t)k];
+        if (hst[k].aux > 0.0) {
+            c.skip = true;
+            rc = hip_fail(hipMemcpyAsync(&states[k].done, &one, sizeof(int), hipMemcpyHostToDevice, s), "flag");
+            if (!rc && !c.x0) rc = launch_fill(x_d[k], c.n, 0.0f, s);
+            if (rc) return rc;
+        }
+    }
+
+    auto ops_of = [&](bool all_flags) {
+        Operands o;
+        memset(&o, 0, sizeof(o));
+        for (int k = 0; k < ns; ++k)
+            o.done[k] = (all_flags || sy[(size_t)k].skip) ? &states[k].done : nullptr;
+        return o;
+    };
+    // b = M P^T y
+    {
+        Operands o = ops_of(true);
+        for (int k = 0; k < ns; ++k) {
+            o.src[k] = y_d[k];
+            o.dst[k] = sy[(size_t)k].b;
+        }
+        o.map = 1;
+        rc = batch_backproject_ops(bt, o, s);
+        if (rc) return rc;
+    }
+    auto apply_A_x = [&]() -> int {  // q = (P^T P) x for every active system (prior added by k_true_res)
+        Operands o = ops_of(false);
+        for (int k = 0; k < ns; ++k) {
+            o.src[k] = x_d[k];
+            o.dst[k] = sy[(size_t)k].img;
+        }
+        int e = batch_project_ops(bt, o, s);
+        for (int k = 0; k < ns; ++k) {
+            o.src[k] = sy[(size_t)k].img;
+            o.dst[k] = sy[(size_t)k].q;
+        }
+        if (!e) e = batch_backproject_ops(bt, o, s);
+        for (auto &c : sy)
+            if (!c.skip) {
+                c.n_proj++;
+                c.n_bp++;
+            }
+        return e;
+    };
+    bool any_x0 = false;
+    for (int k = 0; k < ns; ++k) {
+        Sys &c = sy[(size_t)k];
+        c.n_bp++;
+        if (c.skip) continue;
+        if (c.x0) {
+            any_x0 = true;
+            if (c.mm) hipLaunchKernelGGL(k_mask, dim3(elem_blocks(c.n)), dim3(kThreads), 0, s, x_d[k], c.mm, c.d);
+        } else {
+            rc = launch_fill(x_d[k], c.n, 0.0f, s);
+            if (rc) return rc;
+        }
+    }
+    if (any_x0) {
+        rc = apply_A_x();
+        if (rc) return rc;
+        for (int k = 0; k < ns; ++k) {
+            Sys &c = sy[(size_t)k];
+            if (c.skip) continue;
+            if (!c.x0) {  // that product was not needed for this system
+                c.n_proj--;
+                c.n_bp--;
+                continue;
+            }
+            hipLaunchKernelGGL(k_true_res, dim3(elem_blocks(c.n)), dim3(kThreads), 0, s, x_d[k], c.q, c.b, c.mm,
+                               c.d, c.lr, c.lt, c.ws);
+        }
+    }
+    for (int k = 0; k < ns; ++k) {
+        Sys &c = sy[(size_t)k];
+        if (c.skip) continue;
+        hipLaunchKernelGGL(k_cg_start, dim3(elem_blocks(c.n)), dim3(kThreads), 0, s, c.b, c.r, c.p, c.q, c.n,
+                           c.x0 ? 1 : 0, c.ws, c.rtol, c.maxit, 0);
+    }
+    rc = hip_fail(hipGetLastError(), "batched cg start");
+    if (rc) return rc;
+
+    // one iteration of every system
+    auto enqueue_iteration = [&](hipStream_t st) -> int {
+        Operands o = ops_of(true);
+        for (int k = 0; k < ns; ++k) {
+            o.src[k] = sy[(size_t)k].p;
+            o.dst[k] = sy[(size_t)k].img;
+        }
+        int e = batch_project_ops(bt, o, st);
+        for (int k = 0; k < ns; ++k) {
+            o.src[k] = sy[(size_t)k].img;
+            o.dst[k] = sy[(size_t)k].q;
+        }
+        o.acc = 1;
+        if (!e) e = batch_backproject_ops(bt, o, st);
+        if (e) return e;
+        for (int k = 0; k < ns; ++k) {
+            Sys &c = sy[(size_t)k];
+            if (c.skip) continue;
+            const unsigned eb = elem_blocks(c.n);
+            hipLaunchKernelGGL(k_cg_q, dim3(eb), dim3(kThreads), 0, st, c.p, c.q, c.mm, c.d, c.lr, c.lt, c.ws);
+            hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, st, x_d[k], c.r, c.p, c.q, c.n, c.ws);
+            hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, st, c.r, c.p, c.n, c.ws.st);
+        }
+        return hip_fail(hipGetLastError(), "batched cg iteration launch");
+    };
+
+    // the check interval as a graph
+    struct GraphGuard {
+        hipStream_t cs = nullptr;
+        hipGraphExec_t exec = nullptr;
+        ~GraphGuard()
+        {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (cs) (void)hipStreamDestroy(cs);
+        }
+    } gg;
+    if (use_graph) {
+        // capture on a private stream (the caller's may be the null stream),
+        // replay on the caller's
+        rc = hip_fail(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking), "capture stream");
+        if (!rc) rc = hip_fail(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal), "begin capture");
+        if (rc) return rc;
+        int cap_rc = TOMO_OK;
+        for (int i = 0; i < chunk && !cap_rc; ++i) cap_rc = enqueue_iteration(gg.cs);
+        hipGraph_t graph = nullptr;
+        rc = hip_fail(hipStreamEndCapture(gg.cs, &graph), "end capture");
+        if (!rc && cap_rc) rc = cap_rc;
+        if (!rc) rc = hip_fail(hipGraphInstantiate(&gg.exec, graph, nullptr, nullptr, 0), "graph instantiate");
+        if (graph) (void)hipGraphDestroy(graph);
+        if (rc) return rc;
+    }
+
+    for (;;) {
+        for (;;) {
+            if (gg.exec) {
+                rc = hip_fail(hipGraphLaunch(gg.exec, s), "graph launch");
+            } else {
+                for (int i = 0; i < chunk && !rc; ++i) rc = enqueue_iteration(s);
+            }
+            if (!rc) rc = pull_states();
+            if (rc) return rc;
+            bool all = true;
+            for (int k = 0; k < ns; ++k) all = all && (sy[(size_t)k].skip || hst[k].done);
+            if (all) break;
+        }
+        // true residuals
+        rc = apply_A_x();
+        if (rc) return rc;
+        for (int k = 0; k < ns; ++k) {
+            Sys &c = sy[(size_t)k];
+            if (c.skip) continue;
+            hipLaunchKernelGGL(k_true_res, dim3(elem_blocks(c.n)), dim3(kThreads), 0, s, x_d[k], c.q, c.b, c.mm,
+                               c.d, c.lr, c.lt, c.ws);
+        }
+        rc = pull_states();
+        if (rc) return rc;
+        bool restarted = false;
+        for (int k = 0; k < ns; ++k) {
+            Sys &c = sy[(size_t)k];
+            if (c.skip || hst[k].nonfinite) continue;
+            c.true_rel = hst[k].bb > 0 ? sqrt(hst[k].aux / hst[k].bb) : 0.0;
+            const bool unconfirmed = c.rtol > 0 && c.true_rel > 1.1 * c.rtol;
+            if (unconfirmed && hst[k].iter < c.maxit && c.restarts < 8) {
+                ++c.restarts;
+                restarted = true;
+                hipLaunchKernelGGL(k_cg_start, dim3(elem_blocks(c.n)), dim3(kThreads), 0, s, c.b, c.r, c.p, c.q,
+                                   c.n, 1, c.ws, c.rtol, c.maxit, hst[k].iter);
+            }
+        }
+        if (!restarted) break;
+        rc = hip_fail(hipGetLastError(), "batched cg restart");
+        if (rc) return rc;
+    }
+
+    // reports
+    for (int k = 0; k < ns; ++k) {
+        Sys &c = sy[(size_t)k];
+        tomo_cg_report &r = rep[k];
+        double *hist_h = r.history;
+        const int32_t cap = r.history_cap;
+        memset(&r, 0, offsetof(tomo_cg_report, history));
+        r.fell_back = -1;
+        if (c.skip) {
+            r.status = TOMO_ENONFINITE;
+            r.rel_res = r.true_rel_res = NAN;
+            r.history_len = 0;
+            continue;
+        }
+        const CgState &h = hst[k];
+        r.iters = h.iter;
+        r.n_project = c.n_proj + h.iter;
+        r.n_backproject = c.n_bp + h.iter;
+        r.bnorm = sqrt(h.bb);
+        r.rel_res = h.bb > 0 ? sqrt(h.res2 / h.bb) : 0.0;
+        r.true_rel_res = c.true_rel;
+        if (h.nonfinite) r.status = TOMO_ENONFINITE;
+        else if (c.rtol > 0 && !(c.true_rel <= 1.1 * c.rtol)) r.status = TOMO_ENOCONV;
+        else r.status = TOMO_OK;
+        r.history_len = 0;
+        if (hist_h && cap > 0) {
+            const int nh = h.iter + 1 < cap ? h.iter + 1 : cap;
+            rc = hip_fail(hipMemcpy(hist_h, c.ws.hist, sizeof(double) * nh, hipMemcpyDeviceToHost), "history copy");
+            if (rc) return rc;
+            r.history_len = nh;
+        }
+        r.ms_project = r.ms_backproject = 0.0;
     }
     return TOMO_OK;
 }

@@ -183,4 +183,37 @@ __device__ inline int64_t block_tile(const Bundle &b)
     return b.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
 }
 
+// P for one 16x16 tile (all threads of the workgroup): each lane's pixel =
+// sum over its ray's segments of length x voxel value, written to images.
+template <bool kMapMask, bool kDataMask>
+__device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict__ views, int32_t nviews,
+                                    int log2_bw, int64_t tile, int32_t maxit,
+                                    const float *__restrict__ cube, const uint8_t *__restrict__ map_mask,
+                                    const uint8_t *__restrict__ data_mask, float *__restrict__ images)
+{
+    const LanePixel lp = lane_pixel(views, nviews, tile, log2_bw);
+    const ViewDev &v = views[lp.view];
+    if (lp.col >= v.ncol || lp.row >= v.nrow) return;
+    const int64_t pix = v.pix_off + (int64_t)lp.row * v.ncol + lp.col;
+    float out = 0.0f;
+    RayState r;
+    if ((!kDataMask || data_mask[pix]) && ray_setup(g, v, lp.col, lp.row, r)) {
+        const auto rc = make_rsrc(cube + (int64_t)v.frame * g.nvox, (uint32_t)(g.nvox * 4));
+        double acc = 0.0;
+        if constexpr (kMapMask) {
+            const auto rm = make_rsrc(map_mask, (uint32_t)g.nvox);
+            ray_walk(r, maxit, [&](int32_t off, double dl) {
+                const float x = buf_load_f32(rc, (uint32_t)off * 4u);
+                acc = fma(dl, buf_load_u8(rm, (uint32_t)off) ? (double)x : 0.0, acc);
+            });
+        } else {
+            ray_walk(r, maxit, [&](int32_t off, double dl) {
+                acc = fma(dl, (double)buf_load_f32(rc, (uint32_t)off * 4u), acc);
+            });
+        }
+        out = (float)(acc * r.dn);
+    }
+    images[pix] = out;
+}
+
 }  // namespace tomo

@@ -24,7 +24,7 @@ TOMO_ENOCONV = -4
 TOMO_ENOMEM = -5
 TOMO_EUNSUPPORTED = -6
 
-BP_AUTO, BP_ATOMIC, BP_BINNED = 0, 1, 2
+BP_AUTO, BP_ATOMIC, BP_BINNED, BP_BLOCKED = 0, 1, 2, 3
 
 
 class TomoError(RuntimeError):
@@ -51,7 +51,8 @@ class TomoGeometry(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("p_bundle", c_int32), ("p_xcd_remap", c_int32), ("bp_bundle", c_int32),
-                ("bp_xcd_remap", c_int32), ("bp_lds_bins", c_int32), ("bp_default", c_int32)]
+                ("bp_xcd_remap", c_int32), ("bp_lds_bins", c_int32), ("bp_default", c_int32),
+                ("bp_block", c_int32 * 3), ("bp_splits", c_int32)]
 
 
 class CgParams(ctypes.Structure):
@@ -77,7 +78,10 @@ EXPORTS = [
     "tomo_view_from_wcs", "tomo_validate_geometry", "tomo_geometry_pixels",
     "tomo_release_cache", "tomo_status_string", "tomo_last_error", "tomo_binning_spills",
     "tomo_get_tuning", "tomo_set_tuning", "tomo_convnet_workspace_bytes", "tomo_convnet_forward",
-    "tomo_convnet_loss_grad", "tomo_convnet_backward", "tomo_adam_step",
+    "tomo_convnet_loss_grad", "tomo_convnet_backward", "tomo_adam_step", "tomo_autotune",
+    "tomo_get_class_tuning", "tomo_autotune_clear", "tomo_batch_create", "tomo_batch_destroy",
+    "tomo_batch_project", "tomo_batch_backproject", "tomo_batch_binning_spills", "tomo_batch_items",
+    "tomo_batch_cg_solve",
 ]
 NPARAMS = 7809
 
@@ -123,6 +127,21 @@ def lib():
         L.tomo_adam_step.argtypes = [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                      c_double, c_double, c_double, c_double, c_void_p]
         L.tomo_set_tuning.argtypes = [POINTER(Tuning)]
+        L.tomo_autotune.argtypes = [POINTER(TomoGeometry), c_int32, POINTER(Tuning), c_void_p]
+        L.tomo_get_class_tuning.argtypes = [POINTER(TomoGeometry), POINTER(Tuning), POINTER(c_int32)]
+        L.tomo_autotune_clear.argtypes = []
+        L.tomo_autotune_clear.restype = None
+        L.tomo_batch_create.argtypes = [POINTER(TomoGeometry), c_int32, POINTER(c_void_p)]
+        L.tomo_batch_destroy.argtypes = [c_void_p]
+        L.tomo_batch_destroy.restype = None
+        L.tomo_batch_project.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), c_void_p]
+        L.tomo_batch_backproject.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), ctypes.c_int,
+                                             c_void_p]
+        L.tomo_batch_binning_spills.argtypes = [c_void_p, POINTER(c_int64)]
+        L.tomo_batch_items.argtypes = [c_void_p, c_int32]
+        L.tomo_batch_items.restype = c_int64
+        L.tomo_batch_cg_solve.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(CgParams),
+                                          POINTER(CgReport), c_void_p]
         L.tomo_geometry_pixels.argtypes = [POINTER(TomoGeometry)]
         _lib = L
     return _lib
@@ -229,7 +248,9 @@ def backproject(geom: DeviceGeometry, images: torch.Tensor, out: torch.Tensor | 
 def get_tuning() -> dict:
     t = Tuning()
     _check(lib().tomo_get_tuning(ctypes.byref(t)))
-    return {k: getattr(t, k) for k, _ in Tuning._fields_}
+    out = {k: getattr(t, k) for k, _ in Tuning._fields_}
+    out["bp_block"] = tuple(t.bp_block)
+    return out
 
 
 def set_tuning(**kw) -> dict:
@@ -240,10 +261,135 @@ def set_tuning(**kw) -> dict:
     for k, v in kw.items():
         if k not in new:
             raise KeyError(k)
-        new[k] = int(v)
-    t = Tuning(**new)
+        new[k] = tuple(int(e) for e in v) if k == "bp_block" else int(v)
+    t = Tuning(**{k: v for k, v in new.items() if k != "bp_block"})
+    for a in range(3):
+        t.bp_block[a] = new["bp_block"][a]
     _check(lib().tomo_set_tuning(ctypes.byref(t)))
     return old
+
+
+def _tuning_dict(t: Tuning) -> dict:
+    out = {k: getattr(t, k) for k, _ in Tuning._fields_}
+    out["bp_block"] = tuple(t.bp_block)
+    return out
+
+
+def autotune(geom: DeviceGeometry, reps: int = 3) -> dict:
+    """Time the launch candidates on this geometry and keep the fastest for
+    its size class (tomo_autotune); returns the chosen tuning."""
+    t = Tuning()
+    _check(lib().tomo_autotune(geom.ref, int(reps), ctypes.byref(t), _stream()))
+    return _tuning_dict(t)
+
+
+def class_tuning(geom: DeviceGeometry):
+    """(tuning in effect for this geometry, whether the autotuner chose it)."""
+    t = Tuning()
+    tuned = c_int32(0)
+    _check(lib().tomo_get_class_tuning(geom.ref, ctypes.byref(t), ctypes.byref(tuned)))
+    return _tuning_dict(t), bool(tuned.value)
+
+
+def autotune_clear():
+    lib().tomo_autotune_clear()
+
+
+def _ptrs(tensors, numels, name):
+    arr = (c_void_p * len(tensors))()
+    for k, (t, n) in enumerate(zip(tensors, numels)):
+        arr[k] = _dev_f32(t, n, f"{name}[{k}]").value
+    return arr
+
+
+def _cg_params(lam_r, lam_t, max_iter, rtol, check_every, use_graph, x0_given):
+    p = CgParams()
+    lib().tomo_cg_default_params(ctypes.byref(p))
+    p.lambda_r, p.lambda_t, p.max_iter, p.rtol = lam_r, lam_t, int(max_iter), rtol
+    p.check_every, p.use_graph, p.x0_given = int(check_every), int(bool(use_graph)), int(bool(x0_given))
+    return p
+
+
+_REPORT_KEYS = ("iters", "status", "fell_back", "n_project", "n_backproject", "rel_res", "true_rel_res",
+                "bnorm", "ms_project", "ms_backproject")
+
+
+class Batch:
+    """Several independent systems (DeviceGeometry each) behind one persistent
+    P launch and one persistent P^T launch (tomo_batch_*)."""
+
+    def __init__(self, geoms):
+        self.geoms = list(geoms)  # keeps the masks alive
+        n = len(self.geoms)
+        arr = (TomoGeometry * n)(*[g.g for g in self.geoms])
+        self._arr = arr
+        self.h = c_void_p()
+        _check(lib().tomo_batch_create(arr, n, ctypes.byref(self.h)))
+
+    def close(self):
+        if self.h:
+            lib().tomo_batch_destroy(self.h)
+            self.h = c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def items(self, which: int) -> int:
+        return int(lib().tomo_batch_items(self.h, int(which)))
+
+    def spills(self) -> int:
+        c = c_int64(0)
+        _check(lib().tomo_batch_binning_spills(self.h, ctypes.byref(c)))
+        return int(c.value)
+
+    def project(self, cubes, outs=None):
+        if outs is None:
+            outs = [torch.empty(g.npix, dtype=torch.float32, device=c.device) for g, c in zip(self.geoms, cubes)]
+        src = _ptrs(cubes, [g.nvox * g.nframes for g in self.geoms], "cubes")
+        dst = _ptrs(outs, [g.npix for g in self.geoms], "images")
+        _check(lib().tomo_batch_project(self.h, src, dst, _stream()))
+        return outs
+
+    def backproject(self, images, outs=None, accumulate=False):
+        if outs is None:
+            outs = [torch.empty(g.cube_shape, dtype=torch.float32, device=y.device)
+                    for g, y in zip(self.geoms, images)]
+        src = _ptrs(images, [g.npix for g in self.geoms], "images")
+        dst = _ptrs(outs, [g.nvox * g.nframes for g in self.geoms], "cubes")
+        _check(lib().tomo_batch_backproject(self.h, src, dst, int(bool(accumulate)), _stream()))
+        return outs
+
+    def cg_solve(self, ys, x0s=None, *, lam_r=1e-2, lam_t=0.0, max_iter=50, rtol=0.0, check_every=10,
+                 use_graph=False, outs=None):
+        """CG on every system at once; lam_r, lam_t, max_iter, rtol may be
+        per-system lists.  Returns (xs, reports)."""
+        n = len(self.geoms)
+        per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * n  # noqa: E731
+        lr, lt, mi, rt = per(lam_r), per(lam_t), per(max_iter), per(rtol)
+        if outs is None:
+            outs = [torch.empty(g.cube_shape, dtype=torch.float32, device=y.device) for g, y in zip(self.geoms, ys)]
+        if x0s is not None:
+            for o, x0 in zip(outs, x0s):
+                o.copy_(x0.reshape(o.shape))
+        params = (CgParams * n)(*[_cg_params(lr[k], lt[k], mi[k], rt[k], check_every, use_graph, x0s is not None)
+                                  for k in range(n)])
+        hists = [(c_double * (int(mi[k]) + 1))() for k in range(n)]
+        reps = (CgReport * n)()
+        for k in range(n):
+            reps[k].history = hists[k]
+            reps[k].history_cap = int(mi[k]) + 1
+        src = _ptrs(ys, [g.npix for g in self.geoms], "y")
+        dst = _ptrs(outs, [g.nvox * g.nframes for g in self.geoms], "x")
+        _check(lib().tomo_batch_cg_solve(self.h, src, dst, params, reps, _stream()))
+        out = []
+        for k in range(n):
+            d = {key: getattr(reps[k], key) for key in _REPORT_KEYS}
+            d["history"] = np.ctypeslib.as_array(hists[k])[:reps[k].history_len].copy()
+            out.append(d)
+        return outs, out
 
 
 def binning_spills(geom: DeviceGeometry) -> int:
@@ -320,9 +466,7 @@ def cg_solve(geom: DeviceGeometry, y: torch.Tensor, x0: torch.Tensor | None = No
     _check(lib().tomo_cg_solve(geom.ref, _dev_f32(y, geom.npix, "y"),
                                _dev_f32(out, geom.nvox * geom.nframes, "x"), ctypes.byref(p),
                                ctypes.byref(rep), _stream()))
-    report = {k: getattr(rep, k) for k in ("iters", "status", "fell_back", "n_project",
-                                          "n_backproject", "rel_res", "true_rel_res", "bnorm",
-                                          "ms_project", "ms_backproject")}
+    report = {k: getattr(rep, k) for k in _REPORT_KEYS}
     report["history"] = np.ctypeslib.as_array(hist)[:rep.history_len].copy()
     return out, report
 

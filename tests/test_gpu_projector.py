@@ -14,7 +14,8 @@ def tomo():
     return need_gpu()
 
 
-STRATEGIES = ["binned", "atomic"]
+STRATEGIES = ["blocked", "binned", "atomic"]
+CODES = {"blocked": 3, "binned": 2, "atomic": 1}
 
 
 def _parity_full(tomo, ora, g, x, y, strategies=STRATEGIES):
@@ -27,7 +28,7 @@ def _parity_full(tomo, ora, g, x, y, strategies=STRATEGIES):
     assert_p_close(img, ora.project(g, x), ora.project(g, np.abs(xm)), atol=res * np.abs(x).max())
     ref, refa = ora.backproject(g, y), ora.backproject(g, np.abs(y))
     for strat in strategies:
-        code = {"binned": tomo.BP_BINNED, "atomic": tomo.BP_ATOMIC}[strat]
+        code = CODES[strat]
         bp = to_host(tomo.backproject(dg, to_dev(y), strategy=code))
         assert_p_close(bp, ref, refa, rtol=1e-4, what=f"P^T ({strat})", atol=res * np.abs(y).max())
         assert tomo.binning_spills(dg) == 0
@@ -203,3 +204,74 @@ def test_adjoint_identity(tomo):
         scale = float(torch.linalg.norm(px)) * float(np.linalg.norm(y))
         worst = max(worst, abs(lhs - rhs) / scale)
     assert worst <= 1e-5
+
+
+@pytest.fixture
+def tuning(tomo):
+    """Restores the process-wide tuning after a test changes it."""
+    old = tomo.get_tuning()
+    yield tomo
+    tomo.set_tuning(**old)
+
+
+@pytest.mark.parametrize("block,splits", [((4, 4, 4), 1), ((5, 3, 7), 3), ((32, 2, 9), 0), ((16, 16, 16), 8)])
+def test_blocked_shapes(tuning, ora, block, splits):
+    """The blocked P^T with small, ragged and flat voxel blocks and several
+    owners per block, on the tiny, masked and multi-frame geometries."""
+    tomo = tuning
+    tomo.set_tuning(bp_block=block, bp_splits=splits)
+    wl = ts.tiny()
+    g = wl.geom
+    rng = np.random.default_rng(21)
+    _parity_full(tomo, ora, g, wl.x, rng.normal(size=g.nrays), strategies=["blocked"])
+    dm = (rng.uniform(size=g.nrays) > 0.3).astype(np.uint8)
+    mm = (rng.uniform(size=g.cube_shape()) > 0.2).astype(np.uint8)
+    vf = (np.arange(g.nviews) % 3).astype(np.int32)
+    gm = ts.Geometry(g.n, g.lo, g.hi, g.views, g.npix, vf, 3, data_mask=dm, map_mask=mm)
+    x3 = np.stack([wl.x * (f + 1) for f in range(3)])
+    _parity_full(tomo, ora, gm, x3, rng.normal(size=g.nrays), strategies=["blocked"])
+
+
+@pytest.mark.parametrize("block", [(4, 4, 4), (5, 3, 7)])
+def test_blocked_one_hot_rays_match_the_walk(tuning, block):
+    """P^T of a one-hot image through the blocked strategy is that ray's
+    segment list: the same voxels as the full walk (tomo_trace_ray) and the
+    same lengths to FP32 rounding, although every ray is walked piecewise
+    through many small blocks."""
+    import torch
+
+    tomo = tuning
+    tomo.set_tuning(bp_block=block, bp_splits=1)
+    wl = ts.tiny()
+    g = wl.geom
+    dg = tomo.DeviceGeometry(g)
+    y = torch.zeros(g.nrays, dtype=torch.float32, device="cuda")
+    checked = 0
+    for v, col, row in sample_pixels(g, 120, 31):
+        gi, gl, _ = tomo.trace_ray(dg, v, col, row)
+        k = flat_index(g, v, col, row)
+        y.zero_()
+        y[k] = 1.0
+        bp = to_host(tomo.backproject(dg, y, strategy=tomo.BP_BLOCKED)).reshape(-1)
+        ref = np.zeros(g.nvox)
+        np.add.at(ref, gi, gl)
+        # near-tie segments of ~1e-16 fall below the fixed-point quantum
+        # (~1e-15 here) and may vanish; everything else must be there
+        got = set(np.flatnonzero(bp).tolist())
+        assert set(gi[gl > 3e-12].tolist()) <= got <= set(gi.tolist()), (v, col, row)
+        np.testing.assert_allclose(bp, ref, rtol=2.0 ** -23, atol=1e-12)
+        checked += len(gi)
+    assert checked > 1000
+
+
+def test_blocked_is_deterministic(tomo):
+    import torch
+
+    wl = ts.euvi()
+    g = wl.geom.subset([0, 3, 7])
+    dg = tomo.DeviceGeometry(g)
+    y = to_dev(np.random.default_rng(8).normal(size=g.nrays))
+    a = tomo.backproject(dg, y, strategy=tomo.BP_BLOCKED)
+    b = tomo.backproject(dg, y, strategy=tomo.BP_BLOCKED)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
