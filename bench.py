@@ -13,7 +13,10 @@ most of the step time, timed per launch with HIP events recorded on the
 stream the library launches it on.  The CPU baseline is the FP64 oracle on a
 bounded sample of the same workload.  After the timed steps, the learned
 preconditioner's wall time to relative residual 1e-3 is compared with plain
-CG on held-out problems of its own family (time_to_rel_res_1e-3).
+CG on held-out problems of its own family (time_to_rel_res_1e-3), and the
+COR1-like batch (five systems of uneven size in persistent launches with
+autotuned shapes) is timed against solving its systems one after another
+(batched).
 """
 from __future__ import annotations
 
@@ -32,6 +35,11 @@ METRIC = "Siddon P/Pᵀ voxel-crossings/s; time to rel. residual 1e-3 (learned v
 HBM_PEAK_GBS = 8000.0
 
 
+def log(msg):
+    """Progress on stderr (stdout carries only the result line)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -44,6 +52,8 @@ def parse():
                     help="back-projection strategy")
     ap.add_argument("--no-learned", action="store_true",
                     help="skip the learned-vs-plain time to relative residual 1e-3")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batched COR1-like measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the timed steps, run 3 device-to-device copies of MIB MiB: the "
                          "known-size kernel that calibrates hardware byte counters")
@@ -81,6 +91,63 @@ def learned_vs_plain(tomo, ts, seeds=(2003, 2004), reps=3):
             "plain_ms": float(np.mean([r["plain_ms"] for r in rows])),
             "learned_ms": float(np.mean([r["learned_ms"] for r in rows])),
             "problems": rows}
+
+
+def batched_cor1(tomo, ts, iters=10, reps=3):
+    """COR1-like batch: 8 time frames of 256^3 on [-4, 4]^3 (60 views of
+    512x512, detector annulus 1.4-4 kept, unit sphere masked, temporal prior
+    lambda_t 10) plus 4 independent reconstructions of 64^3-192^3 (16 views
+    of 256x256 each), every launch shape chosen by the autotuner for its size
+    class.  Times `iters` CG iterations of all five systems in the batched
+    persistent launches with graph-captured check intervals (median of
+    `reps`) against the same iterations run system after system."""
+    import torch
+
+    wl = ts.cor1_frames()
+    extras = ts.cor1_extras()
+    works = [wl] + extras
+    dgs = [tomo.DeviceGeometry(w.geom) for w in works]
+    tunings = [tomo.autotune(dg, reps=2) for dg in dgs]
+    ys = [tomo.project(dg, torch.as_tensor(w.x.astype(np.float32)).cuda()) for dg, w in zip(dgs, works)]
+    cross = [tomo.count_crossings(dg) for dg in dgs]
+    lam_t = [w.lam_t for w in works]
+    batch = tomo.Batch(dgs)
+
+    def run_batch():
+        return batch.cg_solve(ys, lam_r=1e-2, lam_t=lam_t, max_iter=iters, check_every=iters, use_graph=True)
+
+    def run_seq():
+        for dg, y, lt in zip(dgs, ys, lam_t):
+            tomo.cg_solve(dg, y, lam_r=1e-2, lam_t=lt, max_iter=iters, check_every=iters)
+
+    def timed(f):
+        f()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            t0 = time.perf_counter()
+            f()
+            torch.cuda.synchronize()
+            out.append(time.perf_counter() - t0)
+        return float(np.median(out))
+
+    t_batch, t_seq = timed(run_batch), timed(run_seq)
+    _, reps_b = run_batch()
+    apps = sum(r["n_project"] + r["n_backproject"] for r in reps_b)
+    per_app = {k: c for k, c in zip(range(len(cross)), cross)}
+    crossings = sum((r["n_project"] + r["n_backproject"]) * per_app[k] for k, r in enumerate(reps_b))
+    out = {"workload": "COR1-like: 8 frames of 256^3 (60 views of 512^2, annulus mask, lambda_t 10) + "
+                       "64^3, 96^3, 128^3, 192^3 extras (16 views of 256^2), one persistent P and P^T "
+                       "launch per operator, graph-captured CG",
+           "iterations": iters, "systems": len(dgs), "applications": apps,
+           "ms_batched": 1e3 * t_batch, "ms_sequential": 1e3 * t_seq, "speedup": t_seq / t_batch,
+           "crossings_per_s": crossings / t_batch,
+           "p_items": batch.items(0), "pt_items": batch.items(1), "p_workgroups": batch.items(2),
+           "pt_workgroups": batch.items(3),
+           "tuning": [{k: (list(v) if isinstance(v, tuple) else v) for k, v in t.items()} for t in tunings]}
+    batch.close()
+    tomo.autotune_clear()
+    return out
 
 
 def cpu_baseline(wl, reps):
@@ -193,10 +260,16 @@ def main():
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
     }
+    log(f"timed steps done: {ms_step:.1f} ms per step")
     if not args.no_learned:
         out["time_to_rel_res_1e-3"] = learned_vs_plain(tomo, ts)
+        log("learned vs plain done")
+    if not args.no_batch:
+        out["batched"] = batched_cor1(tomo, ts)
+        log("batched COR1-like done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_reps)
+        log("cpu baseline done")
     print(json.dumps(out), flush=True)
 
 

@@ -175,7 +175,7 @@ int tomo_trace_ray(const tomo_geometry *g, int32_t view, int32_t col,
  *     back-projection owns (each 1..64, product <= 8192 64-bit LDS bins).
  *   bp_splits: owners per block in the blocked back-projection, the block's
  *     views dealt round-robin (1..64; 0 = chosen from the block count so
- *     that the launch has about 2048 workgroups).
+ *     that the launch has about 4096 workgroups, at most 8 owners).
  * tomo_set_tuning returns TOMO_EINVAL (and changes nothing) for values out
  * of range.  Not synchronised with launches in flight on other threads.
  */

@@ -158,12 +158,16 @@ def draw_shell_blobs(rng, nblobs, r_range=(1.5, 3.5), sigma=(0.1, 0.6), amp=(0.0
 def blob_cube(n, lo, hi, blobs, rot_z_deg: float = 0.0) -> np.ndarray:
     """Sum of Gaussian blobs a exp(-|c - mu|^2 / 2 sigma^2) at voxel centres,
     optionally with the blob centres rotated about z."""
-    x, y, z = voxel_centres(n, lo, hi)
-    out = np.zeros(x.shape)
+    nx, ny, nz = n
+    ax = [lo[a] + (np.arange(m) + 0.5) * (hi[a] - lo[a]) / m for a, m in enumerate((nx, ny, nz))]
+    out = np.zeros((nz, ny, nx))
     c, s = np.cos(np.deg2rad(rot_z_deg)), np.sin(np.deg2rad(rot_z_deg))
     for mx, my, mz, sg, a in blobs:
         rx, ry = c * mx - s * my, s * mx + c * my
-        out += a * np.exp(-((x - rx) ** 2 + (y - ry) ** 2 + (z - mz) ** 2) / (2.0 * sg * sg))
+        # exp of a sum of squares = product of per-axis factors
+        k = 1.0 / (2.0 * sg * sg)
+        gx, gy, gz = (np.exp(-((ax[i] - m) ** 2) * k) for i, m in enumerate((rx, ry, mz)))
+        out += a * gz[:, None, None] * (gy[:, None] * gx[None, :])[None]
     return out
 
 
