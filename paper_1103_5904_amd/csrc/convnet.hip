@@ -65,6 +65,34 @@ __device__ inline float read_scale(const double *norm2)
 
 // ------------------------------------------------------------- forward
 
+// Forward kernels work on output tiles of 16 x 4 x 4 voxels (one per
+// workgroup, on a 3-D grid: no index division).  The tile's input region
+// with its one-voxel halo (18 x 6 x 6) is staged in LDS once, zero outside
+// the volume, and every tap reads LDS instead of re-gathering from L2.
+constexpr int kTX = 16, kTY = 4, kTZ = 4;
+constexpr int kRX = kTX + 2, kRY = kTY + 2, kRZ = kTZ + 2, kRegion = kRX * kRY * kRZ;
+
+__device__ inline int region_index(int lx, int ly, int lz, int t)
+{
+    return ((lz + t / 9) * kRY + (ly + (t / 3) % 3)) * kRX + lx + t % 3;
+}
+
+// Stages the [voxel][16] BF16 region of the tile at (x0, y0, z0) into
+// lds[kRegion * 2] (two 16-byte halves per voxel).
+__device__ inline void stage_channels(const uint16_t *__restrict__ src, const Vol &d, int x0, int y0, int z0,
+                                      uint4 *lds)
+{
+    for (int e = threadIdx.x; e < kRegion * 2; e += kThreads) {
+        const int rv = e >> 1;
+        const int ex = rv % kRX, ey = (rv / kRX) % kRY, ez = rv / (kRX * kRY);
+        const int gx = x0 + ex - 1, gy = y0 + ey - 1, gz = z0 + ez - 1;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
+            v = reinterpret_cast<const uint4 *>(src + (((int64_t)gz * d.ny + gy) * d.nx + gx) * kC)[e & 1];
+        lds[e] = v;
+    }
+}
+
 // layer 1: a1[v][c] = relu(b1[c] + sum_t w1[c][t] x[v + t - 1] / s)
 __global__ __launch_bounds__(kThreads) void k_conv1(const float *__restrict__ P,
                                                     const float *__restrict__ x, Vol d,
@@ -72,35 +100,43 @@ __global__ __launch_bounds__(kThreads) void k_conv1(const float *__restrict__ P,
                                                     uint16_t *__restrict__ a1,
                                                     const int *__restrict__ skip)
 {
+    __shared__ float xs[kRegion];
+    __shared__ float wsh[kC * kTaps + kC];  // w1 then b1 (contiguous in P)
     if (skip && *skip) return;
     const float s = read_scale(norm2);
     const float inv = s > 0.0f ? 1.0f / s : 0.0f;
-    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < d.n;
-         v += (int64_t)gridDim.x * kThreads) {
-        int i, j, k;
-        vox_ijk(d, v, i, j, k);
-        float in[kTaps];
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
+    for (int e = threadIdx.x; e < kRegion; e += kThreads) {
+        const int ex = e % kRX, ey = (e / kRX) % kRY, ez = e / (kRX * kRY);
+        const int gx = x0 + ex - 1, gy = y0 + ey - 1, gz = z0 + ez - 1;
+        float v = 0.0f;
+        if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
+            v = x[((int64_t)gz * d.ny + gy) * d.nx + gx] * inv;
+        xs[e] = v;
+    }
+    for (int e = threadIdx.x; e < kC * kTaps + kC; e += kThreads) wsh[e] = P[OW1 + e];
+    __syncthreads();
+    const int lx = threadIdx.x % kTX, ly = (threadIdx.x / kTX) % kTY, lz = threadIdx.x / (kTX * kTY);
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    if (gx >= d.nx || gy >= d.ny || gz >= d.nz) return;
+    float in[kTaps];
+#pragma unroll
+    for (int t = 0; t < kTaps; ++t) in[t] = xs[region_index(lx, ly, lz, t)];
+    uint32_t packed[8];
+#pragma unroll
+    for (int c = 0; c < kC; c += 2) {
+        float a0 = wsh[kC * kTaps + c], a1v = wsh[kC * kTaps + c + 1];
 #pragma unroll
         for (int t = 0; t < kTaps; ++t) {
-            const int ii = i + t % 3 - 1, jj = j + (t / 3) % 3 - 1, kk = k + t / 9 - 1;
-            const bool ok = ii >= 0 && ii < d.nx && jj >= 0 && jj < d.ny && kk >= 0 && kk < d.nz;
-            in[t] = ok ? x[((int64_t)kk * d.ny + jj) * d.nx + ii] * inv : 0.0f;
+            a0 = fmaf(wsh[c * kTaps + t], in[t], a0);
+            a1v = fmaf(wsh[(c + 1) * kTaps + t], in[t], a1v);
         }
-        uint32_t packed[8];
-#pragma unroll
-        for (int c = 0; c < kC; c += 2) {
-            float a0 = P[OB1 + c], a1v = P[OB1 + c + 1];
-#pragma unroll
-            for (int t = 0; t < kTaps; ++t) {
-                a0 = fmaf(P[OW1 + c * kTaps + t], in[t], a0);
-                a1v = fmaf(P[OW1 + (c + 1) * kTaps + t], in[t], a1v);
-            }
-            packed[c / 2] = (uint32_t)f2bf(fmaxf(a0, 0.0f)) | ((uint32_t)f2bf(fmaxf(a1v, 0.0f)) << 16);
-        }
-        uint4 *dst = reinterpret_cast<uint4 *>(a1 + v * kC);
-        dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-        dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
+        packed[c / 2] = (uint32_t)f2bf(fmaxf(a0, 0.0f)) | ((uint32_t)f2bf(fmaxf(a1v, 0.0f)) << 16);
     }
+    const int64_t v = ((int64_t)gz * d.ny + gy) * d.nx + gx;
+    uint4 *dst = reinterpret_cast<uint4 *>(a1 + v * kC);
+    dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
+    dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
 }
 
 // Weight fragments of the 16 -> 16 layer for MFMA: frag[t][lane] holds
@@ -124,10 +160,11 @@ __global__ void k_conv16_frags(const float *__restrict__ P, int transpose, bf16x
     frag[idx] = f;
 }
 
-// 16 -> 16 convolution on MFMA.  One wavefront per (y, z) row; 16-voxel
-// tiles along x.  out = act(bias + conv) where act is ReLU (relu = 1), or
-// multiplication by [mask > 0] (mask != nullptr, the ReLU derivative of the
-// layer below), or nothing.
+// 16 -> 16 convolution on MFMA.  Each wavefront takes four 16-voxel rows of
+// the tile; per row and tap one v_mfma_f32_16x16x16_bf16 with the weights
+// in registers and the inputs read from the LDS region.  out = act(bias +
+// conv) where act is ReLU (relu = 1), or multiplication by [mask > 0] (mask
+// != nullptr, the ReLU derivative of the layer below), or nothing.
 __global__ __launch_bounds__(kThreads) void k_conv16(const uint16_t *__restrict__ in,
                                                      const bf16x4 *__restrict__ frag,
                                                      const float *__restrict__ bias, Vol d,
@@ -135,12 +172,11 @@ __global__ __launch_bounds__(kThreads) void k_conv16(const uint16_t *__restrict_
                                                      uint16_t *__restrict__ out,
                                                      const int *__restrict__ skip)
 {
+    __shared__ uint4 region[kRegion * 2];
     if (skip && *skip) return;
-    const int lane = threadIdx.x & 63;
-    const int64_t row = (int64_t)blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
-    const int64_t nrows = (int64_t)d.ny * d.nz;
-    if (row >= nrows) return;  // whole wavefront
-    const int j = (int)(row % d.ny), k = (int)(row / d.ny);
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
+    stage_channels(in, d, x0, y0, z0, region);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     bf16x4 w[kTaps];
 #pragma unroll
     for (int t = 0; t < kTaps; ++t) w[t] = frag[t * 64 + lane];
@@ -149,30 +185,22 @@ __global__ __launch_bounds__(kThreads) void k_conv16(const uint16_t *__restrict_
     if (bias)
 #pragma unroll
         for (int r = 0; r < 4; ++r) b[r] = bias[cg + r];
-    for (int x0 = 0; x0 < d.nx; x0 += 16) {
+    __syncthreads();
+    const char *rbytes = reinterpret_cast<const char *>(region);
+    const int xo = x0 + vl;
+    for (int rr = 0; rr < 4; ++rr) {
+        const int ri = wave * 4 + rr;
+        const int ly = ri % kTY, lz = ri / kTY;
         f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int dz = 0; dz < 3; ++dz) {
-            const int kk = k + dz - 1;
-            if (kk < 0 || kk >= d.nz) continue;  // uniform
-#pragma unroll
-            for (int dy = 0; dy < 3; ++dy) {
-                const int jj = j + dy - 1;
-                if (jj < 0 || jj >= d.ny) continue;  // uniform
-                const int64_t rbase = ((int64_t)kk * d.ny + jj) * d.nx;
-#pragma unroll
-                for (int dx = 0; dx < 3; ++dx) {
-                    const int ii = x0 + vl + dx - 1;
-                    bf16x4 bv = {0, 0, 0, 0};
-                    if (ii >= 0 && ii < d.nx)
-                        bv = *reinterpret_cast<const bf16x4 *>(in + (rbase + ii) * kC + cg);
-                    acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[dz * 9 + dy * 3 + dx], bv, acc, 0, 0, 0);
-                }
-            }
+        for (int t = 0; t < kTaps; ++t) {
+            const bf16x4 bv =
+                *reinterpret_cast<const bf16x4 *>(rbytes + region_index(vl, ly, lz, t) * 32 + cg * 2);
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[t], bv, acc, 0, 0, 0);
         }
-        const int xo = x0 + vl;
-        if (xo < d.nx) {
-            const int64_t vo = ((int64_t)k * d.ny + j) * d.nx + xo;
+        const int yo = y0 + ly, zo = z0 + lz;
+        if (xo < d.nx && yo < d.ny && zo < d.nz) {
+            const int64_t vo = ((int64_t)zo * d.ny + yo) * d.nx + xo;
             bf16x4 m = {1, 1, 1, 1};
             if (mask) m = *reinterpret_cast<const bf16x4 *>(mask + vo * kC + cg);
             bf16x4 o;
@@ -197,30 +225,33 @@ __global__ __launch_bounds__(kThreads) void k_conv3(const float *__restrict__ P,
                                                     float *__restrict__ out,
                                                     const int *__restrict__ skip)
 {
+    __shared__ uint4 region[kRegion * 2];
+    __shared__ float wsh[kC * kTaps + 1];  // w3 then b3 (contiguous in P)
     if (skip && *skip) return;
     const float s = read_scale(norm2);
-    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < d.n;
-         v += (int64_t)gridDim.x * kThreads) {
-        int i, j, k;
-        vox_ijk(d, v, i, j, k);
-        float acc = P[OB3];
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
+    stage_channels(a2, d, x0, y0, z0, region);
+    for (int e = threadIdx.x; e < kC * kTaps + 1; e += kThreads) wsh[e] = P[OW3 + e];
+    __syncthreads();
+    const int lx = threadIdx.x % kTX, ly = (threadIdx.x / kTX) % kTY, lz = threadIdx.x / (kTX * kTY);
+    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
+    if (gx >= d.nx || gy >= d.ny || gz >= d.nz) return;
+    float acc = wsh[kC * kTaps];
 #pragma unroll 3
-        for (int t = 0; t < kTaps; ++t) {
-            const int ii = i + t % 3 - 1, jj = j + (t / 3) % 3 - 1, kk = k + t / 9 - 1;
-            if (ii < 0 || ii >= d.nx || jj < 0 || jj >= d.ny || kk < 0 || kk >= d.nz) continue;
-            const uint4 *src = reinterpret_cast<const uint4 *>(a2 + (((int64_t)kk * d.ny + jj) * d.nx + ii) * kC);
-            const uint4 lo = src[0], hi = src[1];
-            const uint32_t wds[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    for (int t = 0; t < kTaps; ++t) {
+        const int rv = region_index(lx, ly, lz, t);
+        const uint4 lo = region[2 * rv], hi = region[2 * rv + 1];
+        const uint32_t wds[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
 #pragma unroll
-            for (int c = 0; c < kC; c += 2) {
-                acc = fmaf(P[OW3 + c * kTaps + t], bf2f((uint16_t)(wds[c / 2] & 0xffffu)), acc);
-                acc = fmaf(P[OW3 + (c + 1) * kTaps + t], bf2f((uint16_t)(wds[c / 2] >> 16)), acc);
-            }
+        for (int c = 0; c < kC; c += 2) {
+            acc = fmaf(wsh[c * kTaps + t], bf2f((uint16_t)(wds[c / 2] & 0xffffu)), acc);
+            acc = fmaf(wsh[(c + 1) * kTaps + t], bf2f((uint16_t)(wds[c / 2] >> 16)), acc);
         }
-        float o = s * acc;
-        if (map_mask && !map_mask[v]) o = 0.0f;
-        out[v] = o;
     }
+    const int64_t v = ((int64_t)gz * d.ny + gy) * d.nx + gx;
+    float o = s * acc;
+    if (map_mask && !map_mask[v]) o = 0.0f;
+    out[v] = o;
 }
 
 // ------------------------------------------------------------ training
@@ -445,6 +476,12 @@ size_t convnet_forward_ws_bytes(int64_t n)
     return align256(sizeof(uint16_t) * kC * n) * 2 + align256(sizeof(bf16x4) * kTaps * 64);
 }
 
+static dim3 tile_grid(const Vol &d)
+{
+    return dim3((unsigned)((d.nx + kTX - 1) / kTX), (unsigned)((d.ny + kTY - 1) / kTY),
+                (unsigned)((d.nz + kTZ - 1) / kTZ));
+}
+
 static unsigned vox_blocks(int64_t n)
 {
     int64_t b = (n + kThreads - 1) / kThreads;
@@ -465,12 +502,10 @@ int convnet_forward_dev(const tomo_cube &c, const float *P, const float *x, floa
     bf16x4 *frag = (bf16x4 *)(base + 2 * align256(sizeof(uint16_t) * kC * d.n));
     if (prep_frags)
         hipLaunchKernelGGL(k_conv16_frags, dim3((kTaps * 64 + 255) / 256), dim3(256), 0, s, P, 0, frag);
-    hipLaunchKernelGGL(k_conv1, dim3(vox_blocks(d.n)), dim3(kThreads), 0, s, P, x, d, norm2, a1, skip);
-    const int64_t nrows = (int64_t)d.ny * d.nz;
-    hipLaunchKernelGGL(k_conv16, dim3((unsigned)((nrows + 3) / 4)), dim3(kThreads), 0, s, a1, frag,
-                       P + OB2, d, 1, (const uint16_t *)nullptr, a2, skip);
-    hipLaunchKernelGGL(k_conv3, dim3(vox_blocks(d.n)), dim3(kThreads), 0, s, P, a2, d, norm2, map_mask,
-                       out, skip);
+    hipLaunchKernelGGL(k_conv1, tile_grid(d), dim3(kThreads), 0, s, P, x, d, norm2, a1, skip);
+    hipLaunchKernelGGL(k_conv16, tile_grid(d), dim3(kThreads), 0, s, a1, frag, P + OB2, d, 1,
+                       (const uint16_t *)nullptr, a2, skip);
+    hipLaunchKernelGGL(k_conv3, tile_grid(d), dim3(kThreads), 0, s, P, a2, d, norm2, map_mask, out, skip);
     return hip_fail(hipGetLastError(), "convnet forward launch");
 }
 
@@ -520,18 +555,17 @@ static int convnet_train_pass(const tomo_cube *cube, const float *params_d, cons
     NetWs w;
     ws_layout(n, &w, (char *)ws_d);
     const Vol d{cube->nx, cube->ny, cube->nz, n};
-    const int64_t nrows = (int64_t)d.ny * d.nz;
-    const dim3 rowgrid((unsigned)((nrows + 3) / 4));
+    const dim3 rowgrid = tile_grid(d);
     // forward, keeping activations
     hipLaunchKernelGGL(k_conv16_frags, dim3((kTaps * 64 + 255) / 256), dim3(256), 0, s, params_d, 0, w.frag);
     hipLaunchKernelGGL(k_conv16_frags, dim3((kTaps * 64 + 255) / 256), dim3(256), 0, s, params_d, 1, w.fragT);
     const int *noskip = nullptr;
-    hipLaunchKernelGGL(k_conv1, dim3(vox_blocks(n)), dim3(kThreads), 0, s, params_d, x_d, d,
+    hipLaunchKernelGGL(k_conv1, rowgrid, dim3(kThreads), 0, s, params_d, x_d, d,
                        (const double *)nullptr, w.a1, noskip);
     hipLaunchKernelGGL(k_conv16, rowgrid, dim3(kThreads), 0, s, w.a1, w.frag, params_d + OB2, d, 1,
                        (const uint16_t *)nullptr, w.a2, noskip);
     if (target_d) {
-        hipLaunchKernelGGL(k_conv3, dim3(vox_blocks(n)), dim3(kThreads), 0, s, params_d, w.a2, d,
+        hipLaunchKernelGGL(k_conv3, rowgrid, dim3(kThreads), 0, s, params_d, w.a2, d,
                            (const double *)nullptr, (const uint8_t *)nullptr, w.out, noskip);
         // loss and d loss / d out
         hipLaunchKernelGGL(k_mse, dim3(kLossBlocks), dim3(kThreads), 0, s, w.out, target_d, n, w.g,
