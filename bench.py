@@ -34,6 +34,29 @@ sys.path.insert(0, ROOT)
 METRIC = "Siddon P/Pᵀ voxel-crossings/s; time to rel. residual 1e-3 (learned vs plain)"
 HBM_PEAK_GBS = 8000.0
 
+# HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes on this workload (scaled by a
+# 256 MiB copy's counts; profiles/euvi128_cg50_blocked_backprojection.md), valid only for the kernel
+# sources they were taken on: sha256 over the listed files, first 16 hex digits.
+TRAFFIC = {
+    "k_backproject_blocked": (210.4e6, "cbd4ee9c9fb8d714",
+                              ["blocked.h", "blocked.hip", "walk.h", "common.h"]),
+    "k_project": (264.5e6, None, ["siddon.hip", "walk.h", "common.h"]),
+}
+
+
+def measured_traffic(kernel):
+    """The profiled HBM bytes of `kernel`, or None if its sources changed since."""
+    import hashlib
+
+    if kernel not in TRAFFIC:
+        return None
+    nbytes, digest, files = TRAFFIC[kernel]
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_1103_5904_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return nbytes if digest is not None and h.hexdigest()[:16] == digest else None
+
 
 def log(msg):
     """Progress on stderr (stdout carries only the result line)."""
@@ -258,7 +281,7 @@ def main():
                     "project_crossings_per_s": crossings / (ms_p * 1e-3),
                     "backproject_crossings_per_s": crossings / (ms_bp * 1e-3)},
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom)},
     }
     log(f"timed steps done: {ms_step:.1f} ms per step")
     if not args.no_learned:
