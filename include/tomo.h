@@ -83,7 +83,7 @@ typedef struct tomo_view {
     double v[3];        /* unit vector along +row in the tangent plane          */
     double cdelt[2];    /* tangent-plane radians per pixel (column, row), != 0  */
     double crpix[2];    /* 0-based pixel position of the tangent point          */
-    int32_t ncol, nrow; /* image size, each >= 1                                */
+    int32_t ncol, nrow; /* image size, each in 1..65535                         */
     int32_t frame;      /* time frame seen by this view, 0..nframes-1           */
     int32_t reserved;   /* set to 0                                             */
 } tomo_view;

@@ -88,8 +88,9 @@ static int validate_geometry_impl(const tomo_geometry *g, int64_t *npix_out)
             return set_error(TOMO_EINVAL, "view %d: cdelt must be finite and non-zero", k);
         if (!isfinite(v.crpix[0]) || !isfinite(v.crpix[1]))
             return set_error(TOMO_EINVAL, "view %d: crpix must be finite", k);
-        if (v.ncol < 1 || v.nrow < 1)
-            return set_error(TOMO_EINVAL, "view %d: image size %d x %d is invalid", k, v.ncol, v.nrow);
+        if (v.ncol < 1 || v.nrow < 1 || v.ncol > 65535 || v.nrow > 65535)
+            return set_error(TOMO_EINVAL, "view %d: image size %d x %d is invalid (1..65535 each)", k, v.ncol,
+                             v.nrow);
         if (v.frame < 0 || v.frame >= g->cube.nframes)
             return set_error(TOMO_EINVAL, "view %d: frame %d outside [0, %d)", k, v.frame, g->cube.nframes);
         npix += (int64_t)v.ncol * v.nrow;
@@ -143,6 +144,7 @@ static int build_plan(const tomo_geometry *g, int64_t npix, Plan &p)
         gd.lo[a] = c.box_min[a];
         gd.hi[a] = c.box_max[a];
         gd.delta[a] = (c.box_max[a] - c.box_min[a]) / (double)gd.n[a];
+        gd.inv_delta[a] = 1.0 / gd.delta[a];
     }
     gd.nvox = (int64_t)c.nx * c.ny * c.nz;
     std::vector<ViewDev> hv((size_t)g->nviews);

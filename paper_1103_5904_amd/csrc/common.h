@@ -36,6 +36,7 @@ struct GridDev {
     double lo[3];
     double hi[3];
     double delta[3];
+    double inv_delta[3];  // 1 / delta
     int64_t nvox;       // voxels per frame
 };
 

@@ -21,6 +21,17 @@ struct RayState {
 
 __device__ inline int clampi(int v, int lo, int hi) { return v < lo ? lo : (v > hi ? hi : v); }
 
+// n / d from a reciprocal inv ~ 1/d and one residual correction: the
+// residual n - q d is exact in FP64 (fma), and q + r inv lands on the exactly
+// rounded quotient whenever that quotient is representable, and within an
+// ulp otherwise.  So equal quotients from equal data stay equal (ties
+// between axes, entries exactly on a plane) at a fraction of a division.
+__device__ inline double qdiv(double n, double d, double inv)
+{
+    const double q = n * inv;
+    return fma(fma(-q, d, n), inv, q);
+}
+
 // Line of sight through pixel (col, row): gnomonic pinhole d = w + x u + y v.
 // Returns false if the half-line misses the (half-open) box.
 // Per-axis entry state, for kernels that need voxel coordinates.
@@ -40,14 +51,18 @@ __device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, in
     for (int a = 0; a < 3; ++a) d[a] = v.w[a] + x * v.u[a] + y * v.v[a];
     r.dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
 
-    // slab clip of t >= 0 against the box
+    // slab clip of t >= 0 against the box (one division per axis, the
+    // other quotients from its reciprocal)
+    double inv[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) inv[a] = d[a] != 0.0 ? 1.0 / d[a] : 0.0;
     double tin = 0.0, tout = kFar;
     bool inside = true;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         if (d[a] != 0.0) {
-            const double t1 = (g.lo[a] - v.o[a]) / d[a];
-            const double t2 = (g.hi[a] - v.o[a]) / d[a];
+            const double t1 = qdiv(g.lo[a] - v.o[a], d[a], inv[a]);
+            const double t2 = qdiv(g.hi[a] - v.o[a], d[a], inv[a]);
             tin = fmax(tin, fmin(t1, t2));
             tout = fmin(tout, fmax(t1, t2));
         } else {
@@ -65,12 +80,12 @@ __device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, in
         if (d[a] != 0.0) {
             // voxel entered first: half-open voxels, so a ray starting on a
             // plane belongs to the voxel on the side it moves into
-            const double p = (v.o[a] + tin * d[a] - g.lo[a]) / g.delta[a];
+            const double p = qdiv(v.o[a] + tin * d[a] - g.lo[a], g.delta[a], g.inv_delta[a]);
             const bool up = d[a] > 0.0;
             int i = up ? clampi((int)floor(p), 0, N - 1) : clampi((int)ceil(p) - 1, 0, N - 1);
             const double k0 = up ? (double)(i + 1) : (double)i;  // first plane ahead
-            sf[a] = (g.lo[a] + k0 * g.delta[a] - v.o[a]) / d[a] - tin;
-            ds[a] = g.delta[a] / fabs(d[a]);
+            sf[a] = qdiv(g.lo[a] + k0 * g.delta[a] - v.o[a], d[a], inv[a]) - tin;
+            ds[a] = qdiv(g.delta[a], fabs(d[a]), fabs(inv[a]));
             jface[a] = up ? (double)N - k0 : k0;  // crossings to reach the far face
             int kplane = (int)k0;
             if (sf[a] <= 0.0) {  // rounding put the entry just before plane k0
@@ -83,7 +98,9 @@ __device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, in
             if (ax) ax->k0[a] = kplane;
             r.st[a] = up ? stride[a] : -stride[a];
         } else {
-            idx[a] = clampi((int)floor((v.o[a] - g.lo[a]) / g.delta[a]), 0, N - 1);
+            // an observer exactly on a plane (k delta from the face) gives k,
+            // the voxel above it
+            idx[a] = clampi((int)floor(qdiv(v.o[a] - g.lo[a], g.delta[a], g.inv_delta[a])), 0, N - 1);
             if (ax) ax->k0[a] = 0;
             sf[a] = kFar;
             ds[a] = 0.0;
