@@ -274,7 +274,7 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
         b->nitems += bs.items;
         b->nviews += p->nviews;
         if (bs.splits > 1) part_floats += (int64_t)bs.splits * sd.ntot;
-        const size_t lds = sizeof(unsigned long long) * (size_t)bs.b[0] * bs.b[1] * bs.b[2];
+        const size_t lds = sizeof(unsigned long long) * ((size_t)bs.b[0] * bs.b[1] * bs.b[2] + 1);  // + dummy bin
         b->lds_bytes = lds > b->lds_bytes ? lds : b->lds_bytes;
         b->plans.push_back(p);
         b->geoms.push_back(systems[k]);

@@ -103,13 +103,20 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
     const bool finite = ybits < 0x7f800000u;
     const double ymax = (double)__builtin_bit_cast(float, ybits);
     const double vdiag = sqrt(g.delta[0] * g.delta[0] + g.delta[1] * g.delta[1] + g.delta[2] * g.delta[2]);
-    int eb = 0;
-    (void)frexp(fmax(rays, 1.0) * vdiag * ymax * 1.0000001, &eb);  // bound on any bin < 2^eb
+    // scale 2^(61 - eb): every bin below 2^61 (at most `rays` contributions
+    // of at most vdiag max|y| each) and every single contribution below 2^50,
+    // so that adding 1.5 * 2^52 rounds it to an integer held in the low
+    // mantissa bits
+    int eb = 0, e1 = 0;
+    (void)frexp(fmax(rays, 1.0) * vdiag * ymax * 1.0000001, &eb);
+    (void)frexp(vdiag * ymax * 1.0000001, &e1);
+    eb = eb > e1 + 11 ? eb : e1 + 11;
     const double fx_scale = ldexp(1.0, 61 - eb), fx_inv = ldexp(1.0, eb - 61);
     float *fbins = reinterpret_cast<float *>(bins);
 
     __syncthreads();  // the previous item of this workgroup is done with the bins
-    for (int i = threadIdx.x; i < nbins; i += kThreads) bins[i] = 0ull;
+    for (int i = threadIdx.x; i <= nbins; i += kThreads) bins[i] = 0ull;  // + the dummy bin
+    unsigned spills = 0u;
 
     int dc = 0, dr = 0;
     tile_lane(log2_bw, dc, dr);
@@ -211,26 +218,38 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 loc += (idx - blo[a]) * lstride[a];
             }
             const double wys = (double)yv * r.dn * (finite ? fx_scale : 1.0);
-            double scur = E;
-            for (int it = 0; it < bd.maxit; ++it) {
-                const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
-                if ((uint32_t)loc < (uint32_t)nbins) {
-                    if (finite) atomicAdd(&bins[loc], (unsigned long long)(long long)rint((m - scur) * wys));
-                    else atomicAdd(&fbins[loc], (float)((m - scur) * wys));
-                } else {
-                    atomicAdd(spill, 1u);
-                }
-                if (m >= X) break;
+            // a segment outside the box (never expected) lands in the dummy
+            // bin nbins and is counted instead of branching per step
+            auto walk = [&](auto deposit) {
+                double scur = E;
+                for (int it = 0; it < bd.maxit; ++it) {
+                    const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
+                    const bool in = (uint32_t)loc < (uint32_t)nbins;
+                    spills += in ? 0u : 1u;
+                    deposit(in ? loc : nbins, (m - scur) * wys);
+                    if (m >= X) break;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    const bool tie = (r.s[a] == m);
-                    r.s[a] += tie ? r.ds[a] : 0.0;
-                    loc += tie ? lst[a] : 0;
+                    for (int a = 0; a < 3; ++a) {
+                        const bool tie = (r.s[a] == m);
+                        r.s[a] = fma(r.ds[a], tie_factor(tie), r.s[a]);
+                        loc += tie ? lst[a] : 0;
+                    }
+                    scur = m;
                 }
-                scur = m;
+            };
+            if (finite) {
+                walk([&](int32_t l, double v) {
+                    // v + 1.5 * 2^52 rounds v to an integer (|v| < 2^50) in the low bits
+                    const double t = v + 6755399441055744.0;
+                    const long long q = (long long)__builtin_bit_cast(uint64_t, t) - 0x4338000000000000ll;
+                    atomicAdd(&bins[l], (unsigned long long)q);
+                });
+            } else {
+                walk([&](int32_t l, double v) { atomicAdd(&fbins[l], (float)v); });
             }
         }
     }
+    if (spills) atomicAdd(spill, spills);
     __syncthreads();
 
     // ---- write the block once

@@ -145,7 +145,7 @@ int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const floa
     bd.splits = bs.splits;
     bd.maxit = bs.b[0] + bs.b[1] + bs.b[2] + 3;
     const Bundle bun{tu.bp_bundle, tu.bp_xcd_remap};
-    const size_t lds = sizeof(unsigned long long) * (size_t)bs.b[0] * bs.b[1] * bs.b[2];
+    const size_t lds = sizeof(unsigned long long) * ((size_t)bs.b[0] * bs.b[1] * bs.b[2] + 1);  // + dummy bin
     float *dst = bs.splits == 1 ? cube : part;
     const int acc = accumulate ? 1 : 0;
 #define TOMO_LAUNCH_BK(M, D)                                                                            \

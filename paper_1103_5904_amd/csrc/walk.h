@@ -140,6 +140,13 @@ __device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, in
     return true;
 }
 
+// 1.0 if t else 0.0: only the high word differs, so one select; fma(ds, f,
+// s) then equals s + ds or s exactly.
+__device__ inline double tie_factor(bool t)
+{
+    return __builtin_bit_cast(double, (uint64_t)(t ? 0x3FF00000u : 0u) << 32);
+}
+
 // Walk the ray voxel by voxel.  visit(off, dl) receives the flat voxel
 // offset and the parameter length of the segment (length = dl * |d|).
 // Simultaneous crossings advance every tied axis in one step.  maxit bounds
@@ -155,7 +162,7 @@ __device__ inline void ray_walk(RayState &r, int maxit, Visit &&visit)
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool t = (r.s[a] == m);
-            r.s[a] += t ? r.ds[a] : 0.0;  // exact on the common grid
+            r.s[a] = fma(r.ds[a], tie_factor(t), r.s[a]);  // s + ds or s, exact on the common grid
             r.off += t ? r.st[a] : 0;
         }
         scur = m;
