@@ -200,9 +200,11 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 if (r.ds[a] != 0.0) {
                     int j = 0;
                     if (E >= r.s[a]) {
-                        // the quotient is within one of the count; settle it
-                        // with exact comparisons on the grid
-                        j = max((int)floor((E - r.s[a]) / r.ds[a]) + 1, 1);
+                        // the estimate from the unrounded spacing is within
+                        // one of the count (a capped spacing only makes it
+                        // smaller, where the count is 1); settle it with exact
+                        // comparisons on the grid
+                        j = max((int)floor((E - r.s[a]) * ax.rds[a]) + 1, 1);
 #pragma unroll
                         for (int fix = 0; fix < 2; ++fix) {
                             j -= (j > 1 && r.s[a] + (double)(j - 1) * r.ds[a] > E) ? 1 : 0;

@@ -36,9 +36,10 @@ __device__ inline double qdiv(double n, double d, double inv)
 // Returns false if the half-line misses the (half-open) box.
 // Per-axis entry state, for kernels that need voxel coordinates.
 struct RayAxes {
-    int idx[3];  // entry voxel index on each axis
-    int k0[3];   // index of the first plane crossed on each axis (after the entry)
-    double tin;  // ray parameter of the entry point
+    int idx[3];     // entry voxel index on each axis
+    int k0[3];      // index of the first plane crossed on each axis (after the entry)
+    double tin;     // ray parameter of the entry point
+    double rds[3];  // ~1 / (spacing) before its rounding to the grid (0: axis not crossed)
 };
 
 __device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, int row,
@@ -95,13 +96,19 @@ __device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, in
                 kplane += up ? 1 : -1;
             }
             idx[a] = i;
-            if (ax) ax->k0[a] = kplane;
+            if (ax) {
+                ax->k0[a] = kplane;
+                ax->rds[a] = fabs(d[a]) * g.inv_delta[a];
+            }
             r.st[a] = up ? stride[a] : -stride[a];
         } else {
             // an observer exactly on a plane (k delta from the face) gives k,
             // the voxel above it
             idx[a] = clampi((int)floor(qdiv(v.o[a] - g.lo[a], g.delta[a], g.inv_delta[a])), 0, N - 1);
-            if (ax) ax->k0[a] = 0;
+            if (ax) {
+                ax->k0[a] = 0;
+                ax->rds[a] = 0.0;
+            }
             sf[a] = kFar;
             ds[a] = 0.0;
             jface[a] = 0.0;
