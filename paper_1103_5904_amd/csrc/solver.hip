@@ -22,7 +22,7 @@
 
 namespace tomo {
 
-constexpr int kRedBlocks = 1024;  // workgroups of every reducing vector kernel
+constexpr int kRedBlocks = 1024;  // workgroups of every reducing vector kernel (at most)
 
 struct CgState {
     double rr;        // r.r (plain CG) or z.r (flexible CG) of the current iterate
@@ -61,17 +61,44 @@ struct Dims {
     int64_t total;  // nvox * nf
 };
 
+// Voxel coordinates of a flat index: frame f, in-frame offset rem and
+// (i, j, k).  32-bit arithmetic when the whole vector has < 2^31 entries
+// (64-bit divisions are long instruction sequences on the GPU).
+struct VoxIdx {
+    int64_t f, rem;
+    int32_t i, j, k;
+};
+
+__device__ inline VoxIdx vox_index(const Dims &d, int64_t idx)
+{
+    VoxIdx o;
+    if (d.total < ((int64_t)1 << 31)) {
+        const uint32_t u = (uint32_t)idx, nv = (uint32_t)d.nvox;
+        const uint32_t f = u / nv, rem = u - f * nv;
+        const uint32_t jk = rem / (uint32_t)d.nx;
+        o.f = f;
+        o.rem = rem;
+        o.i = (int32_t)(rem - jk * (uint32_t)d.nx);
+        o.k = (int32_t)(jk / (uint32_t)d.ny);
+        o.j = (int32_t)(jk - (uint32_t)o.k * (uint32_t)d.ny);
+    } else {
+        o.f = idx / d.nvox;
+        o.rem = idx - o.f * d.nvox;
+        o.i = (int32_t)(o.rem % d.nx);
+        const int64_t jk = o.rem / d.nx;
+        o.j = (int32_t)(jk % d.ny);
+        o.k = (int32_t)(jk / d.ny);
+    }
+    return o;
+}
+
 // lambda_r (D^T D x)_v + lambda_t (D_t^T D_t x)_v: forward differences
 // between in-range neighbours only (free ends).
-__device__ inline float prior_at(const float *__restrict__ x, const Dims &d, int64_t idx, float lr,
-                                 float lt)
+__device__ inline float prior_at(const float *__restrict__ x, const Dims &d, int64_t idx, const VoxIdx &c_,
+                                 float lr, float lt)
 {
-    const int64_t f = idx / d.nvox;
-    const int64_t rem = idx - f * d.nvox;
-    const int32_t i = (int32_t)(rem % d.nx);
-    const int64_t jk = rem / d.nx;
-    const int32_t j = (int32_t)(jk % d.ny);
-    const int32_t k = (int32_t)(jk / d.ny);
+    const int32_t i = c_.i, j = c_.j, k = c_.k;
+    const int64_t f = c_.f;
     const float c = x[idx];
     float s = 0.0f;
     if (i > 0) s += c - x[idx - 1];
@@ -97,7 +124,7 @@ __global__ __launch_bounds__(kThreads) void k_prior(const float *__restrict__ x,
 {
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
          i += (int64_t)gridDim.x * kThreads) {
-        const float v = prior_at(x, d, i, lr, lt);
+        const float v = prior_at(x, d, i, vox_index(d, i), lr, lt);
         out[i] = accumulate ? out[i] + v : v;
     }
 }
@@ -125,12 +152,24 @@ __device__ inline bool grid_reduce(const double (&a)[NV], const Workspace &ws, d
     __syncthreads();
     if (!last) return false;
     __threadfence();
+    // every load of this thread issued before any is summed (one memory
+    // latency instead of one per partial); partials in a fixed order
     double pa[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) pa[k] = 0.0;
-    for (int i = threadIdx.x; i < (int)gridDim.x; i += kThreads)
+    constexpr int kPer = kRedBlocks / kThreads;
+    double v[kPer][NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) pa[k] += __builtin_nontemporal_load(&ws.partials[4 * i + k]);
+    for (int u = 0; u < kPer; ++u) {
+        const int i = threadIdx.x + u * kThreads;
+#pragma unroll
+        for (int k = 0; k < NV; ++k)
+            v[u][k] = i < (int)gridDim.x ? __builtin_nontemporal_load(&ws.partials[4 * i + k]) : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kPer; ++u)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) pa[k] += v[u][k];
 #pragma unroll
     for (int k = 0; k < NV; ++k) t[k] = block_sum(pa[k], lds);
     if (threadIdx.x == 0) *ws.counter = 0u;
@@ -192,8 +231,9 @@ __global__ __launch_bounds__(kThreads) void k_cg_q(const float *__restrict__ p,
     double pq = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
          i += (int64_t)gridDim.x * kThreads) {
-        float v = q[i] + prior_at(p, d, i, lr, lt);
-        if (map_mask && !map_mask[i % d.nvox]) v = 0.0f;
+        const VoxIdx c = vox_index(d, i);
+        float v = q[i] + prior_at(p, d, i, c, lr, lt);
+        if (map_mask && !map_mask[c.rem]) v = 0.0f;
         q[i] = v;
         pq += (double)p[i] * v;
     }
@@ -375,8 +415,9 @@ __global__ __launch_bounds__(kThreads) void k_true_res(const float *__restrict__
     double rr = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
          i += (int64_t)gridDim.x * kThreads) {
-        float v = q[i] + prior_at(x, d, i, lr, lt);
-        if (map_mask && !map_mask[i % d.nvox]) v = 0.0f;
+        const VoxIdx c = vox_index(d, i);
+        float v = q[i] + prior_at(x, d, i, c, lr, lt);
+        if (map_mask && !map_mask[c.rem]) v = 0.0f;
         q[i] = v;
         const double e = (double)b[i] - v;
         rr += e * e;
@@ -404,7 +445,7 @@ __global__ __launch_bounds__(kThreads) void k_mask(float *__restrict__ x,
 {
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
          i += (int64_t)gridDim.x * kThreads)
-        if (!map_mask[i % d.nvox]) x[i] = 0.0f;
+        if (!map_mask[vox_index(d, i).rem]) x[i] = 0.0f;
 }
 
 // ------------------------------------------------------------ host side

@@ -39,6 +39,8 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=2)
     ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--lr-final", type=float, default=3e-5)
+    ap.add_argument("--init", default=None,
+                    help="start from these weights (.npz) instead of the fitted linear filter")
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--npix", type=int, default=256)
     ap.add_argument("--eval-seeds", type=int, default=3, help="held-out problems, seeds 2000, ...")
@@ -65,7 +67,10 @@ def main(argv=None):
     h = pc.fit_linear_filter(pc.NormalOperator(dg, wl.lam_r), inputs[0:args.records:4])
     log("linear filter fit (kz, ky, kx):\n" + np.array2string(h, precision=4, suppress_small=True))
     lin = pc.linear_filter_params(h)
-    init = lin + 1e-3 * np.random.default_rng(0).normal(size=lin.shape) * (lin == 0)
+    if args.init:
+        init = pc.load(args.init).cpu().numpy().astype(np.float64)
+    else:
+        init = lin + 1e-3 * np.random.default_rng(0).normal(size=lin.shape) * (lin == 0)
     params, losses = pc.train(dg, wl.lam_r, inputs, targets, epochs=args.epochs, lr=args.lr,
                               lr_final=args.lr_final, log=log, init=init)
     t_train = time.perf_counter() - t1
@@ -88,7 +93,7 @@ def main(argv=None):
                       "filter_iters": rf["iters"]})
         log(json.dumps(evals[-1]))
     meta = {"train_seeds": args.train_seeds, "records": args.records, "epochs": args.epochs,
-            "lr": args.lr, "lr_final": args.lr_final, "n": args.n, "npix": args.npix,
+            "lr": args.lr, "lr_final": args.lr_final, "init": args.init, "n": args.n, "npix": args.npix,
             "filter": h.ravel().tolist(), "losses": losses, "train_s": t_train, "pairs_s": t1 - t0, "eval": evals}
     pc.save(args.out, params, meta)
     log(f"wrote {args.out}")
