@@ -226,8 +226,8 @@ size_t tomo_convnet_workspace_bytes(const tomo_cube *cube);
 
 /*
  * out = N(x) on one nx*ny*nz volume (x, out: DEVICE float, x fastest).
- * Hidden activations are BF16 and the 16 -> 16 layer runs on MFMA (BF16
- * inputs, FP32 accumulation); the outer layers accumulate in FP32.
+ * Every layer runs on MFMA with BF16 operands (the input, the weights and
+ * the BF16 hidden activations) and FP32 accumulation.
  * ws_d: DEVICE workspace of at least tomo_convnet_workspace_bytes bytes.
  */
 int tomo_convnet_forward(const tomo_cube *cube, const float *params_d,

@@ -8,16 +8,18 @@
 // gfx950 design:
 // * Hidden activations are BF16, channels-last ([voxel][16], 32 B per voxel),
 //   so one voxel's 16 channels are one contiguous 32-byte run.
-// * The 16 -> 16 layer is a real contraction (6912 MACs per voxel) and runs
-//   on MFMA: for each tap, D[cout][voxel] += W_tap[cout][cin] x X_tap[cin][voxel]
-//   with v_mfma_f32_16x16x16_bf16 over a row tile of 16 voxels.  Lane l
-//   holds A = W_tap[l%16][4(l/16)..+3] (weights, kept in registers for all 27
-//   taps), B = X[voxel l%16][4(l/16)..+3] (one 8-byte load, the 64 lanes
-//   covering 512 contiguous bytes) and D = out[voxel l%16][4(l/16)..+3]
-//   (one 8-byte store).  The same kernel computes the data gradient with
-//   flipped, transposed weights.
-// * The 1 -> 16 and 16 -> 1 layers (432 MACs per voxel) are bandwidth-bound
-//   and run on VALU, weights read as uniform (scalar) loads.
+// * Every layer is a contraction over (tap, input channel) and runs on MFMA
+//   over row tiles of 16 voxels: D[cout][voxel] += A[cout][k] B[k][voxel],
+//   with v_mfma_f32_16x16x32_bf16 taking two taps per instruction (fourteen
+//   instructions for the 27 taps of a 16-channel input), the weights held in
+//   registers and the inputs read from an LDS copy of the tile's region.
+//   D lands as out[voxel l % 16][4 (l / 16) .. +3]: one 8-byte store.  The
+//   same kernel computes the 16 -> 16 data gradient with flipped, transposed
+//   weights.
+// * The 1 -> 16 layer takes its 27 taps as the contraction index; it and the
+//   16 -> 1 layer keep ~16 significant bits of their weights by splitting
+//   them into a BF16 value and a BF16 remainder (for the last layer the two
+//   are rows 0 and 1 of one weight matrix, so the split costs nothing).
 // * Weight gradients are reductions over all voxels: per-block FP64 partial
 //   sums, reduced in a fixed order (deterministic).
 #include <math.h>
@@ -27,6 +29,7 @@
 namespace tomo {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kC = 16;
@@ -35,12 +38,8 @@ constexpr int OW1 = 0, OB1 = 432, OW2 = 448, OB2 = 7360, OW3 = 7376, OB3 = 7808;
 static_assert(OB3 + 1 == TOMO_CONVNET_NPARAMS, "parameter layout");
 constexpr int kWgBlocks = 512;  // blocks of the weight-gradient reductions
 
-__device__ inline uint16_t f2bf(float f)
-{
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    u += 0x7fffu + ((u >> 16) & 1u);  // round to nearest even
-    return (uint16_t)(u >> 16);
-}
+// round to nearest even (gfx950 converts in one instruction)
+__device__ inline uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 
 __device__ inline float bf2f(uint16_t h) { return __builtin_bit_cast(float, (uint32_t)h << 16); }
 
@@ -69,39 +68,157 @@ __device__ inline float read_scale(const double *norm2)
 // workgroup, on a 3-D grid: no index division).  The tile's input region
 // with its one-voxel halo (18 x 6 x 6) is staged in LDS once, zero outside
 // the volume, and every tap reads LDS instead of re-gathering from L2.
+// Wavefront w takes the four 16-voxel rows (y = 0..3, z = w) of the tile,
+// interleaved so that four independent MFMA accumulations are in flight.
 constexpr int kTX = 16, kTY = 4, kTZ = 4;
 constexpr int kRX = kTX + 2, kRY = kTY + 2, kRZ = kTZ + 2, kRegion = kRX * kRY * kRZ;
+static_assert(kTY == 4 && kTZ * 64 == kThreads, "one wavefront per tile z, four rows each");
 
+// region entry of output voxel (lx, ly, lz) of the tile at tap t
 __device__ inline int region_index(int lx, int ly, int lz, int t)
 {
     return ((lz + t / 9) * kRY + (ly + (t / 3) % 3)) * kRX + lx + t % 3;
 }
 
-// Stages the [voxel][16] BF16 region of the tile at (x0, y0, z0) into
-// lds[kRegion * 2] (two 16-byte halves per voxel).
+// Stages the [voxel][16] BF16 region of the tile at (x0, y0, z0) into LDS as
+// two planes of kRegion 16-byte entries: plane h holds channels 8h..8h+7.
+// Sixteen lanes reading one plane at sixteen consecutive voxels then cover
+// 256 contiguous bytes (no bank conflicts).
 __device__ inline void stage_channels(const uint16_t *__restrict__ src, const Vol &d, int x0, int y0, int z0,
                                       uint4 *lds)
 {
     for (int e = threadIdx.x; e < kRegion * 2; e += kThreads) {
-        const int rv = e >> 1;
+        const int rv = e >> 1, h = e & 1;
         const int ex = rv % kRX, ey = (rv / kRX) % kRY, ez = rv / (kRX * kRY);
         const int gx = x0 + ex - 1, gy = y0 + ey - 1, gz = z0 + ez - 1;
         uint4 v = make_uint4(0u, 0u, 0u, 0u);
         if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
-            v = reinterpret_cast<const uint4 *>(src + (((int64_t)gz * d.ny + gy) * d.nx + gx) * kC)[e & 1];
-        lds[e] = v;
+            v = reinterpret_cast<const uint4 *>(src + (((int64_t)gz * d.ny + gy) * d.nx + gx) * kC)[h];
+        lds[h * kRegion + rv] = v;
     }
 }
 
-// layer 1: a1[v][c] = relu(b1[c] + sum_t w1[c][t] x[v + t - 1] / s)
-__global__ __launch_bounds__(kThreads) void k_conv1(const float *__restrict__ P,
+// MFMA weight fragments.  v_mfma_f32_16x16x32_bf16 computes D(16x16) +=
+// A(16x32) B(32x16) with lane l holding A[l % 16][8 (l / 16) + e] and
+// B[8 (l / 16) + e][l % 16] (e = 0..7) and D[4 (l / 16) + r][l % 16] (r =
+// 0..3); v_mfma_f32_16x16x16_bf16 has the same D with A[l % 16][4 (l / 16) +
+// e], e = 0..3.  A 16 -> C layer contracts over (tap, input channel): one
+// K = 32 instruction takes the tap pair (2p, 2p + 1), k = 16 j + c for tap
+// 2p + j and channel c, so that lane group g = l / 16 reads tap 2p + g / 2
+// from LDS plane g % 2; thirteen pairs, then tap 26 as a K = 16 instruction
+// (k = channel).  Fragment f of a set is the 64 bf16x8 entries [64 f, 64 f +
+// 64); the K = 16 fragment uses elements 0..3.
+//   forward set, kFragFwd entries:
+//   * fragments 0-13: the 16 -> 16 layer, A[cout][k] = W2[cout][c][tap];
+//   * fragments 14-27: the 16 -> 1 layer, row 0 = bf16(W3[0][c][tap]), row 1 =
+//     its remainder W3 - bf16(W3), rows 2-15 zero: output row 0 + row 1 is
+//     the layer with ~16 significant bits of weight at no extra instruction;
+//   * fragments 28-29: the 1 -> 16 layer with the 27 taps as k (27-31 zero),
+//     A[cout][k] = bf16(W1[cout][k]) and its remainder.
+//   transposed set (transpose = 1), kFragConv entries: the 16 -> 16 data
+//   gradient, A[cin][k] = W2[c][cin][26 - tap] (taps flipped).
+constexpr int kPairs = 13;
+constexpr int kConvFrags = kPairs + 1;
+constexpr int kFragConv = kConvFrags * 64;
+constexpr int kFrag3 = kFragConv, kFrag1 = 2 * kFragConv;
+constexpr int kFragFwd = 2 * kFragConv + 2 * 64;
+
+__global__ void k_conv_frags(const float *__restrict__ P, int transpose, bf16x8 *__restrict__ frag)
+{
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (transpose ? kFragConv : kFragFwd)) return;
+    const int f = idx / 64, lane = idx % 64;
+    const int row = lane % 16, g = lane / 16;
+    bf16x8 out;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        float w = 0.0f;
+        if (transpose || f < 2 * kConvFrags) {
+            const int p = f % kConvFrags;
+            const bool tail = p == kPairs;
+            const int tap = tail ? kTaps - 1 : 2 * p + (g >> 1);
+            const int c = tail ? 4 * g + e : 8 * (g & 1) + e;
+            if (tail && e >= 4) {
+                w = 0.0f;
+            } else if (transpose) {
+                w = P[OW2 + (c * kC + row) * kTaps + (kTaps - 1 - tap)];
+            } else if (f < kConvFrags) {
+                w = P[OW2 + (row * kC + c) * kTaps + tap];
+            } else if (row < 2) {
+                w = P[OW3 + c * kTaps + tap];
+                if (row == 1) w -= bf2f(f2bf(w));
+            }
+        } else {
+            const int tap = 8 * g + e;
+            if (tap < kTaps) {
+                w = P[OW1 + row * kTaps + tap];
+                if (f == 2 * kConvFrags + 1) w -= bf2f(f2bf(w));
+            }
+        }
+        out[e] = (short)f2bf(w);
+    }
+    frag[idx] = out;
+}
+
+// Per-lane LDS byte offsets of the B operands of the thirteen tap pairs and
+// the tail tap, for output voxel (vl, 0, lz) of the tile; row y adds y * kRX
+// entries (a compile-time immediate).
+struct ConvOffsets {
+    uint32_t pair[kPairs];
+    uint32_t tail;
+};
+
+__device__ inline ConvOffsets conv_offsets(int vl, int lz, int g)
+{
+    ConvOffsets o;
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p)
+        o.pair[p] = (uint32_t)(((g & 1) * kRegion + region_index(vl, 0, lz, 2 * p + (g >> 1))) * 16);
+    o.tail = (uint32_t)(((g >> 1) * kRegion + region_index(vl, 0, lz, kTaps - 1)) * 16 + (g & 1) * 8);
+    return o;
+}
+
+// acc[y] += sum over taps and channels of A x region, for the four rows of
+// the wavefront; w: the fourteen fragments of a 16 -> C layer in registers.
+__device__ inline void conv_rows(const char *rbytes, const ConvOffsets &o, const bf16x8 (&w)[kPairs],
+                                 const bf16x4 &wt, f32x4 (&acc)[kTY])
+{
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p)
+#pragma unroll
+        for (int y = 0; y < kTY; ++y) {
+            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(rbytes + o.pair[p] + y * kRX * 16);
+            acc[y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[p], bv, acc[y], 0, 0, 0);
+        }
+#pragma unroll
+    for (int y = 0; y < kTY; ++y) {
+        const bf16x4 bv = *reinterpret_cast<const bf16x4 *>(rbytes + o.tail + y * kRX * 16);
+        acc[y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt, bv, acc[y], 0, 0, 0);
+    }
+}
+
+__device__ inline void load_conv_frags(const bf16x8 *__restrict__ frag, int lane, bf16x8 (&w)[kPairs],
+                                       bf16x4 &wt)
+{
+#pragma unroll
+    for (int p = 0; p < kPairs; ++p) w[p] = frag[p * 64 + lane];
+    const bf16x8 t = frag[kPairs * 64 + lane];
+    wt = __builtin_shufflevector(t, t, 0, 1, 2, 3);
+}
+
+// layer 1: a1[v][c] = relu(b1[c] + sum_t w1[c][t] x[v + t - 1] / s), on
+// MFMA with the taps as the contraction index (k = tap, 27-31 with zero
+// weight).  Weights and inputs are each split into a BF16 value and a BF16
+// remainder, and the three products that matter (hi hi, hi lo, lo hi) keep
+// ~16 significant bits: three v_mfma_f32_16x16x32_bf16 per 16-voxel row.
+__global__ __launch_bounds__(kThreads) void k_conv1(const bf16x8 *__restrict__ frag1,
+                                                    const float *__restrict__ P,
                                                     const float *__restrict__ x, Vol d,
                                                     const double *__restrict__ norm2,
                                                     uint16_t *__restrict__ a1,
                                                     const int *__restrict__ skip)
 {
     __shared__ float xs[kRegion];
-    __shared__ float wsh[kC * kTaps + kC];  // w1 then b1 (contiguous in P)
     if (skip && *skip) return;
     const float s = read_scale(norm2);
     const float inv = s > 0.0f ? 1.0f / s : 0.0f;
@@ -114,59 +231,55 @@ __global__ __launch_bounds__(kThreads) void k_conv1(const float *__restrict__ P,
             v = x[((int64_t)gz * d.ny + gy) * d.nx + gx] * inv;
         xs[e] = v;
     }
-    for (int e = threadIdx.x; e < kC * kTaps + kC; e += kThreads) wsh[e] = P[OW1 + e];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const bf16x8 wh = frag1[lane], wl = frag1[64 + lane];  // BF16 weights, remainders
+    const int vl = lane % 16, g = lane / 16, cg = 4 * g;
+    // taps 8g..8g+7 of this lane; taps past 26 read tap 26 (zero weight)
+    int off[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) off[e] = region_index(vl, 0, wave, min(8 * g + e, kTaps - 1));
+    float b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b[r] = P[OB1 + cg + r];
     __syncthreads();
-    const int lx = threadIdx.x % kTX, ly = (threadIdx.x / kTX) % kTY, lz = threadIdx.x / (kTX * kTY);
-    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-    if (gx >= d.nx || gy >= d.ny || gz >= d.nz) return;
-    float in[kTaps];
+    f32x4 acc[kTY];
 #pragma unroll
-    for (int t = 0; t < kTaps; ++t) in[t] = xs[region_index(lx, ly, lz, t)];
-    uint32_t packed[8];
+    for (int y = 0; y < kTY; ++y) {
+        // inputs split the same way: x = bf16(x) + bf16(x - bf16(x)) (+ tiny)
+        bf16x8 xh, xl;
 #pragma unroll
-    for (int c = 0; c < kC; c += 2) {
-        float a0 = wsh[kC * kTaps + c], a1v = wsh[kC * kTaps + c + 1];
-#pragma unroll
-        for (int t = 0; t < kTaps; ++t) {
-            a0 = fmaf(wsh[c * kTaps + t], in[t], a0);
-            a1v = fmaf(wsh[(c + 1) * kTaps + t], in[t], a1v);
+        for (int e = 0; e < 8; ++e) {
+            const float v = xs[off[e] + y * kRX];
+            const uint16_t h = f2bf(v);
+            xh[e] = (short)h;
+            xl[e] = (short)f2bf(v - bf2f(h));
         }
-        packed[c / 2] = (uint32_t)f2bf(fmaxf(a0, 0.0f)) | ((uint32_t)f2bf(fmaxf(a1v, 0.0f)) << 16);
+        acc[y] = f32x4{0.f, 0.f, 0.f, 0.f};
+        acc[y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xh, acc[y], 0, 0, 0);
+        acc[y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xl, acc[y], 0, 0, 0);
+        acc[y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, xh, acc[y], 0, 0, 0);
     }
-    const int64_t v = ((int64_t)gz * d.ny + gy) * d.nx + gx;
-    uint4 *dst = reinterpret_cast<uint4 *>(a1 + v * kC);
-    dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-    dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
-}
-
-// Weight fragments of the 16 -> 16 layer for MFMA: frag[t][lane] holds
-// W[cout = lane%16][cin = 4(lane/16)..+3] at tap t.  With transpose = 1 the
-// fragments are those of the data-gradient convolution:
-// W'[cin][cout][t'] = W[cout][cin][26 - t'] (taps flipped).
-__global__ void k_conv16_frags(const float *__restrict__ P, int transpose, bf16x4 *__restrict__ frag)
-{
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= kTaps * 64) return;
-    const int t = idx / 64, lane = idx % 64;
-    const int row = lane % 16, k0 = 4 * (lane / 16);
-    bf16x4 f;
+    const int xo = x0 + vl, zo = z0 + wave;
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int col = k0 + e;
-        const float w = transpose ? P[OW2 + (col * kC + row) * kTaps + (kTaps - 1 - t)]
-                                  : P[OW2 + (row * kC + col) * kTaps + t];
-        f[e] = (short)f2bf(w);
+    for (int y = 0; y < kTY; ++y) {
+        const int yo = y0 + y;
+        if (xo < d.nx && yo < d.ny && zo < d.nz) {
+            const int64_t vo = ((int64_t)zo * d.ny + yo) * d.nx + xo;
+            bf16x4 o;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o[r] = (short)f2bf(fmaxf(acc[y][r] + b[r], 0.0f));
+            *reinterpret_cast<bf16x4 *>(a1 + vo * kC + cg) = o;
+        }
     }
-    frag[idx] = f;
 }
 
-// 16 -> 16 convolution on MFMA.  Each wavefront takes four 16-voxel rows of
-// the tile; per row and tap one v_mfma_f32_16x16x16_bf16 with the weights
-// in registers and the inputs read from the LDS region.  out = act(bias +
-// conv) where act is ReLU (relu = 1), or multiplication by [mask > 0] (mask
-// != nullptr, the ReLU derivative of the layer below), or nothing.
+// 16 -> 16 convolution on MFMA: fourteen instructions per 16-voxel row with
+// the weights in registers and the inputs read from the LDS region.  out =
+// act(bias + conv) where act is ReLU (relu = 1), or multiplication by
+// [mask > 0] (mask != nullptr, the ReLU derivative of the layer below), or
+// nothing.
 __global__ __launch_bounds__(kThreads) void k_conv16(const uint16_t *__restrict__ in,
-                                                     const bf16x4 *__restrict__ frag,
+                                                     const bf16x8 *__restrict__ frag,
                                                      const float *__restrict__ bias, Vol d,
                                                      int relu, const uint16_t *__restrict__ mask,
                                                      uint16_t *__restrict__ out,
@@ -177,48 +290,47 @@ __global__ __launch_bounds__(kThreads) void k_conv16(const uint16_t *__restrict_
     const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
     stage_channels(in, d, x0, y0, z0, region);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    bf16x4 w[kTaps];
-#pragma unroll
-    for (int t = 0; t < kTaps; ++t) w[t] = frag[t * 64 + lane];
-    const int vl = lane % 16, cg = 4 * (lane / 16);
+    bf16x8 w[kPairs];
+    bf16x4 wt;
+    load_conv_frags(frag, lane, w, wt);
+    const int vl = lane % 16, g = lane / 16, cg = 4 * g;
+    const ConvOffsets o = conv_offsets(vl, wave, g);
     float b[4] = {0.f, 0.f, 0.f, 0.f};
     if (bias)
 #pragma unroll
         for (int r = 0; r < 4; ++r) b[r] = bias[cg + r];
     __syncthreads();
-    const char *rbytes = reinterpret_cast<const char *>(region);
-    const int xo = x0 + vl;
-    for (int rr = 0; rr < 4; ++rr) {
-        const int ri = wave * 4 + rr;
-        const int ly = ri % kTY, lz = ri / kTY;
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+    f32x4 acc[kTY];
 #pragma unroll
-        for (int t = 0; t < kTaps; ++t) {
-            const bf16x4 bv =
-                *reinterpret_cast<const bf16x4 *>(rbytes + region_index(vl, ly, lz, t) * 32 + cg * 2);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[t], bv, acc, 0, 0, 0);
-        }
-        const int yo = y0 + ly, zo = z0 + lz;
+    for (int y = 0; y < kTY; ++y) acc[y] = f32x4{0.f, 0.f, 0.f, 0.f};
+    conv_rows(reinterpret_cast<const char *>(region), o, w, wt, acc);
+    const int xo = x0 + vl, zo = z0 + wave;
+#pragma unroll
+    for (int y = 0; y < kTY; ++y) {
+        const int yo = y0 + y;
         if (xo < d.nx && yo < d.ny && zo < d.nz) {
             const int64_t vo = ((int64_t)zo * d.ny + yo) * d.nx + xo;
             bf16x4 m = {1, 1, 1, 1};
             if (mask) m = *reinterpret_cast<const bf16x4 *>(mask + vo * kC + cg);
-            bf16x4 o;
+            bf16x4 ov;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                float val = acc[r] + b[r];
+                float val = acc[y][r] + b[r];
                 if (relu) val = fmaxf(val, 0.0f);
                 if (mask && !(bf2f((uint16_t)m[r]) > 0.0f)) val = 0.0f;
-                o[r] = (short)f2bf(val);
+                ov[r] = (short)f2bf(val);
             }
-            *reinterpret_cast<bf16x4 *>(out + vo * kC + cg) = o;
+            *reinterpret_cast<bf16x4 *>(out + vo * kC + cg) = ov;
         }
     }
 }
 
 // layer 3: out[v] = s * (b3 + sum_{c,t} w3[c][t] a2[v + t - 1][c]), zero
-// where the map mask is 0.
-__global__ __launch_bounds__(kThreads) void k_conv3(const float *__restrict__ P,
+// where the map mask is 0.  On MFMA like the 16 -> 16 layer with the 1 x 16
+// weight row as rows 0 (BF16 value) and 1 (BF16 remainder) of a 16 x 16
+// matrix: D rows 0 and 1 land in lanes 0-15, elements 0 and 1.
+__global__ __launch_bounds__(kThreads) void k_conv3(const bf16x8 *__restrict__ frag3,
+                                                    const float *__restrict__ P,
                                                     const uint16_t *__restrict__ a2, Vol d,
                                                     const double *__restrict__ norm2,
                                                     const uint8_t *__restrict__ map_mask,
@@ -226,32 +338,33 @@ __global__ __launch_bounds__(kThreads) void k_conv3(const float *__restrict__ P,
                                                     const int *__restrict__ skip)
 {
     __shared__ uint4 region[kRegion * 2];
-    __shared__ float wsh[kC * kTaps + 1];  // w3 then b3 (contiguous in P)
     if (skip && *skip) return;
     const float s = read_scale(norm2);
     const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
     stage_channels(a2, d, x0, y0, z0, region);
-    for (int e = threadIdx.x; e < kC * kTaps + 1; e += kThreads) wsh[e] = P[OW3 + e];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bf16x8 w[kPairs];
+    bf16x4 wt;
+    load_conv_frags(frag3, lane, w, wt);
+    const int vl = lane % 16, g = lane / 16;
+    const ConvOffsets o = conv_offsets(vl, wave, g);
+    const float b3 = P[OB3];
     __syncthreads();
-    const int lx = threadIdx.x % kTX, ly = (threadIdx.x / kTX) % kTY, lz = threadIdx.x / (kTX * kTY);
-    const int gx = x0 + lx, gy = y0 + ly, gz = z0 + lz;
-    if (gx >= d.nx || gy >= d.ny || gz >= d.nz) return;
-    float acc = wsh[kC * kTaps];
-#pragma unroll 3
-    for (int t = 0; t < kTaps; ++t) {
-        const int rv = region_index(lx, ly, lz, t);
-        const uint4 lo = region[2 * rv], hi = region[2 * rv + 1];
-        const uint32_t wds[8] = {lo.x, lo.y, lo.z, lo.w, hi.x, hi.y, hi.z, hi.w};
+    f32x4 acc[kTY];
 #pragma unroll
-        for (int c = 0; c < kC; c += 2) {
-            acc = fmaf(wsh[c * kTaps + t], bf2f((uint16_t)(wds[c / 2] & 0xffffu)), acc);
-            acc = fmaf(wsh[(c + 1) * kTaps + t], bf2f((uint16_t)(wds[c / 2] >> 16)), acc);
+    for (int y = 0; y < kTY; ++y) acc[y] = f32x4{0.f, 0.f, 0.f, 0.f};
+    conv_rows(reinterpret_cast<const char *>(region), o, w, wt, acc);
+    const int xo = x0 + vl, zo = z0 + wave;
+#pragma unroll
+    for (int y = 0; y < kTY; ++y) {
+        const int yo = y0 + y;
+        if (lane < 16 && xo < d.nx && yo < d.ny && zo < d.nz) {
+            const int64_t vo = ((int64_t)zo * d.ny + yo) * d.nx + xo;
+            float ov = s * ((acc[y][0] + acc[y][1]) + b3);
+            if (map_mask && !map_mask[vo]) ov = 0.0f;
+            out[vo] = ov;
         }
     }
-    const int64_t v = ((int64_t)gz * d.ny + gy) * d.nx + gx;
-    float o = s * acc;
-    if (map_mask && !map_mask[v]) o = 0.0f;
-    out[v] = o;
 }
 
 // ------------------------------------------------------------ training
@@ -440,7 +553,7 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
 struct NetWs {
     uint16_t *a1, *a2, *gh;  // [n][16] each
     float *out, *g;          // [n]
-    bf16x4 *frag, *fragT;    // [27][64]
+    bf16x8 *frag, *fragT;    // forward and transposed fragment sets
     double *part;            // weight-gradient partials
     double *loss_part;       // [kRedLossBlocks]
 };
@@ -462,8 +575,8 @@ static size_t ws_layout(int64_t n, NetWs *w, char *base)
     t.gh = (uint16_t *)take(sizeof(uint16_t) * kC * n);
     t.out = (float *)take(sizeof(float) * n);
     t.g = (float *)take(sizeof(float) * n);
-    t.frag = (bf16x4 *)take(sizeof(bf16x4) * kTaps * 64);
-    t.fragT = (bf16x4 *)take(sizeof(bf16x4) * kTaps * 64);
+    t.frag = (bf16x8 *)take(sizeof(bf16x8) * kFragFwd);
+    t.fragT = (bf16x8 *)take(sizeof(bf16x8) * kFragConv);
     t.part = (double *)take(sizeof(double) * kWgBlocks * 6928);
     t.loss_part = (double *)take(sizeof(double) * kLossBlocks);
     if (w) *w = t;
@@ -473,7 +586,7 @@ static size_t ws_layout(int64_t n, NetWs *w, char *base)
 // Forward-only workspace (activations and fragments) for flexible CG.
 size_t convnet_forward_ws_bytes(int64_t n)
 {
-    return align256(sizeof(uint16_t) * kC * n) * 2 + align256(sizeof(bf16x4) * kTaps * 64);
+    return align256(sizeof(uint16_t) * kC * n) * 2 + align256(sizeof(bf16x8) * kFragFwd);
 }
 
 static dim3 tile_grid(const Vol &d)
@@ -499,13 +612,14 @@ int convnet_forward_dev(const tomo_cube &c, const float *P, const float *x, floa
     char *base = (char *)ws;
     uint16_t *a1 = (uint16_t *)base;
     uint16_t *a2 = (uint16_t *)(base + align256(sizeof(uint16_t) * kC * d.n));
-    bf16x4 *frag = (bf16x4 *)(base + 2 * align256(sizeof(uint16_t) * kC * d.n));
+    bf16x8 *frag = (bf16x8 *)(base + 2 * align256(sizeof(uint16_t) * kC * d.n));
     if (prep_frags)
-        hipLaunchKernelGGL(k_conv16_frags, dim3((kTaps * 64 + 255) / 256), dim3(256), 0, s, P, 0, frag);
-    hipLaunchKernelGGL(k_conv1, tile_grid(d), dim3(kThreads), 0, s, P, x, d, norm2, a1, skip);
+        hipLaunchKernelGGL(k_conv_frags, dim3((kFragFwd + 255) / 256), dim3(256), 0, s, P, 0, frag);
+    hipLaunchKernelGGL(k_conv1, tile_grid(d), dim3(kThreads), 0, s, frag + kFrag1, P, x, d, norm2, a1, skip);
     hipLaunchKernelGGL(k_conv16, tile_grid(d), dim3(kThreads), 0, s, a1, frag, P + OB2, d, 1,
                        (const uint16_t *)nullptr, a2, skip);
-    hipLaunchKernelGGL(k_conv3, tile_grid(d), dim3(kThreads), 0, s, P, a2, d, norm2, map_mask, out, skip);
+    hipLaunchKernelGGL(k_conv3, tile_grid(d), dim3(kThreads), 0, s, frag + kFrag3, P, a2, d, norm2, map_mask,
+                       out, skip);
     return hip_fail(hipGetLastError(), "convnet forward launch");
 }
 
@@ -557,15 +671,15 @@ static int convnet_train_pass(const tomo_cube *cube, const float *params_d, cons
     const Vol d{cube->nx, cube->ny, cube->nz, n};
     const dim3 rowgrid = tile_grid(d);
     // forward, keeping activations
-    hipLaunchKernelGGL(k_conv16_frags, dim3((kTaps * 64 + 255) / 256), dim3(256), 0, s, params_d, 0, w.frag);
-    hipLaunchKernelGGL(k_conv16_frags, dim3((kTaps * 64 + 255) / 256), dim3(256), 0, s, params_d, 1, w.fragT);
+    hipLaunchKernelGGL(k_conv_frags, dim3((kFragFwd + 255) / 256), dim3(256), 0, s, params_d, 0, w.frag);
+    hipLaunchKernelGGL(k_conv_frags, dim3((kFragConv + 255) / 256), dim3(256), 0, s, params_d, 1, w.fragT);
     const int *noskip = nullptr;
-    hipLaunchKernelGGL(k_conv1, rowgrid, dim3(kThreads), 0, s, params_d, x_d, d,
+    hipLaunchKernelGGL(k_conv1, rowgrid, dim3(kThreads), 0, s, w.frag + kFrag1, params_d, x_d, d,
                        (const double *)nullptr, w.a1, noskip);
     hipLaunchKernelGGL(k_conv16, rowgrid, dim3(kThreads), 0, s, w.a1, w.frag, params_d + OB2, d, 1,
                        (const uint16_t *)nullptr, w.a2, noskip);
     if (target_d) {
-        hipLaunchKernelGGL(k_conv3, rowgrid, dim3(kThreads), 0, s, params_d, w.a2, d,
+        hipLaunchKernelGGL(k_conv3, rowgrid, dim3(kThreads), 0, s, w.frag + kFrag3, params_d, w.a2, d,
                            (const double *)nullptr, (const uint8_t *)nullptr, w.out, noskip);
         // loss and d loss / d out
         hipLaunchKernelGGL(k_mse, dim3(kLossBlocks), dim3(kThreads), 0, s, w.out, target_d, n, w.g,
