@@ -90,3 +90,23 @@ def sample_pixels(g, count, seed):
 
 def flat_index(g, v, col, row):
     return int(g.view_offsets()[v] + row * g.npix[v][0] + col)
+
+
+STRATEGIES = ["blocked", "binned", "atomic"]
+CODES = {"blocked": 3, "binned": 2, "atomic": 1}
+
+
+def parity_full(tomo, ora, g, x, y, strategies=STRATEGIES):
+    """Every pixel of P and every voxel of P^T (each back-projection
+    strategy) against the oracle."""
+    dg = tomo.DeviceGeometry(g)
+    res = length_resolution(g)
+    img = to_host(tomo.project(dg, to_dev(x)))
+    xm = x if g.map_mask is None else x * (g.map_mask if g.nframes == 1 else g.map_mask[None])
+    assert_p_close(img, ora.project(g, x), ora.project(g, np.abs(xm)), atol=res * np.abs(x).max())
+    ref, refa = ora.backproject(g, y), ora.backproject(g, np.abs(y))
+    for strat in strategies:
+        code = CODES[strat]
+        bp = to_host(tomo.backproject(dg, to_dev(y), strategy=code))
+        assert_p_close(bp, ref, refa, rtol=1e-4, what=f"P^T ({strat})", atol=res * np.abs(y).max())
+        assert tomo.binning_spills(dg) == 0

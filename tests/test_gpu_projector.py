@@ -3,8 +3,8 @@ import numpy as np
 import pytest
 
 import tomo_synth as ts
-from _gpu_common import (assert_p_close, flat_index, length_resolution, need_gpu, oracle_pixels,
-                         sample_pixels, to_dev, to_host)
+from _gpu_common import (CODES, assert_p_close, flat_index, length_resolution, need_gpu, oracle_pixels,
+                         parity_full as _parity_full, sample_pixels, to_dev, to_host)
 
 pytestmark = pytest.mark.gpu
 
@@ -12,26 +12,6 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def tomo():
     return need_gpu()
-
-
-STRATEGIES = ["blocked", "binned", "atomic"]
-CODES = {"blocked": 3, "binned": 2, "atomic": 1}
-
-
-def _parity_full(tomo, ora, g, x, y, strategies=STRATEGIES):
-    """Every pixel of P and every voxel of P^T (each back-projection
-    strategy) against the oracle."""
-    dg = tomo.DeviceGeometry(g)
-    res = length_resolution(g)
-    img = to_host(tomo.project(dg, to_dev(x)))
-    xm = x if g.map_mask is None else x * (g.map_mask if g.nframes == 1 else g.map_mask[None])
-    assert_p_close(img, ora.project(g, x), ora.project(g, np.abs(xm)), atol=res * np.abs(x).max())
-    ref, refa = ora.backproject(g, y), ora.backproject(g, np.abs(y))
-    for strat in strategies:
-        code = CODES[strat]
-        bp = to_host(tomo.backproject(dg, to_dev(y), strategy=code))
-        assert_p_close(bp, ref, refa, rtol=1e-4, what=f"P^T ({strat})", atol=res * np.abs(y).max())
-        assert tomo.binning_spills(dg) == 0
 
 
 def test_tiny_projection_and_transpose(tomo, ora):
