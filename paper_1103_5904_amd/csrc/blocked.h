@@ -194,6 +194,7 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
             // walk state at E: crossings with parameter <= E are done
             int32_t loc = 0;
             int32_t lst[3];
+            bool inblk = true;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
                 int idx = ax.idx[a];
@@ -217,19 +218,26 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 } else {
                     lst[a] = 0;
                 }
+                inblk = inblk && idx >= blo[a] && idx < bhi[a];
                 loc += (idx - blo[a]) * lstride[a];
             }
+            // On the exact grid a walk that starts inside the block stays
+            // inside until X (each axis takes fewer crossings than it needs
+            // to leave), so a start outside it is the only possible spill:
+            // counted, and the ray skipped.
+            if (!inblk) {
+                ++spills;
+                continue;
+            }
             const double wys = (double)yv * r.dn * (finite ? fx_scale : 1.0);
-            // a segment outside the box (never expected) lands in the dummy
-            // bin nbins and is counted instead of branching per step
+            // four steps per loop body, as in ray_walk; the clamp to the
+            // dummy bin nbins only guards the LDS range
             auto walk = [&](auto deposit) {
                 double scur = E;
-                for (int it = 0; it < bd.maxit; ++it) {
+                auto step = [&]() {
                     const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
-                    const bool in = (uint32_t)loc < (uint32_t)nbins;
-                    spills += in ? 0u : 1u;
-                    deposit(in ? loc : nbins, (m - scur) * wys);
-                    if (m >= X) break;
+                    deposit(min((uint32_t)loc, (uint32_t)nbins), (m - scur) * wys);
+                    if (m >= X) return true;
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         const bool tie = (r.s[a] == m);
@@ -237,17 +245,21 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                         loc += tie ? lst[a] : 0;
                     }
                     scur = m;
+                    return false;
+                };
+                for (int it = 0; it < bd.maxit; it += 4) {
+                    if (step() || step() || step() || step()) break;
                 }
             };
             if (finite) {
-                walk([&](int32_t l, double v) {
+                walk([&](uint32_t l, double v) {
                     // v + 1.5 * 2^52 rounds v to an integer (|v| < 2^50) in the low bits
                     const double t = v + 6755399441055744.0;
                     const long long q = (long long)__builtin_bit_cast(uint64_t, t) - 0x4338000000000000ll;
                     atomicAdd(&bins[l], (unsigned long long)q);
                 });
             } else {
-                walk([&](int32_t l, double v) { atomicAdd(&fbins[l], (float)v); });
+                walk([&](uint32_t l, double v) { atomicAdd(&fbins[l], (float)v); });
             }
         }
     }

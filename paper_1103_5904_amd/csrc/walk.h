@@ -157,15 +157,20 @@ __device__ inline double tie_factor(bool t)
 // Walk the ray voxel by voxel.  visit(off, dl) receives the flat voxel
 // offset and the parameter length of the segment (length = dl * |d|).
 // Simultaneous crossings advance every tied axis in one step.  maxit bounds
-// the loop whatever the arithmetic does.
+// the loop whatever the arithmetic does; the loop body holds four steps, so
+// the bound is tested once per four (it may run up to three steps past it).
 template <class Visit>
 __device__ inline void ray_walk(RayState &r, int maxit, Visit &&visit)
 {
     double scur = 0.0;
-    for (int it = 0; it < maxit; ++it) {
+    // The state advances before the segment is visited, so that a gather
+    // of the segment's voxel (issued from its offset at the top of the
+    // step) has the tie updates to arrive in; after the last segment the
+    // advanced state is not used.
+    auto step = [&]() {  // true once the ray has ended
         const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
-        visit(r.off, m - scur);
-        if (m >= r.send) break;
+        const int32_t off = r.off;
+        const double dl = m - scur;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const bool t = (r.s[a] == m);
@@ -173,6 +178,11 @@ __device__ inline void ray_walk(RayState &r, int maxit, Visit &&visit)
             r.off += t ? r.st[a] : 0;
         }
         scur = m;
+        visit(off, dl);
+        return m >= r.send;
+    };
+    for (int it = 0; it < maxit; it += 4) {
+        if (step() || step() || step() || step()) break;
     }
 }
 
@@ -230,18 +240,36 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
     RayState r;
     if ((!kDataMask || data_mask[pix]) && ray_setup(g, v, lp.col, lp.row, r)) {
         const auto rc = make_rsrc(cube + (int64_t)v.frame * g.nvox, (uint32_t)(g.nvox * 4));
-        double acc = 0.0;
+        // software-pipelined by one segment: a step issues its voxel's gather
+        // and adds the previous segment, so each load has a whole step to land
+        double acc = 0.0, dl_prev = 0.0;
+        float x_prev = 0.0f;
         if constexpr (kMapMask) {
             const auto rm = make_rsrc(map_mask, (uint32_t)g.nvox);
             ray_walk(r, maxit, [&](int32_t off, double dl) {
+                acc = fma(dl_prev, (double)x_prev, acc);
                 const float x = buf_load_f32(rc, (uint32_t)off * 4u);
-                acc = fma(dl, buf_load_u8(rm, (uint32_t)off) ? (double)x : 0.0, acc);
+                x_prev = buf_load_u8(rm, (uint32_t)off) ? x : 0.0f;
+                dl_prev = dl;
+            });
+        } else if (g.nvox < ((int64_t)1 << 29)) {
+            // offsets in bytes from here on (below 2^31, so int32 holds them)
+            r.off *= 4;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) r.st[a] *= 4;
+            ray_walk(r, maxit, [&](int32_t off, double dl) {
+                acc = fma(dl_prev, (double)x_prev, acc);
+                x_prev = buf_load_f32(rc, (uint32_t)off);
+                dl_prev = dl;
             });
         } else {
             ray_walk(r, maxit, [&](int32_t off, double dl) {
-                acc = fma(dl, (double)buf_load_f32(rc, (uint32_t)off * 4u), acc);
+                acc = fma(dl_prev, (double)x_prev, acc);
+                x_prev = buf_load_f32(rc, (uint32_t)off * 4u);
+                dl_prev = dl;
             });
         }
+        acc = fma(dl_prev, (double)x_prev, acc);
         out = (float)(acc * r.dn);
     }
     images[pix] = out;
