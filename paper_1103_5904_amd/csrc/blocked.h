@@ -52,10 +52,12 @@ __device__ inline void tile_lane(int log2_bw, int &dc, int &dr)
     dr = (w / wpr) * bh + (l >> log2_bw);
 }
 
-// Shared-memory scratch of one item besides the bins.
+// Shared-memory scratch of one item besides the bins: the pixel rectangles
+// of up to kViewChunk of the owner's views, computed together so that the
+// wavefronts then run through all of them without workgroup barriers.
+constexpr int kViewChunk = 16;
 struct BlockedShared {
-    double cc[8], cr[8];  // detector coordinates of the block's corners
-    int bad;              // a corner lies behind the observer
+    int rect[kViewChunk][4];  // c0, c1, r0, r1 (c0 > c1: the block is not seen)
 };
 
 // One owner item of the blocked P^T: (frame, block, split) from the item
@@ -120,146 +122,185 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
 
     int dc = 0, dr = 0;
     tile_lane(log2_bw, dc, dr);
-    for (int k = v0 + split; k < v1; k += bd.splits) {
-        const ViewDev &v = views[frame_views[k]];
-        // ---- footprint of the block on this view's detector
-        __syncthreads();  // previous view's rectangle no longer in use
-        if (threadIdx.x == 0) sh.bad = 0;
-        __syncthreads();
-        if (threadIdx.x < 8) {
-            const int c = threadIdx.x;
-            const int ci[3] = {(c & 1) ? bhi[0] : blo[0], (c & 2) ? bhi[1] : blo[1], (c & 4) ? bhi[2] : blo[2]};
-            double d[3];
+    const int nvi = v1 - v0 > split ? (v1 - v0 - split + bd.splits - 1) / bd.splits : 0;  // owner's views
+    for (int cs = 0; cs < nvi; cs += kViewChunk) {
+        const int nch = min(kViewChunk, nvi - cs);
+        // ---- footprints: thread 8 j + c projects corner c of the chunk's
+        // view j; the 8 lanes of a view reduce with shuffles
+        __syncthreads();  // the previous chunk's rectangles are no longer in use
+        if (threadIdx.x < 8 * kViewChunk) {
+            const int j = threadIdx.x >> 3, c = threadIdx.x & 7;
+            const bool live = j < nch;
+            const ViewDev &v = views[frame_views[v0 + split + (cs + (live ? j : 0)) * bd.splits]];
+            double cc = 0.0, cr = 0.0;
+            int bad = 0;
+            if (live) {
+                const int ci[3] = {(c & 1) ? bhi[0] : blo[0], (c & 2) ? bhi[1] : blo[1],
+                                   (c & 4) ? bhi[2] : blo[2]};
+                double d[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) d[a] = g.lo[a] + (double)ci[a] * g.delta[a] - v.o[a];
-            const double dep = d[0] * v.w[0] + d[1] * v.w[1] + d[2] * v.w[2];
-            const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
-            if (!(dep > 1e-6 * nd)) {
-                atomicOr(&sh.bad, 1);
-                sh.cc[c] = sh.cr[c] = 0.0;
-            } else {
-                const double x = (d[0] * v.u[0] + d[1] * v.u[1] + d[2] * v.u[2]) / dep;
-                const double y = (d[0] * v.v[0] + d[1] * v.v[1] + d[2] * v.v[2]) / dep;
-                sh.cc[c] = v.cp[0] + x / v.cd[0];
-                sh.cr[c] = v.cp[1] + y / v.cd[1];
+                for (int a = 0; a < 3; ++a) d[a] = g.lo[a] + (double)ci[a] * g.delta[a] - v.o[a];
+                const double dep = d[0] * v.w[0] + d[1] * v.w[1] + d[2] * v.w[2];
+                const double nd = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+                if (!(dep > 1e-6 * nd)) {
+                    bad = 1;  // behind the observer: the whole detector
+                } else {
+                    const double x = (d[0] * v.u[0] + d[1] * v.u[1] + d[2] * v.u[2]) / dep;
+                    const double y = (d[0] * v.v[0] + d[1] * v.v[1] + d[2] * v.v[2]) / dep;
+                    cc = v.cp[0] + x / v.cd[0];
+                    cr = v.cp[1] + y / v.cd[1];
+                }
+            }
+            double cmn = cc, cmx = cc, rmn = cr, rmx = cr;
+#pragma unroll
+            for (int o = 1; o < 8; o <<= 1) {
+                cmn = fmin(cmn, __shfl_xor(cmn, o));
+                cmx = fmax(cmx, __shfl_xor(cmx, o));
+                rmn = fmin(rmn, __shfl_xor(rmn, o));
+                rmx = fmax(rmx, __shfl_xor(rmx, o));
+                bad |= __shfl_xor(bad, o);
+            }
+            if (live && c == 0) {
+                int c0 = 0, c1 = v.ncol - 1, r0 = 0, r1 = v.nrow - 1;
+                if (!bad) {  // clamp in double before converting: far-off corners stay finite
+                    c0 = (int)fmax(floor(cmn) - 1.0, 0.0);
+                    c1 = (int)fmin(ceil(cmx) + 1.0, (double)(v.ncol - 1));
+                    r0 = (int)fmax(floor(rmn) - 1.0, 0.0);
+                    r1 = (int)fmin(ceil(rmx) + 1.0, (double)(v.nrow - 1));
+                }
+                sh.rect[j][0] = c0;
+                sh.rect[j][1] = c1;
+                sh.rect[j][2] = r0;
+                sh.rect[j][3] = r1;
             }
         }
         __syncthreads();
-        int c0 = 0, c1 = v.ncol - 1, r0 = 0, r1 = v.nrow - 1;
-        if (!sh.bad) {
-            double cmn = sh.cc[0], cmx = sh.cc[0], rmn = sh.cr[0], rmx = sh.cr[0];
-#pragma unroll
-            for (int c = 1; c < 8; ++c) {
-                cmn = fmin(cmn, sh.cc[c]);
-                cmx = fmax(cmx, sh.cc[c]);
-                rmn = fmin(rmn, sh.cr[c]);
-                rmx = fmax(rmx, sh.cr[c]);
-            }
-            // clamp in double before converting: far-off corners stay finite
-            c0 = (int)fmax(floor(cmn) - 1.0, 0.0);
-            c1 = (int)fmin(ceil(cmx) + 1.0, (double)(v.ncol - 1));
-            r0 = (int)fmax(floor(rmn) - 1.0, 0.0);
-            r1 = (int)fmin(ceil(rmx) + 1.0, (double)(v.nrow - 1));
-        }
-        if (c0 > c1 || r0 > r1) continue;  // uniform
 
-        // ---- rays of the rectangle, a 16x16 tile per pass
-        const int tx = (c1 - c0) / kTile + 1, ty = (r1 - r0) / kTile + 1;
-        for (int t = 0; t < tx * ty; ++t) {
-            const int col = c0 + (t % tx) * kTile + dc, row = r0 + (t / tx) * kTile + dr;
-            if (col > c1 || row > r1) continue;
-            const int64_t pix = v.pix_off + (int64_t)row * v.ncol + col;
-            const float yv = images[pix];
-            if (!nonzero_bits(yv) || (kDataMask && !data_mask[pix])) continue;
-            RayState r;
-            RayAxes ax;
-            if (!ray_setup(g, v, col, row, r, &ax)) continue;
-            // parameter interval [E, X) inside the block, exact on the ray's grid
-            double E = 0.0, X = r.send;
-            bool hit = true;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                if (r.ds[a] == 0.0) {  // index constant along the ray
-                    hit = hit && ax.idx[a] >= blo[a] && ax.idx[a] < bhi[a];
+        for (int j = 0; j < nch; ++j) {
+            const ViewDev &v = views[frame_views[v0 + split + (cs + j) * bd.splits]];
+            const int c0 = sh.rect[j][0], c1 = sh.rect[j][1], r0 = sh.rect[j][2], r1 = sh.rect[j][3];
+            if (c0 > c1 || r0 > r1) continue;  // uniform
+
+            // ---- rays of the rectangle, a 16x16 tile per pass; each pass loads
+            // the next pass's pixel value so that its latency is hidden by the walk
+            const int tx = (c1 - c0) / kTile + 1, ntile = tx * ((r1 - r0) / kTile + 1);
+            int tcx = 0, tcy = 0;
+            int col = c0 + dc, row = r0 + dr;
+            bool ok = col <= c1 && row <= r1;
+            float ynext = 0.0f;
+            bool mnext = true;
+            if (ok) {
+                const int64_t pix = v.pix_off + (int64_t)row * v.ncol + col;
+                ynext = images[pix];
+                if (kDataMask) mnext = data_mask[pix] != 0;
+            }
+            for (int t = 0; t < ntile; ++t) {
+                const int pcol = col, prow = row;
+                const bool pok = ok, pm = mnext;
+                const float yv = ynext;
+                if (++tcx == tx) {
+                    tcx = 0;
+                    ++tcy;
+                }
+                col = c0 + tcx * kTile + dc;
+                row = r0 + tcy * kTile + dr;
+                ok = t + 1 < ntile && col <= c1 && row <= r1;
+                if (ok) {
+                    const int64_t pix = v.pix_off + (int64_t)row * v.ncol + col;
+                    ynext = images[pix];
+                    if (kDataMask) mnext = data_mask[pix] != 0;
+                }
+                if (!pok || !nonzero_bits(yv) || (kDataMask && !pm)) continue;
+                RayState r;
+                RayAxes ax;
+                if (!ray_setup(g, v, pcol, prow, r, &ax)) continue;
+                // parameter interval [E, X) inside the block, exact on the ray's grid
+                double E = 0.0, X = r.send;
+                bool hit = true;
+    #pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (r.ds[a] == 0.0) {  // index constant along the ray
+                        hit = hit && ax.idx[a] >= blo[a] && ax.idx[a] < bhi[a];
+                        continue;
+                    }
+                    const bool up = r.st[a] > 0;
+                    const int J = up ? blo[a] - ax.idx[a] : ax.idx[a] - (bhi[a] - 1);  // crossings to enter
+                    const int K = up ? bhi[a] - ax.idx[a] : ax.idx[a] - blo[a] + 1;    // crossings to leave
+                    hit = hit && K > 0;
+                    if (J > 0) E = fmax(E, r.s[a] + (double)(J - 1) * r.ds[a]);
+                    X = fmin(X, r.s[a] + (double)(K - 1) * r.ds[a]);
+                }
+                if (!hit || !(X > E)) continue;
+                // walk state at E: crossings with parameter <= E are done
+                int32_t loc = 0;
+                int32_t lst[3];
+                bool inblk = true;
+    #pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    int idx = ax.idx[a];
+                    if (r.ds[a] != 0.0) {
+                        int j = 0;
+                        if (E >= r.s[a]) {
+                            // the estimate from the unrounded spacing is within
+                            // one of the count (a capped spacing only makes it
+                            // smaller, where the count is 1); settle it with exact
+                            // comparisons on the grid
+                            j = max((int)floor((E - r.s[a]) * ax.rds[a]) + 1, 1);
+    #pragma unroll
+                            for (int fix = 0; fix < 2; ++fix) {
+                                j -= (j > 1 && r.s[a] + (double)(j - 1) * r.ds[a] > E) ? 1 : 0;
+                                j += (r.s[a] + (double)j * r.ds[a] <= E) ? 1 : 0;
+                            }
+                        }
+                        r.s[a] += (double)j * r.ds[a];
+                        idx += r.st[a] > 0 ? j : -j;
+                        lst[a] = r.st[a] > 0 ? lstride[a] : -lstride[a];
+                    } else {
+                        lst[a] = 0;
+                    }
+                    inblk = inblk && idx >= blo[a] && idx < bhi[a];
+                    loc += (idx - blo[a]) * lstride[a];
+                }
+                // On the exact grid a walk that starts inside the block stays
+                // inside until X (each axis takes fewer crossings than it needs
+                // to leave), so a start outside it is the only possible spill:
+                // counted, and the ray skipped.
+                if (!inblk) {
+                    ++spills;
                     continue;
                 }
-                const bool up = r.st[a] > 0;
-                const int J = up ? blo[a] - ax.idx[a] : ax.idx[a] - (bhi[a] - 1);  // crossings to enter
-                const int K = up ? bhi[a] - ax.idx[a] : ax.idx[a] - blo[a] + 1;    // crossings to leave
-                hit = hit && K > 0;
-                if (J > 0) E = fmax(E, r.s[a] + (double)(J - 1) * r.ds[a]);
-                X = fmin(X, r.s[a] + (double)(K - 1) * r.ds[a]);
-            }
-            if (!hit || !(X > E)) continue;
-            // walk state at E: crossings with parameter <= E are done
-            int32_t loc = 0;
-            int32_t lst[3];
-            bool inblk = true;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                int idx = ax.idx[a];
-                if (r.ds[a] != 0.0) {
-                    int j = 0;
-                    if (E >= r.s[a]) {
-                        // the estimate from the unrounded spacing is within
-                        // one of the count (a capped spacing only makes it
-                        // smaller, where the count is 1); settle it with exact
-                        // comparisons on the grid
-                        j = max((int)floor((E - r.s[a]) * ax.rds[a]) + 1, 1);
-#pragma unroll
-                        for (int fix = 0; fix < 2; ++fix) {
-                            j -= (j > 1 && r.s[a] + (double)(j - 1) * r.ds[a] > E) ? 1 : 0;
-                            j += (r.s[a] + (double)j * r.ds[a] <= E) ? 1 : 0;
+                const double wys = (double)yv * r.dn * (finite ? fx_scale : 1.0);
+                // four steps per loop body, as in ray_walk; the clamp to the
+                // dummy bin nbins only guards the LDS range
+                auto walk = [&](auto deposit) {
+                    double scur = E;
+                    auto step = [&]() {
+                        const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
+                        deposit(min((uint32_t)loc, (uint32_t)nbins), (m - scur) * wys);
+                        if (m >= X) return true;
+    #pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            const bool tie = (r.s[a] == m);
+                            r.s[a] = fma(r.ds[a], tie_factor(tie), r.s[a]);
+                            loc += tie ? lst[a] : 0;
                         }
+                        scur = m;
+                        return false;
+                    };
+                    for (int it = 0; it < bd.maxit; it += 4) {
+                        if (step() || step() || step() || step()) break;
                     }
-                    r.s[a] += (double)j * r.ds[a];
-                    idx += r.st[a] > 0 ? j : -j;
-                    lst[a] = r.st[a] > 0 ? lstride[a] : -lstride[a];
-                } else {
-                    lst[a] = 0;
-                }
-                inblk = inblk && idx >= blo[a] && idx < bhi[a];
-                loc += (idx - blo[a]) * lstride[a];
-            }
-            // On the exact grid a walk that starts inside the block stays
-            // inside until X (each axis takes fewer crossings than it needs
-            // to leave), so a start outside it is the only possible spill:
-            // counted, and the ray skipped.
-            if (!inblk) {
-                ++spills;
-                continue;
-            }
-            const double wys = (double)yv * r.dn * (finite ? fx_scale : 1.0);
-            // four steps per loop body, as in ray_walk; the clamp to the
-            // dummy bin nbins only guards the LDS range
-            auto walk = [&](auto deposit) {
-                double scur = E;
-                auto step = [&]() {
-                    const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
-                    deposit(min((uint32_t)loc, (uint32_t)nbins), (m - scur) * wys);
-                    if (m >= X) return true;
-#pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        const bool tie = (r.s[a] == m);
-                        r.s[a] = fma(r.ds[a], tie_factor(tie), r.s[a]);
-                        loc += tie ? lst[a] : 0;
-                    }
-                    scur = m;
-                    return false;
                 };
-                for (int it = 0; it < bd.maxit; it += 4) {
-                    if (step() || step() || step() || step()) break;
+                if (finite) {
+                    walk([&](uint32_t l, double v) {
+                        // v + 1.5 * 2^52 rounds v to an integer (|v| < 2^50) in the low bits
+                        const double t = v + 6755399441055744.0;
+                        const long long q = (long long)__builtin_bit_cast(uint64_t, t) - 0x4338000000000000ll;
+                        atomicAdd(&bins[l], (unsigned long long)q);
+                    });
+                } else {
+                    walk([&](uint32_t l, double v) { atomicAdd(&fbins[l], (float)v); });
                 }
-            };
-            if (finite) {
-                walk([&](uint32_t l, double v) {
-                    // v + 1.5 * 2^52 rounds v to an integer (|v| < 2^50) in the low bits
-                    const double t = v + 6755399441055744.0;
-                    const long long q = (long long)__builtin_bit_cast(uint64_t, t) - 0x4338000000000000ll;
-                    atomicAdd(&bins[l], (unsigned long long)q);
-                });
-            } else {
-                walk([&](uint32_t l, double v) { atomicAdd(&fbins[l], (float)v); });
             }
         }
     }
