@@ -113,6 +113,9 @@ enum {
  *   cube_d:   DEVICE float [nframes][nz][ny][nx]
  *   images_d: DEVICE float [total pixels]; every pixel is written (masked and
  *             missing rays get 0).
+ * With a map mask, M x is first written to stream-ordered scratch
+ * (hipMallocAsync, the cube's size) and projected by the unmasked walk; if
+ * that allocation fails the walk applies the mask itself (same result).
  */
 int tomo_project(const tomo_geometry *g, const float *cube_d, float *images_d,
                  tomo_stream stream);
@@ -175,7 +178,7 @@ int tomo_trace_ray(const tomo_geometry *g, int32_t view, int32_t col,
  *     back-projection owns (each 1..64, product <= 8192 64-bit LDS bins).
  *   bp_splits: owners per block in the blocked back-projection, the block's
  *     views dealt round-robin (1..64; 0 = chosen from the block count so
- *     that the launch has about 4096 workgroups, at most 8 owners).
+ *     that the launch has about 2048 workgroups, at most 8 owners).
  * tomo_set_tuning returns TOMO_EINVAL (and changes nothing) for values out
  * of range.  Not synchronised with launches in flight on other threads.
  */

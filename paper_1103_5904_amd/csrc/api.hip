@@ -21,8 +21,9 @@ static thread_local std::string g_last_error;
 static std::mutex g_tuning_mu;
 // Defaults measured on MI355X (EUVI-like 128^3, 28 views of 512^2): P with
 // 4x16 bundles and the XCD remap; P^T owner-computes on 32x16x8 blocks with
-// 16x4 bundles (the binned strategy prefers 8x8 bundles and 4096 bins).
-static tomo_tuning g_tuning = {2, 1, 4, 1, 4096, TOMO_BP_BLOCKED, {32, 16, 8}, 0};
+// 8x8 bundles and the automatic owner count (the binned strategy also
+// prefers 8x8 bundles, with 4096 bins).
+static tomo_tuning g_tuning = {2, 1, 3, 1, 4096, TOMO_BP_BLOCKED, {32, 16, 8}, 0};
 
 tomo_tuning current_tuning()
 {

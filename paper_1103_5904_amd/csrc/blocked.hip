@@ -100,8 +100,8 @@ BlockedShape blocked_shape(const Plan &p, const tomo_tuning &tu)
     }
     nblk *= p.grid.nframes;
     int s = tu.bp_splits;
-    if (s <= 0) {  // enough owners for ~16 workgroups per CU
-        const int64_t want = 4096;
+    if (s <= 0) {  // enough owners for ~8 workgroups per CU (two rounds of the four resident)
+        const int64_t want = 2048;
         s = (int)((want + nblk - 1) / nblk);
         s = s < 1 ? 1 : (s > 8 ? 8 : s);
     }

@@ -130,6 +130,19 @@ __global__ __launch_bounds__(kThreads) void k_fill(float *__restrict__ x, int64_
         x[i] = v;
 }
 
+// out = M x over every frame: out[f][v] = x[f][v] where map_mask[v], else 0.
+// Lets P M x run the unmasked walk, whose one gather per step is the
+// projector's bound (a mask byte per step would double the gathers).
+__global__ __launch_bounds__(kThreads) void k_mask_copy(const float *__restrict__ x,
+                                                        const uint8_t *__restrict__ mask, int64_t nvox,
+                                                        int32_t nframes, float *__restrict__ out)
+{
+    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < nvox; v += (int64_t)gridDim.x * kThreads) {
+        const bool keep = mask[v] != 0;
+        for (int32_t f = 0; f < nframes; ++f) out[(int64_t)f * nvox + v] = keep ? x[(int64_t)f * nvox + v] : 0.0f;
+    }
+}
+
 // ------------------------------------------------------------ launchers
 
 static int64_t grid_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
@@ -163,6 +176,23 @@ int launch_project_tuned(const Plan &p, const tomo_geometry *g, const float *cub
 int launch_project(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
                    bool use_map_mask, hipStream_t s)
 {
+    if (use_map_mask && g->map_mask) {
+        // P M x as the unmasked walk over a masked copy (stream-ordered
+        // scratch); without the memory, the walk tests the mask itself
+        float *tmp = nullptr;
+        const int64_t total = p.grid.nvox * p.grid.nframes;
+        if (hipMallocAsync((void **)&tmp, sizeof(float) * (size_t)total, s) == hipSuccess) {
+            int64_t nb = grid_blocks(p.grid.nvox);
+            nb = nb > 4096 ? 4096 : nb;
+            hipLaunchKernelGGL(k_mask_copy, dim3((unsigned)nb), dim3(kThreads), 0, s, cube, g->map_mask,
+                               p.grid.nvox, (int32_t)p.grid.nframes, tmp);
+            int rc = hip_fail(hipGetLastError(), "mask copy launch");
+            if (!rc) rc = launch_project_tuned(p, g, tmp, images, false, s, nullptr, tuning_for(p));
+            (void)hipFreeAsync(tmp, s);
+            return rc;
+        }
+        (void)hipGetLastError();  // the failed allocation's error is not the caller's
+    }
     return launch_project_tuned(p, g, cube, images, use_map_mask, s, nullptr, tuning_for(p));
 }
 

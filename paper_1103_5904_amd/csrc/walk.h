@@ -261,12 +261,14 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
         float x_prev = 0.0f;
         if constexpr (kMapMask) {
             const auto rm = make_rsrc(map_mask, (uint32_t)g.nvox);
+            uint32_t m_prev = 0u;
             ray_walk(r, maxit, [&](int32_t off, double dl) {
-                acc = fma(dl_prev, (double)x_prev, acc);
-                const float x = buf_load_f32(rc, (uint32_t)off * 4u);
-                x_prev = buf_load_u8(rm, (uint32_t)off) ? x : 0.0f;
+                acc = fma(dl_prev, m_prev ? (double)x_prev : 0.0, acc);
+                x_prev = buf_load_f32(rc, (uint32_t)off * 4u);
+                m_prev = buf_load_u8(rm, (uint32_t)off);
                 dl_prev = dl;
             });
+            if (!m_prev) x_prev = 0.0f;
         } else if (g.nvox < ((int64_t)1 << 29)) {
             // offsets in bytes from here on (below 2^31, so int32 holds them)
             r.off *= 4;
