@@ -131,7 +131,7 @@ int tomo_project(const tomo_geometry *g, const float *cube_d, float *images_d,
  *             in the voxels their rays cross.
  *   strategy: TOMO_BP_* (tomo_backproject uses TOMO_BP_AUTO).  The blocked
  *             strategy takes stream-ordered scratch (hipMallocAsync) of
- *             4 * nviews * 8 bytes plus, when blocks are shared between
+ *             4 * nviews * 64 bytes plus, when blocks are shared between
  *             owners, owners * 4 * nframes * nvox bytes.
  */
 int tomo_backproject(const tomo_geometry *g, const float *images_d,

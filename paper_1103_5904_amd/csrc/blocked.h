@@ -6,7 +6,7 @@
 
 namespace tomo {
 
-constexpr int kYmaxParts = 8;  // partial maxima per view
+constexpr int kYmaxParts = 64;  // partial maxima per view (64 workgroups per view keep the pass short)
 
 // max |y| over the share `part` of view v's unmasked pixels, as an FP32 bit
 // pattern (bit patterns of magnitudes order like the magnitudes; anything
