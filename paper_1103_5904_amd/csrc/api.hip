@@ -58,6 +58,8 @@ int validate_cube(const tomo_cube *c)
     if (c->nx < 1 || c->ny < 1 || c->nz < 1)
         return set_error(TOMO_EINVAL, "cube dims must be >= 1 (got %d x %d x %d)", c->nx, c->ny, c->nz);
     if (c->nframes < 1) return set_error(TOMO_EINVAL, "nframes must be >= 1 (got %d)", c->nframes);
+    if (c->nx > (1 << 24) || c->ny > (1 << 24) || c->nz > (1 << 24))
+        return set_error(TOMO_EINVAL, "cube side exceeds 2^24 voxels (got %d x %d x %d)", c->nx, c->ny, c->nz);
     const int64_t nvox = (int64_t)c->nx * c->ny * c->nz;
     if (nvox >= (int64_t)1 << 30)
         return set_error(TOMO_EINVAL, "cube of %lld voxels exceeds the 2^30 limit", (long long)nvox);

@@ -217,7 +217,7 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 // parameter interval [E, X) inside the block, exact on the ray's grid
                 double E = 0.0, X = r.send;
                 bool hit = true;
-    #pragma unroll
+#pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     if (r.ds[a] == 0.0) {  // index constant along the ray
                         hit = hit && ax.idx[a] >= blo[a] && ax.idx[a] < bhi[a];
@@ -235,22 +235,22 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 int32_t loc = 0;
                 int32_t lst[3];
                 bool inblk = true;
-    #pragma unroll
+#pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     int idx = ax.idx[a];
                     if (r.ds[a] != 0.0) {
                         int j = 0;
                         if (E >= r.s[a]) {
                             // the estimate from the unrounded spacing is within
-                            // one of the count (a capped spacing only makes it
-                            // smaller, where the count is 1); settle it with exact
-                            // comparisons on the grid
+                            // one of the count: the grid moves a spacing by at
+                            // most 2^-49 crossings-per-chord of itself, so C
+                            // crossings shift by at most 2^-49 C^2 < 1/2 on a
+                            // cube side of at most 2^24 voxels (a capped
+                            // spacing only makes it smaller, where the count
+                            // is 1); one exact comparison each way settles it
                             j = max((int)floor((E - r.s[a]) * ax.rds[a]) + 1, 1);
-    #pragma unroll
-                            for (int fix = 0; fix < 2; ++fix) {
-                                j -= (j > 1 && r.s[a] + (double)(j - 1) * r.ds[a] > E) ? 1 : 0;
-                                j += (r.s[a] + (double)j * r.ds[a] <= E) ? 1 : 0;
-                            }
+                            j -= (j > 1 && r.s[a] + (double)(j - 1) * r.ds[a] > E) ? 1 : 0;
+                            j += (r.s[a] + (double)j * r.ds[a] <= E) ? 1 : 0;
                         }
                         r.s[a] += (double)j * r.ds[a];
                         idx += r.st[a] > 0 ? j : -j;
@@ -278,7 +278,7 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                         const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
                         deposit(min((uint32_t)loc, (uint32_t)nbins), (m - scur) * wys);
                         if (m >= X) return true;
-    #pragma unroll
+#pragma unroll
                         for (int a = 0; a < 3; ++a) {
                             const bool tie = (r.s[a] == m);
                             r.s[a] = fma(r.ds[a], tie_factor(tie), r.s[a]);

@@ -64,7 +64,8 @@ def test_validation_accepts_the_tiny_geometry(tomo):
 
 
 @pytest.mark.parametrize("case", ["zero_dim", "inverted_box", "non_unit_w", "non_orthogonal",
-                                  "zero_cdelt", "empty_image", "bad_frame", "nan_obs", "huge_cube"])
+                                  "zero_cdelt", "empty_image", "bad_frame", "nan_obs", "huge_cube",
+                                  "long_side"])
 def test_validation_rejects(tomo, case):
     g = _geom()
     views, npix = g.views.copy(), g.npix.copy()
@@ -87,6 +88,8 @@ def test_validation_rejects(tomo, case):
         views[0, 0] = np.nan
     elif case == "huge_cube":
         kw["n"] = (1024, 1024, 1024)
+    elif case == "long_side":  # under 2^30 voxels, but a side above 2^24
+        kw["n"] = (1, (1 << 24) + 1, 1)
     dg = tomo.DeviceGeometry(_geom(views=views, npix=npix, **kw), device="cpu")
     assert tomo.validate(dg) == tomo.tomo.TOMO_EINVAL
     assert tomo.lib().tomo_last_error()
