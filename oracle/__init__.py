@@ -80,6 +80,12 @@ def _geom_args(g):
     return n, lo, hi, views, npix, vf, dm, mm
 
 
+def _obstacle(g):
+    """The geometry's opaque sphere as (cx, cy, cz, R) float64, or None."""
+    ob = getattr(g, "obstacle", None)
+    return None if ob is None else np.ascontiguousarray(ob, dtype=np.float64).reshape(4)
+
+
 # ------------------------------------------------------------- projector
 
 
@@ -91,8 +97,8 @@ def project(g, cube, nthreads: int = 0, use_map_mask: bool = True) -> np.ndarray
     assert x.size == g.nvox * g.nframes
     out = np.empty(g.nrays, dtype=np.float64)
     rc = lib.ora_project(_p(n), _p(lo), _p(hi), ctypes.c_int(g.nviews), _p(views), _p(npix),
-                         _p(vf), _p(dm), _p(mm if use_map_mask else None), _p(x), _p(out),
-                         ctypes.c_int(nthreads))
+                         _p(vf), _p(dm), _p(mm if use_map_mask else None), _p(_obstacle(g)), _p(x),
+                         _p(out), ctypes.c_int(nthreads))
     if rc:
         raise MemoryError("oracle projection failed")
     return out
@@ -107,8 +113,8 @@ def backproject(g, images, nthreads: int = 0, use_map_mask: bool = True) -> np.n
     out = np.empty(g.nvox * g.nframes, dtype=np.float64)
     rc = lib.ora_backproject(_p(n), _p(lo), _p(hi), ctypes.c_int(g.nviews), _p(views), _p(npix),
                              _p(vf), ctypes.c_int(g.nframes), _p(dm),
-                             _p(mm if use_map_mask else None), _p(y), _p(out), ctypes.c_int(0),
-                             ctypes.c_int(nthreads))
+                             _p(mm if use_map_mask else None), _p(_obstacle(g)), _p(y), _p(out),
+                             ctypes.c_int(0), ctypes.c_int(nthreads))
     if rc:
         raise MemoryError("oracle back-projection failed")
     return out.reshape(g.cube_shape())
@@ -119,15 +125,16 @@ def count_crossings(g, nthreads: int = 0) -> int:
     lib = _load()
     n, lo, hi, views, npix, _, dm, _ = _geom_args(g)
     c = lib.ora_count_crossings(_p(n), _p(lo), _p(hi), ctypes.c_int(g.nviews), _p(views),
-                                _p(npix), _p(dm), ctypes.c_int(nthreads))
+                                _p(npix), _p(dm), _p(_obstacle(g)), ctypes.c_int(nthreads))
     if c < 0:
         raise MemoryError("oracle count failed")
     return int(c)
 
 
-def trace_ray(n, lo, hi, o, d):
+def trace_ray(n, lo, hi, o, d, obstacle=None):
     """Siddon segments of the half-line o + t d: (voxel index, length, t at
-    the segment's entry), in order along the ray."""
+    the segment's entry), in order along the ray, up to the first contact
+    with the obstacle sphere (cx, cy, cz, R) when one is given."""
     lib = _load()
     n = np.ascontiguousarray(n, dtype=np.int32)
     lo = np.ascontiguousarray(lo, dtype=np.float64)
@@ -138,22 +145,25 @@ def trace_ray(n, lo, hi, o, d):
     idx = np.empty(cap, dtype=np.int32)
     ln = np.empty(cap, dtype=np.float64)
     tl = np.empty(cap, dtype=np.float64)
-    k = lib.ora_trace_ray(_p(n), _p(lo), _p(hi), _p(o), _p(d), _p(idx), _p(ln), _p(tl),
+    ob = None if obstacle is None else np.ascontiguousarray(obstacle, dtype=np.float64).reshape(4)
+    k = lib.ora_trace_ray(_p(n), _p(lo), _p(hi), _p(o), _p(d), _p(ob), _p(idx), _p(ln), _p(tl),
                           ctypes.c_int(cap))
     if k < 0:
         raise RuntimeError("segment buffer overflow")
     return idx[:k].copy(), ln[:k].copy(), tl[:k].copy()
 
 
-def ray_row_bruteforce(n, lo, hi, o, d) -> np.ndarray:
-    """Row of P for one ray from the plain definition: one slab clip per voxel."""
+def ray_row_bruteforce(n, lo, hi, o, d, obstacle=None) -> np.ndarray:
+    """Row of P for one ray from the plain definition: one slab clip per voxel
+    (each voxel's interval cut at the obstacle's first contact, if any)."""
     lib = _load()
     n = np.ascontiguousarray(n, dtype=np.int32)
     out = np.empty(int(np.prod(n)), dtype=np.float64)
+    ob = None if obstacle is None else np.ascontiguousarray(obstacle, dtype=np.float64).reshape(4)
     lib.ora_ray_row_bruteforce(_p(n), _p(np.ascontiguousarray(lo, dtype=np.float64)),
                                _p(np.ascontiguousarray(hi, dtype=np.float64)),
                                _p(np.ascontiguousarray(o, dtype=np.float64)),
-                               _p(np.ascontiguousarray(d, dtype=np.float64)), _p(out))
+                               _p(np.ascontiguousarray(d, dtype=np.float64)), _p(ob), _p(out))
     return out
 
 

@@ -29,6 +29,14 @@
  * integer 0-based indices.  Points o + t d with t >= 0.  Lengths are in box
  * units.  Voxels are half-open [lo + k D, lo + (k+1) D).
  *
+ * Optional obstacle (the opaque photosphere, Sec. "Solar Tomography"; the
+ * projector's obstacle variant, Sec. "Fast Parallelized Projector"; line of
+ * sight integration stops at the photosphere, Sec. "Performance"): a sphere
+ * of centre c and radius R.  The line of sight is integrated over
+ * 0 <= t < t_c only, t_c being where it enters the sphere's interior (t_c = 0
+ * when the observer is on or inside the sphere; no limit when the line
+ * never enters it, a tangent line included).
+ *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC oracle.c -lm
  */
 #include <math.h>
@@ -124,6 +132,33 @@ static int clip_box(const double o[3], const double d[3], const double lo[3],
     return 1;
 }
 
+/* Where the half-line o + t d (t >= 0) enters the interior |p - c| < R of
+ * the sphere sph = {cx, cy, cz, R}: 0 if o is inside or on the sphere,
+ * INFINITY if the half-line never enters it.  Written from the closest approach
+ * t* = -(o - c).d / d.d at distance h from the centre: the contact is
+ * t* - sqrt((R^2 - h^2) / d.d), which needs no difference of two nearly
+ * equal large numbers when the observer is far away. */
+static double sphere_contact(const double o[3], const double d[3], const double *sph)
+{
+    double oc[3], dd = 0.0, od = 0.0, oo = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        oc[a] = o[a] - sph[a];
+        dd += d[a] * d[a];
+        od += oc[a] * d[a];
+        oo += oc[a] * oc[a];
+    }
+    const double r2 = sph[3] * sph[3];
+    if (oo <= r2) return 0.0;
+    if (od >= 0.0) return INFINITY; /* outside and moving away */
+    double ts = -od / dd, h2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double p = oc[a] + ts * d[a];
+        h2 += p * p;
+    }
+    if (h2 >= r2) return INFINITY; /* passes beside (or touches) the sphere */
+    return ts - sqrt((r2 - h2) / dd);
+}
+
 /* ------------------------------------------------------------ Siddon walk */
 
 /* Per-thread scratch for the crossing sets of one ray. */
@@ -203,14 +238,19 @@ static int clampi(int v, int lo, int hi)
 }
 
 /* Segments of one ray: for each, the flat voxel index (x fastest) and the
- * length.  Returns the number of segments (0 if the ray misses); -1 if the
- * output capacity is too small. */
+ * length, up to the obstacle sph (or NULL).  Returns the number of segments
+ * (0 if the ray misses); -1 if the output capacity is too small. */
 static int trace(const ora_grid *g, const double o[3], const double d[3],
-                 ora_scratch *s, int32_t *idx, double *len, double *tlo,
-                 int cap)
+                 const double *sph, ora_scratch *s, int32_t *idx, double *len,
+                 double *tlo, int cap)
 {
     double t_in, t_out;
     if (!clip_box(o, d, g->lo, g->hi, &t_in, &t_out)) return 0;
+    if (sph) { /* the line of sight ends at the obstacle */
+        double tc = sphere_contact(o, d, sph);
+        if (tc < t_out) t_out = tc;
+        if (!(t_out > t_in)) return 0;
+    }
     int cnt[3];
     for (int a = 0; a < 3; ++a)
         cnt[a] = axis_crossings(g, a, o[a], d[a], t_in, t_out, s->set[a]);
@@ -280,7 +320,7 @@ int ora_max_threads(void)
 int ora_project(const int *n, const double *lo, const double *hi, int nviews,
                 const double *views, const int *npix, const int *view_frame,
                 const uint8_t *data_mask, const uint8_t *map_mask,
-                const double *cube, double *images, int nthreads)
+                const double *obstacle, const double *cube, double *images, int nthreads)
 {
     ora_grid g = make_grid(n, lo, hi);
     int64_t nvox = (int64_t)n[0] * n[1] * n[2];
@@ -311,7 +351,7 @@ int ora_project(const int *n, const double *lo, const double *hi, int nviews,
                     if (!data_mask || data_mask[off[v] + r]) {
                         double d[3];
                         ray_dir(&vw, col, row, d);
-                        int ns = trace(&g, vw.o, d, &s, idx, len, NULL, cap);
+                        int ns = trace(&g, vw.o, d, obstacle, &s, idx, len, NULL, cap);
                         for (int k = 0; k < ns; ++k)
                             if (!mm || mm[idx[k]]) acc += len[k] * x[idx[k]];
                     }
@@ -337,8 +377,8 @@ int ora_backproject(const int *n, const double *lo, const double *hi,
                     int nviews, const double *views, const int *npix,
                     const int *view_frame, int nframes,
                     const uint8_t *data_mask, const uint8_t *map_mask,
-                    const double *images, double *cube, int accumulate,
-                    int nthreads)
+                    const double *obstacle, const double *images, double *cube,
+                    int accumulate, int nthreads)
 {
     ora_grid g = make_grid(n, lo, hi);
     int64_t nvox = (int64_t)n[0] * n[1] * n[2];
@@ -370,7 +410,7 @@ int ora_backproject(const int *n, const double *lo, const double *hi,
                     int col = (int)(r % vw.ncol), row = (int)(r / vw.ncol);
                     double d[3];
                     ray_dir(&vw, col, row, d);
-                    int ns = trace(&g, vw.o, d, &s, idx, len, NULL, cap);
+                    int ns = trace(&g, vw.o, d, obstacle, &s, idx, len, NULL, cap);
                     for (int k = 0; k < ns; ++k) {
                         if (mm && !mm[idx[k]]) continue;
                         double add = len[k] * yv;
@@ -393,7 +433,7 @@ int ora_backproject(const int *n, const double *lo, const double *hi,
  * crossed, its value is just treated as zero. */
 int64_t ora_count_crossings(const int *n, const double *lo, const double *hi,
                             int nviews, const double *views, const int *npix,
-                            const uint8_t *data_mask, int nthreads)
+                            const uint8_t *data_mask, const double *obstacle, int nthreads)
 {
     ora_grid g = make_grid(n, lo, hi);
     int64_t *off = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nviews + 1));
@@ -421,7 +461,7 @@ int64_t ora_count_crossings(const int *n, const double *lo, const double *hi,
                     int col = (int)(r % vw.ncol), row = (int)(r / vw.ncol);
                     double d[3];
                     ray_dir(&vw, col, row, d);
-                    int ns = trace(&g, vw.o, d, &s, idx, len, NULL, cap);
+                    int ns = trace(&g, vw.o, d, obstacle, &s, idx, len, NULL, cap);
                     for (int k = 0; k < ns; ++k) total += len[k] > 0.0;
                 }
             }
@@ -435,16 +475,17 @@ int64_t ora_count_crossings(const int *n, const double *lo, const double *hi,
 }
 
 /* Segment list of one line of sight, given its origin and direction
- * directly (so tests can place hand-made rays).  tlo receives each segment's
- * entry parameter.  Returns the segment count or -1 on overflow. */
+ * directly (so tests can place hand-made rays), up to the obstacle (or
+ * NULL).  tlo receives each segment's entry parameter.  Returns the segment
+ * count or -1 on overflow. */
 int ora_trace_ray(const int *n, const double *lo, const double *hi,
-                  const double *o, const double *d, int32_t *idx, double *len,
-                  double *tlo, int cap)
+                  const double *o, const double *d, const double *obstacle,
+                  int32_t *idx, double *len, double *tlo, int cap)
 {
     ora_grid g = make_grid(n, lo, hi);
     ora_scratch s;
     if (scratch_init(&s, &g)) return -1;
-    int ns = trace(&g, o, d, &s, idx, len, tlo, cap);
+    int ns = trace(&g, o, d, obstacle, &s, idx, len, tlo, cap);
     scratch_free(&s);
     return ns;
 }
@@ -460,14 +501,17 @@ void ora_pixel_direction(const double *view16, const int *npix, int col,
 /*
  * Brute-force twin of one ray's row of P, straight from the definition:
  * for every voxel, clip the half-line against that voxel's own box and take
- * the length inside.  O(voxels) per ray, no merging; only for tiny cubes.
- * out has one entry per voxel (x fastest).
+ * the length inside, up to the obstacle's first contact (obstacle may be
+ * NULL).  O(voxels) per ray, no merging; only for tiny cubes.  out has one
+ * entry per voxel (x fastest).
  */
 void ora_ray_row_bruteforce(const int *n, const double *lo, const double *hi,
-                            const double *o, const double *d, double *out)
+                            const double *o, const double *d, const double *obstacle,
+                            double *out)
 {
     ora_grid g = make_grid(n, lo, hi);
     double dn = norm3(d);
+    double tc = obstacle ? sphere_contact(o, d, obstacle) : INFINITY;
     for (int k = 0; k < g.n[2]; ++k)
         for (int j = 0; j < g.n[1]; ++j)
             for (int i = 0; i < g.n[0]; ++i) {
@@ -479,7 +523,10 @@ void ora_ray_row_bruteforce(const int *n, const double *lo, const double *hi,
                 }
                 double tin, tout;
                 double l = 0.0;
-                if (clip_box(o, d, vlo, vhi, &tin, &tout)) l = (tout - tin) * dn;
+                if (clip_box(o, d, vlo, vhi, &tin, &tout)) {
+                    if (tc < tout) tout = tc;
+                    if (tout > tin) l = (tout - tin) * dn;
+                }
                 out[((int64_t)k * g.n[1] + j) * g.n[0] + i] = l;
             }
 }

@@ -47,6 +47,7 @@ class Geometry:
     nframes: int = 1
     data_mask: Optional[np.ndarray] = None  # (sum ncol*nrow,) uint8, 1 = keep
     map_mask: Optional[np.ndarray] = None  # (nz, ny, nx) uint8, 1 = keep
+    obstacle: Optional[np.ndarray] = None  # (cx, cy, cz, R): opaque sphere ending every line of sight
 
     @property
     def nviews(self) -> int:
@@ -81,7 +82,8 @@ class Geometry:
         vf = None if self.view_frame is None else self.view_frame[view_ids].copy()
         return Geometry(self.n, self.lo.copy(), self.hi.copy(), self.views[view_ids].copy(),
                         self.npix[view_ids].copy(), vf, self.nframes, dm,
-                        None if self.map_mask is None else self.map_mask.copy())
+                        None if self.map_mask is None else self.map_mask.copy(),
+                        None if self.obstacle is None else np.array(self.obstacle, dtype=np.float64))
 
 
 # ------------------------------------------------------------------ views
