@@ -88,6 +88,18 @@ typedef struct tomo_view {
     int32_t reserved;   /* set to 0                                             */
 } tomo_view;
 
+/*
+ * An opaque sphere, the photosphere of the projector's obstacle variant
+ * (Sec. "Fast Parallelized Projector"; integration stops at the photosphere,
+ * Sec. "Performance"): every line of sight ends where it enters the sphere's
+ * interior.  An observer on or inside the sphere sees nothing; a line that
+ * never enters the interior (a tangent line included) is not cut.
+ */
+typedef struct tomo_obstacle {
+    double center[3];  /* cube frame, box units (the Sun's centre: 0, 0, 0)    */
+    double radius;     /* > 0 (the photosphere: 1 R_sun)                       */
+} tomo_obstacle;
+
 typedef struct tomo_geometry {
     tomo_cube cube;
     int32_t nviews;           /* >= 1                                          */
@@ -96,6 +108,9 @@ typedef struct tomo_geometry {
     const uint8_t *data_mask; /* DEVICE [total pixels] or NULL (keep all)      */
     const uint8_t *map_mask;  /* DEVICE [nz][ny][nx] or NULL (keep all); the
                                  same mask applies to every frame               */
+    const tomo_obstacle *obstacle; /* HOST pointer or NULL (no obstacle); read
+                                      at every call, applies to P, P^T and the
+                                      crossing count alike                   */
 } tomo_geometry;
 
 /* Back-projection strategies. */

@@ -99,6 +99,11 @@ static int validate_geometry_impl(const tomo_geometry *g, int64_t *npix_out)
         npix += (int64_t)v.ncol * v.nrow;
     }
     if (npix >= (int64_t)1 << 40) return set_error(TOMO_EINVAL, "too many pixels");
+    if (g->obstacle) {
+        const tomo_obstacle &ob = *g->obstacle;
+        if (!finite3(ob.center) || !isfinite(ob.radius) || !(ob.radius > 0.0))
+            return set_error(TOMO_EINVAL, "obstacle: centre must be finite and radius finite and > 0");
+    }
     if (npix_out) *npix_out = npix;
     return TOMO_OK;
 }
@@ -124,13 +129,17 @@ static uint64_t fnv1a(const unsigned char *p, size_t n, uint64_t h = 14695981039
 
 static std::vector<unsigned char> geometry_key(const tomo_geometry *g)
 {
-    std::vector<unsigned char> k(sizeof(tomo_cube) + sizeof(int32_t) +
+    const tomo_obstacle none = {{0.0, 0.0, 0.0}, 0.0};
+    const tomo_obstacle &ob = g->obstacle ? *g->obstacle : none;
+    std::vector<unsigned char> k(sizeof(tomo_cube) + sizeof(int32_t) + sizeof(tomo_obstacle) +
                                  sizeof(tomo_view) * (size_t)g->nviews);
     unsigned char *q = k.data();
     memcpy(q, &g->cube, sizeof(tomo_cube));
     q += sizeof(tomo_cube);
     memcpy(q, &g->nviews, sizeof(int32_t));
     q += sizeof(int32_t);
+    memcpy(q, &ob, sizeof(tomo_obstacle));
+    q += sizeof(tomo_obstacle);
     memcpy(q, g->views, sizeof(tomo_view) * (size_t)g->nviews);
     return k;
 }
@@ -150,6 +159,10 @@ static int build_plan(const tomo_geometry *g, int64_t npix, Plan &p)
         gd.inv_delta[a] = 1.0 / gd.delta[a];
     }
     gd.nvox = (int64_t)c.nx * c.ny * c.nz;
+    gd.has_sph = g->obstacle != nullptr;
+    gd.pad = 0;
+    for (int a = 0; a < 3; ++a) gd.sph[a] = g->obstacle ? g->obstacle->center[a] : 0.0;
+    gd.sph[3] = g->obstacle ? g->obstacle->radius : 0.0;
     std::vector<ViewDev> hv((size_t)g->nviews);
     int64_t pix = 0, tiles = 0;
     for (int k = 0; k < g->nviews; ++k) {

@@ -49,7 +49,7 @@ struct tomo_batch_s {
     int device = 0;
     int32_t nsys = 0;
     std::vector<tomo::PlanRef> plans;
-    std::vector<tomo_geometry> geoms;  // headers (views pointer unused after planning)
+    std::vector<tomo_geometry> geoms;  // headers (views and obstacle unused after planning)
     std::vector<tomo::SysDev> sys_h;
     tomo::SysDev *sys_d = nullptr;
     int64_t ntiles = 0, nitems = 0;

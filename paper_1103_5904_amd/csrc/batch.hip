@@ -88,18 +88,24 @@ __global__ __launch_bounds__(kThreads) void k_batch_project(const SysDev *__rest
         const SysDev &sd = sys[k];
         const int64_t lt = t - sd.tile_begin;
         const bool mm = ops.map && sd.map_mask, dm = sd.data_mask != nullptr;
-        if (mm && dm)
-            project_tile<true, true>(sd.grid, sd.views, sd.nviews, sd.p_log2_bw, lt, sd.maxit, ops.src[k],
-                                     sd.map_mask, sd.data_mask, ops.dst[k]);
-        else if (mm)
-            project_tile<true, false>(sd.grid, sd.views, sd.nviews, sd.p_log2_bw, lt, sd.maxit, ops.src[k],
-                                      sd.map_mask, sd.data_mask, ops.dst[k]);
-        else if (dm)
-            project_tile<false, true>(sd.grid, sd.views, sd.nviews, sd.p_log2_bw, lt, sd.maxit, ops.src[k],
-                                      sd.map_mask, sd.data_mask, ops.dst[k]);
-        else
-            project_tile<false, false>(sd.grid, sd.views, sd.nviews, sd.p_log2_bw, lt, sd.maxit, ops.src[k],
-                                       sd.map_mask, sd.data_mask, ops.dst[k]);
+#define TOMO_TILE(M, D, O)                                                                                   \
+    project_tile<M, D, O>(sd.grid, sd.views, sd.nviews, sd.p_log2_bw, lt, sd.maxit, ops.src[k], sd.map_mask, \
+                          sd.data_mask, ops.dst[k])
+        if (sd.grid.has_sph) {  // the obstacle's variant: one code path for every mask combination
+            if (mm && dm) TOMO_TILE(true, true, true);
+            else if (mm) TOMO_TILE(true, false, true);
+            else if (dm) TOMO_TILE(false, true, true);
+            else TOMO_TILE(false, false, true);
+        } else if (mm && dm) {
+            TOMO_TILE(true, true, false);
+        } else if (mm) {
+            TOMO_TILE(true, false, false);
+        } else if (dm) {
+            TOMO_TILE(false, true, false);
+        } else {
+            TOMO_TILE(false, false, false);
+        }
+#undef TOMO_TILE
     }
     leave_queues(q);
 }
@@ -142,18 +148,24 @@ __global__ __launch_bounds__(kThreads) void k_batch_backproject(const SysDev *__
         float *out = sd.bd.splits == 1 ? ops.dst[k] : sd.part;
         const uint32_t *ym = ymax + (int64_t)sd.view_begin * kYmaxParts;
         const bool mm = ops.map && sd.map_mask, dm = sd.data_mask != nullptr;
-        if (mm && dm)
-            blocked_item<true, true>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, sd.bp_log2_bw, li,
-                                     ops.src[k], sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh);
-        else if (mm)
-            blocked_item<true, false>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, sd.bp_log2_bw, li,
-                                      ops.src[k], sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh);
-        else if (dm)
-            blocked_item<false, true>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, sd.bp_log2_bw, li,
-                                      ops.src[k], sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh);
-        else
-            blocked_item<false, false>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, sd.bp_log2_bw, li,
-                                       ops.src[k], sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh);
+#define TOMO_ITEM(M, D, O)                                                                                 \
+    blocked_item<M, D, O>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, sd.bp_log2_bw, li,      \
+                          ops.src[k], sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh)
+        if (sd.grid.has_sph) {  // the obstacle's variant: one code path for every mask combination
+            if (mm && dm) TOMO_ITEM(true, true, true);
+            else if (mm) TOMO_ITEM(true, false, true);
+            else if (dm) TOMO_ITEM(false, true, true);
+            else TOMO_ITEM(false, false, true);
+        } else if (mm && dm) {
+            TOMO_ITEM(true, true, false);
+        } else if (mm) {
+            TOMO_ITEM(true, false, false);
+        } else if (dm) {
+            TOMO_ITEM(false, true, false);
+        } else {
+            TOMO_ITEM(false, false, false);
+        }
+#undef TOMO_ITEM
     }
     leave_queues(q);
 }
@@ -278,6 +290,7 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
         b->lds_bytes = lds > b->lds_bytes ? lds : b->lds_bytes;
         b->plans.push_back(p);
         b->geoms.push_back(systems[k]);
+        b->geoms.back().obstacle = nullptr;  // captured in the plan's grid
         b->sys_h.push_back(sd);
     }
     if (b->ntiles >= ((int64_t)1 << 40) || b->nitems >= ((int64_t)1 << 40)) {

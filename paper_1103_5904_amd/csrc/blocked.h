@@ -64,7 +64,7 @@ struct BlockedShared {
 // index, every ray of the owner's views that can cross the block walked
 // inside it, and the block written once.  bins: nbins 64-bit LDS words.
 // Called by all threads of the workgroup.
-template <bool kMapMask, bool kDataMask>
+template <bool kMapMask, bool kDataMask, bool kObstacle>
 __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict__ views,
                                     const int32_t *__restrict__ frame_views,
                                     const int32_t *__restrict__ frame_voff, const BlockDev &bd,
@@ -213,7 +213,7 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 if (!pok || !nonzero_bits(yv) || (kDataMask && !pm)) continue;
                 RayState r;
                 RayAxes ax;
-                if (!ray_setup(g, v, pcol, prow, r, &ax)) continue;
+                if (!ray_setup<kObstacle>(g, v, pcol, prow, r, &ax)) continue;
                 // parameter interval [E, X) inside the block, exact on the ray's grid
                 double E = 0.0, X = r.send;
                 bool hit = true;

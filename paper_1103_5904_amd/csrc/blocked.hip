@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kThreads) void k_view_absmax(const ViewDev *__restr
     if (threadIdx.x == 0) ymax[blockIdx.x] = m;
 }
 
-template <bool kMapMask, bool kDataMask>
+template <bool kMapMask, bool kDataMask, bool kObstacle>
 __global__ __launch_bounds__(kThreads) void k_backproject_blocked(
     GridDev g, const ViewDev *__restrict__ views, const int32_t *__restrict__ frame_views,
     const int32_t *__restrict__ frame_voff, BlockDev bd, Bundle bun, const float *__restrict__ images,
@@ -65,8 +65,9 @@ __global__ __launch_bounds__(kThreads) void k_backproject_blocked(
     const int64_t nitems = (int64_t)bd.nb[0] * bd.nb[1] * bd.nb[2] * g.nframes * bd.splits;
     const int64_t item = bun.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     if (item >= nitems) return;
-    blocked_item<kMapMask, kDataMask>(g, views, frame_views, frame_voff, bd, bun.log2_bw, item, images,
-                                      map_mask, data_mask, ymax_parts, out, accumulate, spill, bins, sh);
+    blocked_item<kMapMask, kDataMask, kObstacle>(g, views, frame_views, frame_voff, bd, bun.log2_bw, item,
+                                                 images, map_mask, data_mask, ymax_parts, out, accumulate,
+                                                 spill, bins, sh);
 }
 
 // out[i] = M (sum over owners of part[s][i]) (+ out[i]), owners in order.
@@ -148,15 +149,21 @@ int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const floa
     const size_t lds = sizeof(unsigned long long) * ((size_t)bs.b[0] * bs.b[1] * bs.b[2] + 1);  // + dummy bin
     float *dst = bs.splits == 1 ? cube : part;
     const int acc = accumulate ? 1 : 0;
-#define TOMO_LAUNCH_BK(M, D)                                                                            \
-    hipLaunchKernelGGL((k_backproject_blocked<M, D>), dim3((unsigned)bs.items), dim3(kThreads), lds, s, \
-                       p.grid, p.views_d, p.frame_views_d, p.frame_voff_d, bd, bun, images,            \
+#define TOMO_LAUNCH_BK3(M, D, O)                                                                           \
+    hipLaunchKernelGGL((k_backproject_blocked<M, D, O>), dim3((unsigned)bs.items), dim3(kThreads), lds, s, \
+                       p.grid, p.views_d, p.frame_views_d, p.frame_voff_d, bd, bun, images,               \
                        g->map_mask, g->data_mask, ymax, dst, acc, done_flag, p.spill_d)
+#define TOMO_LAUNCH_BK(M, D)                                                                            \
+    do {                                                                                                \
+        if (p.grid.has_sph) TOMO_LAUNCH_BK3(M, D, true);                                                \
+        else TOMO_LAUNCH_BK3(M, D, false);                                                              \
+    } while (0)
     if (mm && dm) TOMO_LAUNCH_BK(true, true);
     else if (mm) TOMO_LAUNCH_BK(true, false);
     else if (dm) TOMO_LAUNCH_BK(false, true);
     else TOMO_LAUNCH_BK(false, false);
 #undef TOMO_LAUNCH_BK
+#undef TOMO_LAUNCH_BK3
     int rc = hip_fail(hipGetLastError(), "blocked back-projection kernel launch");
     if (rc || bs.splits == 1) return rc;
     const int64_t total = p.grid.nvox * p.grid.nframes;

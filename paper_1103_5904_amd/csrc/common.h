@@ -38,6 +38,9 @@ struct GridDev {
     double delta[3];
     double inv_delta[3];  // 1 / delta
     int64_t nvox;       // voxels per frame
+    double sph[4];      // opaque sphere: centre, radius (valid when has_sph)
+    int32_t has_sph;
+    int32_t pad;
 };
 
 // Wave-level ray bundle inside a 16x16 tile: each 64-lane wavefront takes a

@@ -36,7 +36,7 @@ namespace tomo {
 
 // ------------------------------------------------------------- kernels
 
-template <bool kMapMask, bool kDataMask>
+template <bool kMapMask, bool kDataMask, bool kObstacle>
 __global__ __launch_bounds__(kThreads) void k_project(
     GridDev g, const ViewDev *__restrict__ views, int32_t nviews, Bundle bun, int32_t maxit,
     const float *__restrict__ cube, const uint8_t *__restrict__ map_mask,
@@ -44,8 +44,8 @@ __global__ __launch_bounds__(kThreads) void k_project(
     const int *__restrict__ done_flag)
 {
     if (done_flag && *done_flag) return;
-    project_tile<kMapMask, kDataMask>(g, views, nviews, bun.log2_bw, block_tile(bun), maxit, cube, map_mask,
-                                      data_mask, images);
+    project_tile<kMapMask, kDataMask, kObstacle>(g, views, nviews, bun.log2_bw, block_tile(bun), maxit, cube,
+                                                 map_mask, data_mask, images);
 }
 
 template <bool kMapMask, bool kDataMask>
@@ -162,14 +162,20 @@ int launch_project_tuned(const Plan &p, const tomo_geometry *g, const float *cub
     const Bundle b{tu.p_bundle, tu.p_xcd_remap};
     const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;
     const dim3 grid((unsigned)p.ntiles), blk(kThreads);
-#define TOMO_LAUNCH_P(M, D)                                                                         \
-    hipLaunchKernelGGL((k_project<M, D>), grid, blk, 0, s, p.grid, p.views_d, p.nviews, b,           \
+#define TOMO_LAUNCH_P3(M, D, O)                                                                     \
+    hipLaunchKernelGGL((k_project<M, D, O>), grid, blk, 0, s, p.grid, p.views_d, p.nviews, b,        \
                        p.max_steps, cube, g->map_mask, g->data_mask, images, done_flag)
+#define TOMO_LAUNCH_P(M, D)                                                                         \
+    do {                                                                                            \
+        if (p.grid.has_sph) TOMO_LAUNCH_P3(M, D, true);                                             \
+        else TOMO_LAUNCH_P3(M, D, false);                                                           \
+    } while (0)
     if (mm && dm) TOMO_LAUNCH_P(true, true);
     else if (mm) TOMO_LAUNCH_P(true, false);
     else if (dm) TOMO_LAUNCH_P(false, true);
     else TOMO_LAUNCH_P(false, false);
 #undef TOMO_LAUNCH_P
+#undef TOMO_LAUNCH_P3
     return hip_fail(hipGetLastError(), "projection kernel launch");
 }
 

@@ -57,6 +57,9 @@ struct RayAxes {
     double rds[3];  // ~1 / (spacing) before its rounding to the grid (0: axis not crossed)
 };
 
+// kObstacle = false leaves out the obstacle's code (only for grids without
+// one); true cuts the ray at the obstacle when the grid has one.
+template <bool kObstacle = true>
 __device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, int row,
                                  RayState &r, RayAxes *ax = nullptr)
 {
@@ -152,6 +155,35 @@ __device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, in
         r.s[a] = sf[a];
         r.ds[a] = ds[a];
     }
+    if (kObstacle && g.has_sph) {
+        // the obstacle: the line of sight ends where it enters the sphere's
+        // interior, found from the closest approach t* of the line to the
+        // centre (at distance h): t* - sqrt((R^2 - h^2) / d.d); the end is
+        // put on the ray's grid, so that every walk stops at the same value
+        double oc[3], dd = 0.0, od = 0.0, oo = 0.0;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            oc[a] = v.o[a] - g.sph[a];
+            dd = fma(d[a], d[a], dd);
+            od = fma(oc[a], d[a], od);
+            oo = fma(oc[a], oc[a], oo);
+        }
+        const double r2 = g.sph[3] * g.sph[3];
+        if (oo <= r2) return false;  // observer on or inside the sphere
+        if (od < 0.0) {
+            const double ts = -od / dd;
+            double h2 = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double p = fma(ts, d[a], oc[a]);
+                h2 = fma(p, p, h2);
+            }
+            if (h2 < r2) {
+                const double tc = ts - sqrt((r2 - h2) / dd) - tin;  // from the entry
+                send = fmin(send, ldexp(rint(ldexp(tc, 51 - ex)), ex - 51));
+            }
+        }
+    }
     if (!(send > 0.0) || !(send < kFar)) return false;
     r.send = send;
     r.off = (idx[2] * g.n[1] + idx[1]) * g.n[0] + idx[0];
@@ -241,7 +273,7 @@ __device__ inline int64_t block_tile(const Bundle &b)
 
 // P for one 16x16 tile (all threads of the workgroup): each lane's pixel =
 // sum over its ray's segments of length x voxel value, written to images.
-template <bool kMapMask, bool kDataMask>
+template <bool kMapMask, bool kDataMask, bool kObstacle>
 __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict__ views, int32_t nviews,
                                     int log2_bw, int64_t tile, int32_t maxit,
                                     const float *__restrict__ cube, const uint8_t *__restrict__ map_mask,
@@ -253,7 +285,7 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
     const int64_t pix = v.pix_off + (int64_t)lp.row * v.ncol + lp.col;
     float out = 0.0f;
     RayState r;
-    if ((!kDataMask || data_mask[pix]) && ray_setup(g, v, lp.col, lp.row, r)) {
+    if ((!kDataMask || data_mask[pix]) && ray_setup<kObstacle>(g, v, lp.col, lp.row, r)) {
         const auto rc = make_rsrc(cube + (int64_t)v.frame * g.nvox, (uint32_t)(g.nvox * 4));
         // software-pipelined by one segment: a step issues its voxel's gather
         // and adds the previous segment, so each load has a whole step to land

@@ -44,9 +44,14 @@ class TomoView(ctypes.Structure):
                 ("ncol", c_int32), ("nrow", c_int32), ("frame", c_int32), ("reserved", c_int32)]
 
 
+class TomoObstacle(ctypes.Structure):
+    _fields_ = [("center", c_double * 3), ("radius", c_double)]
+
+
 class TomoGeometry(ctypes.Structure):
     _fields_ = [("cube", TomoCube), ("nviews", c_int32), ("reserved", c_int32),
-                ("views", POINTER(TomoView)), ("data_mask", c_void_p), ("map_mask", c_void_p)]
+                ("views", POINTER(TomoView)), ("data_mask", c_void_p), ("map_mask", c_void_p),
+                ("obstacle", POINTER(TomoObstacle))]
 
 
 class Tuning(ctypes.Structure):
@@ -170,7 +175,8 @@ class DeviceGeometry:
     """Marshals a geometry description (box, views, masks) into a
     tomo_geometry.  ``geom`` needs the attributes n, lo, hi, views (V x 16:
     obs, w, u, v, cdelt, crpix), npix (V x 2), view_frame (or None), nframes,
-    data_mask (or None) and map_mask (or None); masks are copied to the
+    data_mask (or None) and map_mask (or None), and may have obstacle
+    ((cx, cy, cz, R) of an opaque sphere, or None); masks are copied to the
     device once."""
 
     def __init__(self, geom, device="cuda"):
@@ -198,9 +204,15 @@ class DeviceGeometry:
         cube = TomoCube(self.n[0], self.n[1], self.n[2], self.nframes,
                         (c_double * 3)(*np.asarray(geom.lo, dtype=np.float64)),
                         (c_double * 3)(*np.asarray(geom.hi, dtype=np.float64)))
+        ob = getattr(geom, "obstacle", None)
+        self._obstacle = None
+        if ob is not None:
+            ob = np.asarray(ob, dtype=np.float64).reshape(4)
+            self._obstacle = TomoObstacle((c_double * 3)(*ob[:3]), float(ob[3]))
         self.g = TomoGeometry(cube, self.nviews, 0, arr,
                               None if self.data_mask is None else self.data_mask.data_ptr(),
-                              None if self.map_mask is None else self.map_mask.data_ptr())
+                              None if self.map_mask is None else self.map_mask.data_ptr(),
+                              None if self._obstacle is None else ctypes.pointer(self._obstacle))
 
     @staticmethod
     def _mask(m, numel, device):
