@@ -16,7 +16,8 @@ preconditioner's wall time to relative residual 1e-3 is compared with plain
 CG on held-out problems of its own family (time_to_rel_res_1e-3), and the
 COR1-like batch (five systems of uneven size in persistent launches with
 autotuned shapes) is timed against solving its systems one after another
-(batched).
+(batched), and the obstacle variant (lines of sight ending at the
+photosphere) is measured on the headline workload (obstacle).
 """
 from __future__ import annotations
 
@@ -77,6 +78,8 @@ def parse():
                     help="skip the learned-vs-plain time to relative residual 1e-3")
     ap.add_argument("--no-batch", action="store_true",
                     help="skip the batched COR1-like measurement")
+    ap.add_argument("--no-obstacle", action="store_true",
+                    help="skip the obstacle-variant measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the timed steps, run 3 device-to-device copies of MIB MiB: the "
                          "known-size kernel that calibrates hardware byte counters")
@@ -171,6 +174,50 @@ def batched_cor1(tomo, ts, iters=10, reps=3):
     batch.close()
     tomo.autotune_clear()
     return out
+
+
+def obstacle_euvi(tomo, ts, wl, y, reps=10):
+    """The obstacle variant on the EUVI-like workload: the same views and
+    cube with the photosphere (unit sphere at the centre) ending every line
+    of sight.  P and P^T per launch (HIP events on the launch stream, median
+    of `reps`) and one 50-iteration CG step."""
+    import torch
+
+    g0 = wl.geom
+    g = ts.Geometry(g0.n, g0.lo, g0.hi, g0.views, g0.npix, map_mask=g0.map_mask,
+                    obstacle=np.array([0.0, 0.0, 0.0, 1.0]))
+    dg = tomo.DeviceGeometry(g)
+    cross = tomo.count_crossings(dg)
+    x = torch.zeros(dg.cube_shape, dtype=torch.float32, device="cuda")
+    img = torch.empty_like(y)
+
+    def per_launch(f):
+        f()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            f()
+            e1.record()
+            e1.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(np.median(out))
+
+    ms_p = per_launch(lambda: tomo.project(dg, x, out=img))
+    ms_bp = per_launch(lambda: tomo.backproject(dg, y, out=x))
+    tomo.cg_solve(dg, y, lam_r=wl.lam_r, max_iter=wl.cg_iters, out=x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep = tomo.cg_solve(dg, y, lam_r=wl.lam_r, max_iter=wl.cg_iters, out=x)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    apps = rep["n_project"] + rep["n_backproject"]
+    return {"workload": "EUVI-like (as the headline) with the photosphere as obstacle: lines of sight end "
+                        "where they enter the unit sphere",
+            "crossings_per_application": cross, "k_project_ms": ms_p, "k_backproject_ms": ms_bp,
+            "project_crossings_per_s": cross / (ms_p * 1e-3), "backproject_crossings_per_s": cross / (ms_bp * 1e-3),
+            "ms_per_step": 1e3 * dt, "crossings_per_s": apps * cross / dt, "final_rel_res": rep["rel_res"]}
 
 
 def cpu_baseline(wl, reps):
@@ -290,6 +337,9 @@ def main():
     if not args.no_batch:
         out["batched"] = batched_cor1(tomo, ts)
         log("batched COR1-like done")
+    if not args.no_obstacle:
+        out["obstacle"] = obstacle_euvi(tomo, ts, wl, y)
+        log("obstacle variant done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_reps)
         log("cpu baseline done")
