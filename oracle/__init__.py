@@ -19,6 +19,9 @@ Contents, each following the paper (Barbey, Guennou & Auchere, Solar Physics,
   as untried (Sec. "Smooth Temporal Evolution"), as flexible CG around a small
   3-D convolution network, and the network's training step.
 * ``view_from_wcs``: the oracle's own reading of WCS pointing keywords.
+* ``thomson_*``: the white-light Thomson-scattering operators of
+  Sec. "White Light: Thomson Scattering" (Eq. thomson_lo, Eq. brightness,
+  Eq. thomson_direct): pB = O P M n_e and B = (-O P M + P M') n_e.
 
 Parity status: every function above is pinned by ``tests/test_oracle_*.py``
 except the learned network's *benefit*, which the paper does not quantify
@@ -498,3 +501,91 @@ def view_from_wcs(dsun, hgln_deg, hglt_deg, crval1_as, crval2_as, crota_deg,
     row = np.concatenate([obs, w, u, v, [cdelt1_as * a2r, cdelt2_as * a2r],
                           [crpix1 - 1.0, crpix2 - 1.0]])
     return row, np.array([ncol, nrow], dtype=np.int32)
+
+
+# ------------------------------------------------------- Thomson scattering
+
+
+def thomson_c1234(sin_omega):
+    """Billings' coefficients C1..C4 of Eq. 4C at sin(Omega) = R_sun / r,
+    Omega the half-angle of the solar disc seen from the scattering point.
+    C4 takes +1/8 in front of its bracket: the printed minus sign would make
+    the fully limb-darkened total brightness negative, and only +1/8 gives
+    C4 / C3 -> 2/3 as Omega -> 0 (the flux of a linearly limb-darkened disc
+    relative to a uniform one), as C2 / C1 does."""
+    s = np.asarray(sin_omega, dtype=np.float64)
+    c = np.sqrt(1.0 - s * s)
+    lg = np.log((1.0 + s) / c)
+    c1 = c * s * s
+    c2 = -0.125 * (1.0 - 3.0 * s * s - (c * c / s) * (1.0 + 3.0 * s * s) * lg)
+    c3 = 4.0 / 3.0 - c - c ** 3 / 3.0
+    c4 = 0.125 * (5.0 + s * s - (c * c / s) * (5.0 - s * s) * lg)
+    return c1, c2, c3, c4
+
+
+def thomson_voxel_weights(g, u, sun=(0.0, 0.0, 0.0, 1.0)):
+    """Per-voxel diagonals m_j and m'_j (Eq. thomson_lo, with the limb-
+    darkening factor u on C2 and C4 and the factor 2 of the radial term
+    taken from Eq. brightness): at the voxel centre's distance r from the
+    Sun's centre, in solar radii R (sun = (cx, cy, cz, R)),
+      m  = ((1 - u) C1 + u C2) / r^4,   m' = 2 ((1 - u) C3 + u C4) / r^2,
+    and 0 for centres on or inside the photosphere (r <= 1).  Shape of one
+    frame, z slowest."""
+    nx, ny, nz = g.n
+    cen = [g.lo[a] + (np.arange(k) + 0.5) * (g.hi[a] - g.lo[a]) / k for a, k in enumerate((nx, ny, nz))]
+    zz, yy, xx = np.meshgrid(cen[2], cen[1], cen[0], indexing="ij")
+    r = np.sqrt((xx - sun[0]) ** 2 + (yy - sun[1]) ** 2 + (zz - sun[2]) ** 2) / sun[3]
+    out = r > 1.0
+    rr = np.where(out, r, 2.0)
+    c1, c2, c3, c4 = thomson_c1234(1.0 / rr)
+    m = np.where(out, ((1.0 - u) * c1 + u * c2) / rr ** 4, 0.0)
+    mp = np.where(out, 2.0 * ((1.0 - u) * c3 + u * c4) / rr ** 2, 0.0)
+    return m, mp
+
+
+def thomson_pixel_weights(g, sun=(0.0, 0.0, 0.0, 1.0)):
+    """o_k = rho_k^2 (Eq. thomson_lo): the squared impact parameter, in solar
+    radii, of every pixel's line of sight (its distance from the Sun's
+    centre), views concatenated."""
+    out = np.empty(g.nrays)
+    off = g.view_offsets()
+    c = np.asarray(sun[:3], dtype=np.float64)
+    for v in range(g.nviews):
+        ncol, nrow = (int(k) for k in g.npix[v])
+        o = g.views[v, 0:3] - c
+        k = off[v]
+        for row in range(nrow):
+            for col in range(ncol):
+                d = pixel_direction(g.views[v], g.npix[v], col, row)
+                cr = np.cross(o, d)
+                out[k] = (cr @ cr) / (d @ d) / sun[3] ** 2
+                k += 1
+    return out
+
+
+def _frames(w, g):
+    return w if g.nframes == 1 else np.broadcast_to(w, (g.nframes,) + w.shape)
+
+
+def thomson_project(g, ne, u, kind, scale=1.0, sun=(0.0, 0.0, 0.0, 1.0)):
+    """Eq. thomson_direct without noise: kind 'pB' gives scale O P M n_e,
+    kind 'B' gives scale (-O P M + P M') n_e."""
+    m, mp = thomson_voxel_weights(g, u, sun)
+    o = thomson_pixel_weights(g, sun)
+    ne = np.asarray(ne, dtype=np.float64)
+    pm = project(g, ne * _frames(m, g))
+    if kind == "pB":
+        return scale * o * pm
+    return scale * (project(g, ne * _frames(mp, g)) - o * pm)
+
+
+def thomson_backproject(g, y, u, kind, scale=1.0, sun=(0.0, 0.0, 0.0, 1.0)):
+    """Transposes: scale M P^T O y (pB), scale (M' P^T y - M P^T O y) (B)."""
+    m, mp = thomson_voxel_weights(g, u, sun)
+    o = thomson_pixel_weights(g, sun)
+    y = np.asarray(y, dtype=np.float64).ravel()
+    bo = backproject(g, o * y) * _frames(m, g)
+    if kind == "pB":
+        return scale * bo
+    return scale * (backproject(g, y) * _frames(mp, g) - bo)
+
