@@ -220,6 +220,40 @@ int tomo_set_tuning(const tomo_tuning *in);
 int tomo_binning_spills(const tomo_geometry *g, int64_t *count_h);
 
 /*
+ * White-light Thomson-scattering operators (Sec. "White Light: Thomson
+ * Scattering"; Eq. 4C, Eq. thomson_lo, Eq. brightness, Eq. thomson_direct):
+ *   pB = scale O P M n_e,        B = scale (P M' - O P M) n_e,
+ * with O = diag(rho_k^2) over pixels (rho the impact parameter of the line
+ * of sight) and M, M' diagonal over voxels from Billings' coefficients at
+ * sin(Omega) = R_sun / r:
+ *   m = ((1 - u) C1 + u C2) / r^4,   m' = 2 ((1 - u) C3 + u C4) / r^2,
+ * r and rho in solar radii from the Sun's centre; 0 for voxel centres on or
+ * inside the photosphere.  C4 = +1/8 [5 + sin^2 - cos^2/sin (5 - sin^2)
+ * ln((1 + sin)/cos)] (the sign its small-angle limit requires).  The map
+ * mask multiplies M and M'; masked pixels give 0.  B costs two projections.
+ * Work memory: stream-ordered scratch (hipMallocAsync) of one cube and, for
+ * B, one more cube and one image set (plus the blocked back-projection's).
+ */
+typedef struct tomo_thomson {
+    double u;             /* limb darkening, in [0, 1]                           */
+    double scale;         /* the constant pi sigma I0 / 2 (1: unit-free)         */
+    double sun_center[3]; /* cube frame, box units                               */
+    double sun_radius;    /* > 0, box units (1 when the box is in R_sun)         */
+} tomo_thomson;
+
+enum { TOMO_THOMSON_PB = 0, TOMO_THOMSON_B = 1 };
+
+/* images_d = T n_e (T = T_pB or T_B by kind); ne_d, images_d as in
+ * tomo_project. */
+int tomo_thomson_project(const tomo_geometry *g, const tomo_thomson *t, int32_t kind,
+                         const float *ne_d, float *images_d, tomo_stream stream);
+
+/* ne_d = T^T y (or += with accumulate != 0); deterministic (blocked P^T). */
+int tomo_thomson_backproject(const tomo_geometry *g, const tomo_thomson *t, int32_t kind,
+                             const float *images_d, float *ne_d, int32_t accumulate,
+                             tomo_stream stream);
+
+/*
  * Prior term (Sec. "Single Spacecraft Static Tomography"; Eq. stsrt):
  *   out = [out if accumulate] + lambda_r D^T D x + lambda_t D_t^T D_t x
  * with D the forward differences between in-cube neighbours along x, y and

@@ -6,5 +6,6 @@ from .tomo import (  # noqa: F401
     NPARAMS, Batch, ConvNet, adam_step, autotune, autotune_clear, class_tuning,
     BP_ATOMIC, BP_AUTO, BP_BINNED, BP_BLOCKED, DeviceGeometry, TomoError, apply_prior, backproject,
     binning_spills, cg_solve, get_tuning, set_tuning,
-    count_crossings, lib, project, status_string, trace_ray, validate, view_from_wcs,
+    count_crossings, lib, project, status_string, thomson_backproject, thomson_project, trace_ray, validate,
+    view_from_wcs,
 )

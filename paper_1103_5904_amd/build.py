@@ -13,7 +13,7 @@ LIB = os.path.join(HERE, "libtomo.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
 
 SOURCES = ["api.hip", "siddon.hip", "binned.hip", "blocked.hip", "batch.hip", "tune.hip", "solver.hip",
-           "convnet.hip"]
+           "convnet.hip", "thomson.hip"]
 
 # The projector's inputs are validated finite, so its min/max need no NaN
 # quieting; the solver keeps IEEE NaN semantics for its non-finite checks.

@@ -54,6 +54,13 @@ class TomoGeometry(ctypes.Structure):
                 ("obstacle", POINTER(TomoObstacle))]
 
 
+class ThomsonParams(ctypes.Structure):
+    _fields_ = [("u", c_double), ("scale", c_double), ("sun_center", c_double * 3), ("sun_radius", c_double)]
+
+
+THOMSON_KINDS = {"pB": 0, "B": 1}
+
+
 class Tuning(ctypes.Structure):
     _fields_ = [("p_bundle", c_int32), ("p_xcd_remap", c_int32), ("bp_bundle", c_int32),
                 ("bp_xcd_remap", c_int32), ("bp_lds_bins", c_int32), ("bp_default", c_int32),
@@ -79,6 +86,7 @@ class CgReport(ctypes.Structure):
 
 EXPORTS = [
     "tomo_project", "tomo_backproject", "tomo_backproject_ex", "tomo_count_crossings",
+    "tomo_thomson_project", "tomo_thomson_backproject",
     "tomo_trace_ray", "tomo_apply_prior", "tomo_cg_solve", "tomo_cg_default_params",
     "tomo_view_from_wcs", "tomo_validate_geometry", "tomo_geometry_pixels",
     "tomo_release_cache", "tomo_status_string", "tomo_last_error", "tomo_binning_spills",
@@ -148,6 +156,10 @@ def lib():
         L.tomo_batch_cg_solve.argtypes = [c_void_p, POINTER(c_void_p), POINTER(c_void_p), POINTER(CgParams),
                                           POINTER(CgReport), c_void_p]
         L.tomo_geometry_pixels.argtypes = [POINTER(TomoGeometry)]
+        L.tomo_thomson_project.argtypes = [POINTER(TomoGeometry), POINTER(ThomsonParams), c_int32, c_void_p,
+                                           c_void_p, c_void_p]
+        L.tomo_thomson_backproject.argtypes = [POINTER(TomoGeometry), POINTER(ThomsonParams), c_int32,
+                                               c_void_p, c_void_p, c_int32, c_void_p]
         _lib = L
     return _lib
 
@@ -429,6 +441,38 @@ def trace_ray(geom: DeviceGeometry, view: int, col: int, row: int):
     k = n.value
     return (np.ctypeslib.as_array(idx)[:k].copy(), np.ctypeslib.as_array(ln)[:k].copy(),
             np.ctypeslib.as_array(dp)[:k].copy())
+
+
+def _thomson_params(u, scale, sun):
+    sun = np.asarray(sun, dtype=np.float64).reshape(4)
+    return ThomsonParams(float(u), float(scale), (c_double * 3)(*sun[:3]), float(sun[3]))
+
+
+def thomson_project(geom: DeviceGeometry, ne: torch.Tensor, u: float = 0.6, kind: str = "pB",
+                    scale: float = 1.0, sun=(0.0, 0.0, 0.0, 1.0), out: torch.Tensor | None = None):
+    """Thomson-scattering images T n_e (kind "pB": scale O P M n_e; "B":
+    scale (P M' - O P M) n_e); sun = (cx, cy, cz, R_sun) in box units."""
+    if out is None:
+        out = torch.empty(geom.npix, dtype=torch.float32, device=ne.device)
+    t = _thomson_params(u, scale, sun)
+    _check(lib().tomo_thomson_project(geom.ref, ctypes.byref(t), THOMSON_KINDS[kind],
+                                      _dev_f32(ne, geom.nvox * geom.nframes, "ne"),
+                                      _dev_f32(out, geom.npix, "out"), _stream()))
+    return out
+
+
+def thomson_backproject(geom: DeviceGeometry, images: torch.Tensor, u: float = 0.6, kind: str = "pB",
+                        scale: float = 1.0, sun=(0.0, 0.0, 0.0, 1.0), out: torch.Tensor | None = None,
+                        accumulate: bool = False):
+    """Transpose T^T y of thomson_project (or += with accumulate)."""
+    if out is None:
+        out = torch.empty(geom.cube_shape, dtype=torch.float32, device=images.device)
+    t = _thomson_params(u, scale, sun)
+    _check(lib().tomo_thomson_backproject(geom.ref, ctypes.byref(t), THOMSON_KINDS[kind],
+                                          _dev_f32(images, geom.npix, "images"),
+                                          _dev_f32(out, geom.nvox * geom.nframes, "out"),
+                                          int(bool(accumulate)), _stream()))
+    return out
 
 
 def apply_prior(geom: DeviceGeometry, x: torch.Tensor, lam_r: float, lam_t: float = 0.0,

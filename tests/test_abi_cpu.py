@@ -136,3 +136,25 @@ def test_wcs_rejects_bad_keywords(tomo):
         tomo.view_from_wcs(0.0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 8, 8)
     with pytest.raises(tomo.TomoError):
         tomo.view_from_wcs(215.0, np.nan, 0, 0, 0, 0, 1, 1, 1, 1, 8, 8)
+
+
+@pytest.mark.parametrize("case", ["u_high", "u_nan", "radius", "kind", "centre"])
+def test_thomson_parameters_rejected(tomo, case):
+    """Invalid Thomson parameters return TOMO_EINVAL before any device work."""
+    dg = tomo.DeviceGeometry(_geom(), device="cpu")
+    u, scale, sun, kind = 0.6, 1.0, [0.0, 0.0, 0.0, 1.0], 0
+    if case == "u_high":
+        u = 1.5
+    elif case == "u_nan":
+        u = float("nan")
+    elif case == "radius":
+        sun[3] = 0.0
+    elif case == "kind":
+        kind = 2
+    elif case == "centre":
+        sun[1] = float("inf")
+    t = tomo.tomo._thomson_params(u, scale, sun)
+    rc = tomo.lib().tomo_thomson_project(dg.ref, ctypes.byref(t), kind, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                         None)
+    assert rc == tomo.tomo.TOMO_EINVAL
+    assert tomo.lib().tomo_last_error()
