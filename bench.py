@@ -16,8 +16,9 @@ preconditioner's wall time to relative residual 1e-3 is compared with plain
 CG on held-out problems of its own family (time_to_rel_res_1e-3), and the
 COR1-like batch (five systems of uneven size in persistent launches with
 autotuned shapes) is timed against solving its systems one after another
-(batched), and the obstacle variant (lines of sight ending at the
-photosphere) is measured on the headline workload (obstacle).
+(batched), the obstacle variant (lines of sight ending at the photosphere)
+is measured on the headline workload (obstacle), and the Thomson-scattering
+operators pB and B on a COR1-like frame (thomson).
 """
 from __future__ import annotations
 
@@ -80,6 +81,8 @@ def parse():
                     help="skip the batched COR1-like measurement")
     ap.add_argument("--no-obstacle", action="store_true",
                     help="skip the obstacle-variant measurement")
+    ap.add_argument("--no-thomson", action="store_true",
+                    help="skip the Thomson-scattering operator measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the timed steps, run 3 device-to-device copies of MIB MiB: the "
                          "known-size kernel that calibrates hardware byte counters")
@@ -220,6 +223,46 @@ def obstacle_euvi(tomo, ts, wl, y, reps=10):
             "ms_per_step": 1e3 * dt, "crossings_per_s": apps * cross / dt, "final_rel_res": rep["rel_res"]}
 
 
+def thomson_cor1(tomo, ts, reps=5):
+    """Thomson-scattering operators on a static COR1-like frame: 256^3 on
+    [-4, 4]^3 R_sun, all 60 views of 512^2 (annulus 1.4-4 R_sun kept, unit
+    sphere masked), u = 0.63: T_pB and T_B and their transposes per call
+    (HIP events on the launch stream, median of `reps`)."""
+    import torch
+
+    wl = ts.cor1_frames(K=1)
+    dg = tomo.DeviceGeometry(wl.geom)
+    cross = tomo.count_crossings(dg)
+    ne = torch.as_tensor(wl.x.reshape(dg.cube_shape).astype(np.float32)).cuda()
+    img = torch.empty(dg.npix, dtype=torch.float32, device="cuda")
+    back = torch.empty(dg.cube_shape, dtype=torch.float32, device="cuda")
+
+    def per_call(f):
+        f()
+        torch.cuda.synchronize()
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            f()
+            e1.record()
+            e1.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(np.median(out))
+
+    res = {"workload": "COR1-like static frame: 256^3 on [-4,4]^3 R_sun, 60 views of 512^2, annulus "
+                       "1.4-4 R_sun, unit sphere masked, u 0.63",
+           "crossings_per_projection": cross}
+    for kind in ("pB", "B"):
+        nproj = 1 if kind == "pB" else 2
+        ms_f = per_call(lambda: tomo.thomson_project(dg, ne, 0.63, kind, out=img))
+        ms_b = per_call(lambda: tomo.thomson_backproject(dg, img, 0.63, kind, out=back))
+        res[kind] = {"project_ms": ms_f, "backproject_ms": ms_b,
+                     "project_crossings_per_s": nproj * cross / (ms_f * 1e-3),
+                     "backproject_crossings_per_s": nproj * cross / (ms_b * 1e-3)}
+    return res
+
+
 def cpu_baseline(wl, reps):
     """The FP64 oracle (as it stands) on a bounded sample: `reps` passes of
     P and P^T over the full geometry (the CG's operator pair), all host
@@ -340,6 +383,9 @@ def main():
     if not args.no_obstacle:
         out["obstacle"] = obstacle_euvi(tomo, ts, wl, y)
         log("obstacle variant done")
+    if not args.no_thomson:
+        out["thomson"] = thomson_cor1(tomo, ts)
+        log("Thomson operators done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_reps)
         log("cpu baseline done")
