@@ -12,7 +12,12 @@ Contents, each following the paper (Barbey, Guennou & Auchere, Solar Physics,
   ``oracle.c``); ``ray_row_bruteforce`` recomputes one row straight from the
   definition (per-voxel slab clip).
 * ``laplacian6`` / ``laplacian_t``: D^T D for the finite-difference priors
-  (Sec. "Single Spacecraft Static Tomography"; Eq. stsrt for time).
+  (Sec. "Single Spacecraft Static Tomography"; Eq. stsrt for time);
+  ``voxel_heights`` / ``height_prior``: R D^T D R, the prior weighted by
+  voxel height of Eq. srt_inversion.
+* ``ray_gains``: the per-instrument gains of Eq. two_spacecraft /
+  Eq. lin2space, applied by ``project`` and ``backproject`` when the
+  geometry carries them.
 * ``normal_operator`` / ``cg``: the normal equations of Eq. criterion,
   (P^T P + lambda D^T D) x = P^T y, solved by textbook conjugate gradient.
 * ``fcg``, ``convnet_*``, ``adam_step``: the preconditioner the paper names
@@ -89,11 +94,24 @@ def _obstacle(g):
     return None if ob is None else np.ascontiguousarray(ob, dtype=np.float64).reshape(4)
 
 
+def ray_gains(g):
+    """The gain of each ray's instrument (Eq. two_spacecraft, Eq. lin2space:
+    view v's rows of the stacked operator are g_v P_v), one value per pixel
+    in image order, or None when the geometry has no gains (all 1)."""
+    gn = getattr(g, "gains", None)
+    if gn is None:
+        return None
+    gn = np.asarray(gn, dtype=np.float64).reshape(g.nviews)
+    return np.repeat(gn, g.npix[:, 0].astype(np.int64) * g.npix[:, 1])
+
+
 # ------------------------------------------------------------- projector
 
 
 def project(g, cube, nthreads: int = 0, use_map_mask: bool = True) -> np.ndarray:
-    """(P M x): one line integral per pixel, concatenated over views."""
+    """(G P M x): one line integral per pixel, concatenated over views, times
+    the gain of the view's instrument when the geometry has gains (G, the
+    diagonal of ``ray_gains``)."""
     lib = _load()
     n, lo, hi, views, npix, vf, dm, mm = _geom_args(g)
     x = np.ascontiguousarray(cube, dtype=np.float64)
@@ -104,15 +122,20 @@ def project(g, cube, nthreads: int = 0, use_map_mask: bool = True) -> np.ndarray
                          _p(out), ctypes.c_int(nthreads))
     if rc:
         raise MemoryError("oracle projection failed")
-    return out
+    gr = ray_gains(g)
+    return out if gr is None else out * gr
 
 
 def backproject(g, images, nthreads: int = 0, use_map_mask: bool = True) -> np.ndarray:
-    """(M P^T y), returned in the geometry's cube shape."""
+    """(M P^T G y), the transpose of ``project``, returned in the geometry's
+    cube shape."""
     lib = _load()
     n, lo, hi, views, npix, vf, dm, mm = _geom_args(g)
     y = np.ascontiguousarray(images, dtype=np.float64).ravel()
     assert y.size == g.nrays
+    gr = ray_gains(g)
+    if gr is not None:
+        y = np.ascontiguousarray(y * gr)
     out = np.empty(g.nvox * g.nframes, dtype=np.float64)
     rc = lib.ora_backproject(_p(n), _p(lo), _p(hi), ctypes.c_int(g.nviews), _p(views), _p(npix),
                              _p(vf), ctypes.c_int(g.nframes), _p(dm),
@@ -180,8 +203,9 @@ def pixel_direction(view16, npix, col, row) -> np.ndarray:
 
 
 def dense_matrix(g) -> np.ndarray:
-    """P as a dense (rays x voxels) matrix, one Siddon trace per ray (tiny
-    geometries only).  Data-masked rows are zero."""
+    """The geometric P as a dense (rays x voxels) matrix, one Siddon trace
+    per ray (tiny geometries only; gains are not applied).  Data-masked rows
+    are zero."""
     rows = []
     off = g.view_offsets()
     for v in range(g.nviews):
@@ -230,16 +254,41 @@ def laplacian_t(x) -> np.ndarray:
     return _dtd_along(x, 0)
 
 
-def normal_operator(g, lam_r, lam_t=0.0, nthreads=0):
-    """x -> M (P^T P + lam_r D^T D + lam_t D_t^T D_t) M x on the geometry's
-    cube shape; the map mask M restricts the unknowns (operator P M)."""
+def voxel_heights(g, height):
+    """Diagonal of R in Eq. srt_inversion for height = (cx, cy, cz, offset):
+    the distance from each voxel's centre to the point (cx, cy, cz) (the
+    Sun's centre), plus offset, in box units, shaped (nz, ny, nx)."""
+    cx, cy, cz, off = (float(t) for t in height)
+    ax = []
+    for a, c in zip(range(3), (cx, cy, cz)):
+        n = int(g.n[a])
+        step = (float(g.hi[a]) - float(g.lo[a])) / n
+        ax.append(float(g.lo[a]) + (np.arange(n) + 0.5) * step - c)
+    zz, yy, xx = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return np.sqrt(xx * xx + yy * yy + zz * zz) + off
+
+
+def height_prior(x, h) -> np.ndarray:
+    """R D^T D R x with R = diag(h) (Eq. srt_inversion): the spatial prior
+    of every frame with each voxel weighted by its height."""
+    x = np.asarray(x, dtype=np.float64)
+    return h * laplacian6(h * x)
+
+
+def normal_operator(g, lam_r, lam_t=0.0, nthreads=0, height=None):
+    """x -> M (P^T G^2 P + lam_r R D^T D R + lam_t D_t^T D_t) M x on the
+    geometry's cube shape: the map mask M restricts the unknowns (operator
+    P M), G holds the instruments' gains (Eq. srt_multiple_inv) and R the
+    voxel heights when ``height`` = (cx, cy, cz, offset) is given
+    (Eq. srt_inversion; R = I otherwise)."""
     mm = None if g.map_mask is None else g.map_mask.astype(np.float64)
+    h = None if height is None else voxel_heights(g, height)
 
     def apply(x):
         x = np.asarray(x, dtype=np.float64).reshape(g.cube_shape())
         xm = x * mm if mm is not None else x
         q = backproject(g, project(g, xm, nthreads), nthreads, use_map_mask=False)
-        q = q + lam_r * laplacian6(xm)
+        q = q + lam_r * (laplacian6(xm) if h is None else height_prior(xm, h))
         if lam_t:
             q = q + lam_t * laplacian_t(xm)
         return q * mm if mm is not None else q
@@ -248,19 +297,21 @@ def normal_operator(g, lam_r, lam_t=0.0, nthreads=0):
 
 
 def rhs(g, y, nthreads=0):
-    """b = M P^T y."""
+    """b = M P^T G y."""
     return backproject(g, y, nthreads)
 
 
-def criterion(g, x, y, lam_r, lam_t=0.0):
-    """J(x) = ||y - P M x||^2 + lam_r ||D M x||^2 + lam_t ||D_t M x||^2 (Eq.
-    criterion / Eq. stsrt)."""
+def criterion(g, x, y, lam_r, lam_t=0.0, height=None):
+    """J(x) = ||y - G P M x||^2 + lam_r ||D R M x||^2 + lam_t ||D_t M x||^2
+    (Eq. criterion, Eq. stsrt, Eq. srt_inversion, Eq. srt_multiple_inv;
+    R = I without ``height``)."""
     x = np.asarray(x, dtype=np.float64).reshape(g.cube_shape())
     xm = x * g.map_mask if g.map_mask is not None else x
     res = y - project(g, xm)
     j = float(res @ res)
+    rx = xm if height is None else xm * voxel_heights(g, height)
     for ax in (-1, -2, -3):
-        j += lam_r * float(np.sum(np.diff(xm, axis=ax) ** 2))
+        j += lam_r * float(np.sum(np.diff(rx, axis=ax) ** 2))
     if lam_t and xm.ndim == 4:
         j += lam_t * float(np.sum(np.diff(xm, axis=0) ** 2))
     return j

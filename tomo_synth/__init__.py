@@ -48,6 +48,7 @@ class Geometry:
     data_mask: Optional[np.ndarray] = None  # (sum ncol*nrow,) uint8, 1 = keep
     map_mask: Optional[np.ndarray] = None  # (nz, ny, nx) uint8, 1 = keep
     obstacle: Optional[np.ndarray] = None  # (cx, cy, cz, R): opaque sphere ending every line of sight
+    gains: Optional[np.ndarray] = None  # (V,) float64 gain of the instrument that took each view
 
     @property
     def nviews(self) -> int:
@@ -83,7 +84,8 @@ class Geometry:
         return Geometry(self.n, self.lo.copy(), self.hi.copy(), self.views[view_ids].copy(),
                         self.npix[view_ids].copy(), vf, self.nframes, dm,
                         None if self.map_mask is None else self.map_mask.copy(),
-                        None if self.obstacle is None else np.array(self.obstacle, dtype=np.float64))
+                        None if self.obstacle is None else np.array(self.obstacle, dtype=np.float64),
+                        None if self.gains is None else np.asarray(self.gains, dtype=np.float64)[view_ids].copy())
 
 
 # ------------------------------------------------------------------ views
