@@ -111,6 +111,13 @@ typedef struct tomo_geometry {
     const tomo_obstacle *obstacle; /* HOST pointer or NULL (no obstacle); read
                                       at every call, applies to P, P^T and the
                                       crossing count alike                   */
+    const double *gains;      /* HOST [nviews] or NULL (all 1): the gain of the
+                                 instrument that took each view, finite
+                                 (Eq. two_spacecraft, Eq. lin2space: the rows
+                                 of view v are g_v P_v).  Applies to P and P^T
+                                 (and so to the solvers and the Thomson
+                                 operators), not to the crossing count or the
+                                 ray trace, which are geometric            */
 } tomo_geometry;
 
 /* Back-projection strategies. */
@@ -265,6 +272,31 @@ int tomo_apply_prior(const tomo_cube *cube, double lambda_r, double lambda_t,
                      const float *x_d, float *out_d, int accumulate,
                      tomo_stream stream);
 
+/*
+ * Voxel heights for the height-weighted prior of Eq. srt_inversion
+ * (lambda ||D R e||^2, R the diagonal of voxel heights): the height of a
+ * voxel is the distance from its centre to `center` (box units; the Sun's
+ * centre) plus `offset` (0: distance from the centre; -1 with a 1 R_sun
+ * Sun: altitude above the photosphere).  Both finite.
+ */
+typedef struct tomo_height {
+    double center[3];
+    double offset;
+} tomo_height;
+
+/*
+ * Height-weighted prior (Eq. srt_inversion; Eq. stsrt for time):
+ *   out = [out if accumulate] + lambda_r R D^T D R x + lambda_t D_t^T D_t x
+ * with R = diag(voxel height) applied to every frame; the temporal term is
+ * not weighted.  Heights are computed on the fly from the voxel indices in
+ * FP32 (no height array is stored).  h == NULL gives tomo_apply_prior.
+ *   x_d, out_d: DEVICE float [nframes][nz][ny][nx], must not overlap.
+ */
+int tomo_apply_height_prior(const tomo_cube *cube, const tomo_height *h,
+                            double lambda_r, double lambda_t,
+                            const float *x_d, float *out_d, int accumulate,
+                            tomo_stream stream);
+
 /* Learned preconditioner network (a 3x3x3 convolution stack, 1 -> 16 -> 16
  * -> 1 channels with ReLU between layers, zero padding 1).  Parameters are a
  * DEVICE float array of TOMO_CONVNET_NPARAMS values, in this order:
@@ -335,6 +367,9 @@ typedef struct tomo_cg_params {
     float *record_r;       /* DEVICE [record_count][voxels] or NULL: residual r_k */
     int32_t record_count;  /* iterates to record (>= 0)                          */
     int32_t reserved;
+    const tomo_height *height; /* HOST pointer or NULL: spatial prior
+                                  lambda_r R D^T D R (Eq. srt_inversion)
+                                  instead of lambda_r D^T D                  */
 } tomo_cg_params;
 
 typedef struct tomo_cg_report {
@@ -358,8 +393,10 @@ typedef struct tomo_cg_report {
 
 /*
  * Conjugate-gradient solution of the normal equations of Eq. criterion /
- * Eq. stsrt,  A x = b  with  A = M (P^T P + lambda_r D^T D + lambda_t D_t^T
- * D_t) M  and  b = M P^T y  (the map mask M restricts the unknowns).
+ * Eq. stsrt,  A x = b  with  A = M (P^T G^2 P + lambda_r R D^T D R +
+ * lambda_t D_t^T D_t) M  and  b = M P^T G y  (the map mask M restricts the
+ * unknowns; G holds the geometry's gains, Eq. srt_multiple_inv; R = I
+ * unless params->height is set, Eq. srt_inversion).
  * Textbook CG (FP32 vectors, FP64 dot products and scalars, kept on the
  * device).  Non-finite values in y (unmasked pixels) are reported as
  * status TOMO_ENONFINITE without iterating.  With a preconditioner network,

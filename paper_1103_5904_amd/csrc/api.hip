@@ -104,6 +104,9 @@ static int validate_geometry_impl(const tomo_geometry *g, int64_t *npix_out)
         if (!finite3(ob.center) || !isfinite(ob.radius) || !(ob.radius > 0.0))
             return set_error(TOMO_EINVAL, "obstacle: centre must be finite and radius finite and > 0");
     }
+    if (g->gains)
+        for (int k = 0; k < g->nviews; ++k)
+            if (!isfinite(g->gains[k])) return set_error(TOMO_EINVAL, "view %d: gain must be finite", k);
     if (npix_out) *npix_out = npix;
     return TOMO_OK;
 }
@@ -131,8 +134,9 @@ static std::vector<unsigned char> geometry_key(const tomo_geometry *g)
 {
     const tomo_obstacle none = {{0.0, 0.0, 0.0}, 0.0};
     const tomo_obstacle &ob = g->obstacle ? *g->obstacle : none;
+    const size_t ng = g->gains ? sizeof(double) * (size_t)g->nviews : 0;
     std::vector<unsigned char> k(sizeof(tomo_cube) + sizeof(int32_t) + sizeof(tomo_obstacle) +
-                                 sizeof(tomo_view) * (size_t)g->nviews);
+                                 sizeof(tomo_view) * (size_t)g->nviews + 1 + ng);
     unsigned char *q = k.data();
     memcpy(q, &g->cube, sizeof(tomo_cube));
     q += sizeof(tomo_cube);
@@ -141,6 +145,9 @@ static std::vector<unsigned char> geometry_key(const tomo_geometry *g)
     memcpy(q, &ob, sizeof(tomo_obstacle));
     q += sizeof(tomo_obstacle);
     memcpy(q, g->views, sizeof(tomo_view) * (size_t)g->nviews);
+    q += sizeof(tomo_view) * (size_t)g->nviews;
+    *q++ = g->gains ? 1 : 0;
+    if (ng) memcpy(q, g->gains, ng);
     return k;
 }
 
@@ -178,6 +185,7 @@ static int build_plan(const tomo_geometry *g, int64_t npix, Plan &p)
         d.cd[1] = v.cdelt[1];
         d.cp[0] = v.crpix[0];
         d.cp[1] = v.crpix[1];
+        d.gain = g->gains ? g->gains[k] : 1.0;
         d.ncol = v.ncol;
         d.nrow = v.nrow;
         d.frame = v.frame;

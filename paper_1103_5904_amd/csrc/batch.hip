@@ -291,6 +291,7 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
         b->plans.push_back(p);
         b->geoms.push_back(systems[k]);
         b->geoms.back().obstacle = nullptr;  // captured in the plan's grid
+        b->geoms.back().gains = nullptr;     // captured in the plan's view table
         b->sys_h.push_back(sd);
     }
     if (b->ntiles >= ((int64_t)1 << 40) || b->nitems >= ((int64_t)1 << 40)) {

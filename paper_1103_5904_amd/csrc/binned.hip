@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kThreads) void k_backproject_binned(
         yv = images[pix];
         if (nonzero_bits(yv) && (!kDataMask || data_mask[pix]) && ray_setup(g, v, lp.col, lp.row, r, &ax)) {
             active = true;
-            wy = (double)yv * r.dn;
+            wy = (double)yv * (r.dn * v.gain);
         }
     }
 
@@ -180,7 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_backproject_binned(
     binned = binned && ymax_bits < 0x7f800000u;
 
     // fixed-point scale: every bin stays below 2^61
-    const double ymax = (double)__builtin_bit_cast(float, ymax_bits);
+    const double ymax = (double)__builtin_bit_cast(float, ymax_bits) * fabs(v.gain);
     const double vdiag = sqrt(g.delta[0] * g.delta[0] + g.delta[1] * g.delta[1] + g.delta[2] * g.delta[2]);
     int eb = 0;
     (void)frexp((double)kThreads * vdiag * ymax * 1.0000001, &eb);  // bound < 2^eb

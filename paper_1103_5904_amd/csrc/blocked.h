@@ -91,19 +91,24 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
 
     const int v0 = frame_voff[frame], v1 = frame_voff[frame + 1];
 
-    // ---- fixed-point scale from the views this owner handles (uniform)
-    uint32_t ybits = 0u;
+    // ---- fixed-point scale from the views this owner handles (uniform):
+    // the largest |gain y| among them
+    bool finite = true;
+    double ymax = 0.0;
     double rays = 0.0;
     for (int k = v0 + split; k < v1; k += bd.splits) {
         const int vi = frame_views[k];
+        uint32_t ybits = 0u;
         for (int p = 0; p < kYmaxParts; ++p) {
             const uint32_t b = ymax_parts[vi * kYmaxParts + p];
             ybits = b > ybits ? b : ybits;
         }
+        if (ybits < 0x7f800000u)
+            ymax = fmax(ymax, (double)__builtin_bit_cast(float, ybits) * fabs(views[vi].gain));
+        else
+            finite = false;
         rays += (double)views[vi].ncol * (double)views[vi].nrow;
     }
-    const bool finite = ybits < 0x7f800000u;
-    const double ymax = (double)__builtin_bit_cast(float, ybits);
     const double vdiag = sqrt(g.delta[0] * g.delta[0] + g.delta[1] * g.delta[1] + g.delta[2] * g.delta[2]);
     // scale 2^(61 - eb): every bin below 2^61 (at most `rays` contributions
     // of at most vdiag max|y| each) and every single contribution below 2^50,
@@ -269,7 +274,7 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                     ++spills;
                     continue;
                 }
-                const double wys = (double)yv * r.dn * (finite ? fx_scale : 1.0);
+                const double wys = (double)yv * (r.dn * v.gain) * (finite ? fx_scale : 1.0);
                 // four steps per loop body, as in ray_walk; the clamp to the
                 // dummy bin nbins only guards the LDS range
                 auto walk = [&](auto deposit) {

@@ -22,6 +22,7 @@ struct ViewDev {
     double v[3];        // +row direction
     double cd[2];       // cdelt (radians per pixel)
     double cp[2];       // crpix (0-based)
+    double gain;        // instrument gain: the view's rows of P are scaled by it
     int64_t pix_off;    // first pixel of the view in the image vector
     int64_t tile_off;   // first 16x16 tile of the view in a launch
     int32_t ncol, nrow;

@@ -66,7 +66,7 @@ __global__ __launch_bounds__(kThreads) void k_backproject_atomic(
     RayState r;
     if (!ray_setup(g, v, lp.col, lp.row, r)) return;
     const auto rc = make_rsrc(cube + (int64_t)v.frame * g.nvox, (uint32_t)(g.nvox * 4));
-    const double wy = (double)yv * r.dn;
+    const double wy = (double)yv * (r.dn * v.gain);
     if constexpr (kMapMask) {
         const auto rm = make_rsrc(map_mask, (uint32_t)g.nvox);
         ray_walk(r, maxit, [&](int32_t off, double dl) {

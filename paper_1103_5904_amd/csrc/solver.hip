@@ -92,23 +92,56 @@ __device__ inline VoxIdx vox_index(const Dims &d, int64_t idx)
     return o;
 }
 
-// lambda_r (D^T D x)_v + lambda_t (D_t^T D_t x)_v: forward differences
+// Voxel heights of the weighted prior (Eq. srt_inversion): the height of
+// voxel (i, j, k) is |c0 + (i, j, k) * step| + offset, c0 the first voxel's
+// centre relative to the height origin.  FP32, recomputed where needed (no
+// height array in memory).
+struct HeightDev {
+    float c0[3];
+    float step[3];
+    float offset;
+    int32_t pad;
+};
+
+__device__ inline float height_of(float dx, float dy, float dz, float off)
+{
+    return sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz))) + off;
+}
+
+// lambda_r (D^T D x)_v + lambda_t (D_t^T D_t x)_v, or with kHeight
+// lambda_r (R D^T D R x)_v + lambda_t (D_t^T D_t x)_v: forward differences
 // between in-range neighbours only (free ends).
+template <bool kHeight = false>
 __device__ inline float prior_at(const float *__restrict__ x, const Dims &d, int64_t idx, const VoxIdx &c_,
-                                 float lr, float lt)
+                                 float lr, float lt, const HeightDev &hd = HeightDev{})
 {
     const int32_t i = c_.i, j = c_.j, k = c_.k;
     const int64_t f = c_.f;
     const float c = x[idx];
-    float s = 0.0f;
-    if (i > 0) s += c - x[idx - 1];
-    if (i < d.nx - 1) s += c - x[idx + 1];
-    if (j > 0) s += c - x[idx - d.nx];
-    if (j < d.ny - 1) s += c - x[idx + d.nx];
     const int64_t pl = (int64_t)d.nx * d.ny;
-    if (k > 0) s += c - x[idx - pl];
-    if (k < d.nz - 1) s += c - x[idx + pl];
-    float out = lr * s;
+    float s = 0.0f, w = 1.0f;
+    if constexpr (!kHeight) {
+        if (i > 0) s += c - x[idx - 1];
+        if (i < d.nx - 1) s += c - x[idx + 1];
+        if (j > 0) s += c - x[idx - d.nx];
+        if (j < d.ny - 1) s += c - x[idx + d.nx];
+        if (k > 0) s += c - x[idx - pl];
+        if (k < d.nz - 1) s += c - x[idx + pl];
+    } else {
+        // (R D^T D R x)_v = h_v sum over neighbours n of (h_v x_v - h_n x_n)
+        const float dx = fmaf((float)i, hd.step[0], hd.c0[0]);
+        const float dy = fmaf((float)j, hd.step[1], hd.c0[1]);
+        const float dz = fmaf((float)k, hd.step[2], hd.c0[2]);
+        w = height_of(dx, dy, dz, hd.offset);
+        const float hc = w * c;
+        if (i > 0) s += hc - height_of(dx - hd.step[0], dy, dz, hd.offset) * x[idx - 1];
+        if (i < d.nx - 1) s += hc - height_of(dx + hd.step[0], dy, dz, hd.offset) * x[idx + 1];
+        if (j > 0) s += hc - height_of(dx, dy - hd.step[1], dz, hd.offset) * x[idx - d.nx];
+        if (j < d.ny - 1) s += hc - height_of(dx, dy + hd.step[1], dz, hd.offset) * x[idx + d.nx];
+        if (k > 0) s += hc - height_of(dx, dy, dz - hd.step[2], hd.offset) * x[idx - pl];
+        if (k < d.nz - 1) s += hc - height_of(dx, dy, dz + hd.step[2], hd.offset) * x[idx + pl];
+    }
+    float out = lr * (w * s);
     if (lt != 0.0f) {
         float t = 0.0f;
         if (f > 0) t += c - x[idx - d.nvox];
@@ -118,13 +151,14 @@ __device__ inline float prior_at(const float *__restrict__ x, const Dims &d, int
     return out;
 }
 
+template <bool kHeight>
 __global__ __launch_bounds__(kThreads) void k_prior(const float *__restrict__ x,
                                                     float *__restrict__ out, Dims d, float lr,
-                                                    float lt, int accumulate)
+                                                    float lt, int accumulate, HeightDev hd)
 {
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
          i += (int64_t)gridDim.x * kThreads) {
-        const float v = prior_at(x, d, i, vox_index(d, i), lr, lt);
+        const float v = prior_at<kHeight>(x, d, i, vox_index(d, i), lr, lt, hd);
         out[i] = accumulate ? out[i] + v : v;
     }
 }
@@ -222,17 +256,18 @@ __global__ __launch_bounds__(kThreads) void k_cg_start(const float *__restrict__
 }
 
 // q = M (q + prior(p)); pq = p.q; alpha = rr / pq.
+template <bool kHeight>
 __global__ __launch_bounds__(kThreads) void k_cg_q(const float *__restrict__ p,
                                                    float *__restrict__ q,
                                                    const uint8_t *__restrict__ map_mask, Dims d,
-                                                   float lr, float lt, Workspace ws)
+                                                   float lr, float lt, Workspace ws, HeightDev hd)
 {
     if (ws.st->done) return;
     double pq = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
          i += (int64_t)gridDim.x * kThreads) {
         const VoxIdx c = vox_index(d, i);
-        float v = q[i] + prior_at(p, d, i, c, lr, lt);
+        float v = q[i] + prior_at<kHeight>(p, d, i, c, lr, lt, hd);
         if (map_mask && !map_mask[c.rem]) v = 0.0f;
         q[i] = v;
         pq += (double)p[i] * v;
@@ -406,17 +441,18 @@ __global__ __launch_bounds__(kThreads) void k_fcg_p(const float *__restrict__ z,
 }
 
 // q = M (q + prior(x)); aux = |b - q|^2 (true residual of x).
+template <bool kHeight>
 __global__ __launch_bounds__(kThreads) void k_true_res(const float *__restrict__ x,
                                                        float *__restrict__ q,
                                                        const float *__restrict__ b,
                                                        const uint8_t *__restrict__ map_mask,
-                                                       Dims d, float lr, float lt, Workspace ws)
+                                                       Dims d, float lr, float lt, Workspace ws, HeightDev hd)
 {
     double rr = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
          i += (int64_t)gridDim.x * kThreads) {
         const VoxIdx c = vox_index(d, i);
-        float v = q[i] + prior_at(x, d, i, c, lr, lt);
+        float v = q[i] + prior_at<kHeight>(x, d, i, c, lr, lt, hd);
         if (map_mask && !map_mask[c.rem]) v = 0.0f;
         q[i] = v;
         const double e = (double)b[i] - v;
@@ -468,6 +504,37 @@ static unsigned elem_blocks(int64_t n)
     return (unsigned)(nb > kRedBlocks ? kRedBlocks : (nb < 1 ? 1 : nb));
 }
 
+// Height parameters of the weighted prior for this cube (h == NULL: none).
+static int height_dev(const tomo_cube &c, const tomo_height *h, HeightDev &hd, const char *who)
+{
+    memset(&hd, 0, sizeof(hd));
+    if (!h) return TOMO_OK;
+    if (!isfinite(h->center[0]) || !isfinite(h->center[1]) || !isfinite(h->center[2]) || !isfinite(h->offset))
+        return set_error(TOMO_EINVAL, "%s: height centre and offset must be finite", who);
+    const int32_t n[3] = {c.nx, c.ny, c.nz};
+    for (int a = 0; a < 3; ++a) {
+        const double step = (c.box_max[a] - c.box_min[a]) / (double)n[a];
+        hd.step[a] = (float)step;
+        hd.c0[a] = (float)(c.box_min[a] + 0.5 * step - h->center[a]);
+    }
+    hd.offset = (float)h->offset;
+    return TOMO_OK;
+}
+
+template <typename... Args>
+static void launch_cg_q(bool hw, unsigned blocks, hipStream_t s, Args... a)
+{
+    if (hw) hipLaunchKernelGGL(k_cg_q<true>, dim3(blocks), dim3(kThreads), 0, s, a...);
+    else hipLaunchKernelGGL(k_cg_q<false>, dim3(blocks), dim3(kThreads), 0, s, a...);
+}
+
+template <typename... Args>
+static void launch_true_res(bool hw, unsigned blocks, hipStream_t s, Args... a)
+{
+    if (hw) hipLaunchKernelGGL(k_true_res<true>, dim3(blocks), dim3(kThreads), 0, s, a...);
+    else hipLaunchKernelGGL(k_true_res<false>, dim3(blocks), dim3(kThreads), 0, s, a...);
+}
+
 // Device allocations of one solve, released on every exit path.
 struct SolveBuffers {
     hipStream_t s = nullptr;
@@ -517,8 +584,8 @@ void tomo_cg_default_params(tomo_cg_params *p)
     p->min_drop = 1e-6;
 }
 
-int tomo_apply_prior(const tomo_cube *cube, double lambda_r, double lambda_t, const float *x_d,
-                     float *out_d, int accumulate, tomo_stream stream)
+int tomo_apply_height_prior(const tomo_cube *cube, const tomo_height *h, double lambda_r, double lambda_t,
+                            const float *x_d, float *out_d, int accumulate, tomo_stream stream)
 {
     int rc = validate_cube(cube);
     if (rc) return rc;
@@ -526,11 +593,24 @@ int tomo_apply_prior(const tomo_cube *cube, double lambda_r, double lambda_t, co
     if (!(lambda_r >= 0) || !(lambda_t >= 0) || !isfinite(lambda_r) || !isfinite(lambda_t))
         return set_error(TOMO_EINVAL, "tomo_apply_prior: weights must be finite and >= 0");
     if (x_d == out_d) return set_error(TOMO_EINVAL, "tomo_apply_prior: x and out must differ");
+    HeightDev hd;
+    rc = height_dev(*cube, h, hd, "tomo_apply_height_prior");
+    if (rc) return rc;
     const Dims d = dims_of(*cube);
-    hipLaunchKernelGGL(k_prior, dim3(elem_blocks(d.total)), dim3(kThreads), 0,
-                       (hipStream_t)stream, x_d, out_d, d, (float)lambda_r, (float)lambda_t,
-                       accumulate);
+    const dim3 grid(elem_blocks(d.total));
+    if (h)
+        hipLaunchKernelGGL(k_prior<true>, grid, dim3(kThreads), 0, (hipStream_t)stream, x_d, out_d, d,
+                           (float)lambda_r, (float)lambda_t, accumulate, hd);
+    else
+        hipLaunchKernelGGL(k_prior<false>, grid, dim3(kThreads), 0, (hipStream_t)stream, x_d, out_d, d,
+                           (float)lambda_r, (float)lambda_t, accumulate, hd);
     return hip_fail(hipGetLastError(), "prior kernel launch");
+}
+
+int tomo_apply_prior(const tomo_cube *cube, double lambda_r, double lambda_t, const float *x_d,
+                     float *out_d, int accumulate, tomo_stream stream)
+{
+    return tomo_apply_height_prior(cube, nullptr, lambda_r, lambda_t, x_d, out_d, accumulate, stream);
 }
 
 int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const tomo_cg_params *prm,
@@ -569,6 +649,10 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     const int64_t n = d.total;
     const float lr = (float)prm->lambda_r, lt = (float)prm->lambda_t;
     const int maxit = prm->max_iter;
+    const bool hw = prm->height != nullptr;
+    HeightDev hd;
+    int hrc = height_dev(g->cube, prm->height, hd, "tomo_cg_solve");
+    if (hrc) return hrc;
 
     SolveBuffers buf;
     buf.s = s;
@@ -651,8 +735,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     if (prm->x0_given) {
         rc = apply_A_to(x_d);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_true_res, dim3(eb), dim3(kThreads), 0, s, x_d, q, b, g->map_mask, d,
-                           lr, lt, ws);
+        launch_true_res(hw, eb, s, x_d, q, b, g->map_mask, d, lr, lt, ws, hd);
     } else {
         rc = launch_fill(x_d, n, 0.0f, s);
         if (rc) return rc;
@@ -711,7 +794,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
             evB.push_back(e2);
         }
         if (e) return e;
-        hipLaunchKernelGGL(k_cg_q, dim3(eb), dim3(kThreads), 0, s, p, q, g->map_mask, d, lr, lt, ws);
+        launch_cg_q(hw, eb, s, p, q, g->map_mask, d, lr, lt, ws, hd);
         if (!fcg) {
             hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
             hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, s, r, p, n, ws.st);
@@ -757,8 +840,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         // true residual of x
         rc = apply_A_to(x_d);
         if (rc) return rc;
-        hipLaunchKernelGGL(k_true_res, dim3(eb), dim3(kThreads), 0, s, x_d, q, b, g->map_mask, d,
-                           lr, lt, ws);
+        launch_true_res(hw, eb, s, x_d, q, b, g->map_mask, d, lr, lt, ws, hd);
         rc = hip_fail(hipMemcpyAsync(hst, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s), "state copy");
         if (!rc) rc = hip_fail(hipStreamSynchronize(s), "cg synchronise");
         if (rc) return rc;
@@ -843,6 +925,8 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
         float *b, *r, *p, *q, *img;
         Workspace ws;
         float lr, lt;
+        bool hw;       // height-weighted spatial prior
+        HeightDev hd;
         const uint8_t *mm, *dm;
         int maxit;
         double rtol;
@@ -863,6 +947,9 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
         c.npix = bt->plans[(size_t)k]->npix;
         c.lr = (float)prm[k].lambda_r;
         c.lt = (float)prm[k].lambda_t;
+        c.hw = prm[k].height != nullptr;
+        int hrc = height_dev(g.cube, prm[k].height, c.hd, "tomo_batch_cg_solve");
+        if (hrc) return hrc;
         c.mm = g.map_mask;
         c.dm = g.data_mask;
         c.maxit = prm[k].max_iter;
@@ -978,8 +1065,7 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
                 c.n_bp--;
                 continue;
             }
-            hipLaunchKernelGGL(k_true_res, dim3(elem_blocks(c.n)), dim3(kThreads), 0, s, x_d[k], c.q, c.b, c.mm,
-                               c.d, c.lr, c.lt, c.ws);
+            launch_true_res(c.hw, elem_blocks(c.n), s, x_d[k], c.q, c.b, c.mm, c.d, c.lr, c.lt, c.ws, c.hd);
         }
     }
     for (int k = 0; k < ns; ++k) {
@@ -1010,7 +1096,7 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
             Sys &c = sy[(size_t)k];
             if (c.skip) continue;
             const unsigned eb = elem_blocks(c.n);
-            hipLaunchKernelGGL(k_cg_q, dim3(eb), dim3(kThreads), 0, st, c.p, c.q, c.mm, c.d, c.lr, c.lt, c.ws);
+            launch_cg_q(c.hw, eb, st, c.p, c.q, c.mm, c.d, c.lr, c.lt, c.ws, c.hd);
             hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, st, x_d[k], c.r, c.p, c.q, c.n, c.ws);
             hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, st, c.r, c.p, c.n, c.ws.st);
         }
@@ -1062,8 +1148,7 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
         for (int k = 0; k < ns; ++k) {
             Sys &c = sy[(size_t)k];
             if (c.skip) continue;
-            hipLaunchKernelGGL(k_true_res, dim3(elem_blocks(c.n)), dim3(kThreads), 0, s, x_d[k], c.q, c.b, c.mm,
-                               c.d, c.lr, c.lt, c.ws);
+            launch_true_res(c.hw, elem_blocks(c.n), s, x_d[k], c.q, c.b, c.mm, c.d, c.lr, c.lt, c.ws, c.hd);
         }
         rc = pull_states();
         if (rc) return rc;

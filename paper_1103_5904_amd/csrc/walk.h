@@ -319,7 +319,7 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
             });
         }
         acc = fma(dl_prev, (double)x_prev, acc);
-        out = (float)(acc * r.dn);
+        out = (float)(acc * (r.dn * v.gain));
     }
     images[pix] = out;
 }

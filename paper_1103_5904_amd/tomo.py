@@ -51,7 +51,11 @@ class TomoObstacle(ctypes.Structure):
 class TomoGeometry(ctypes.Structure):
     _fields_ = [("cube", TomoCube), ("nviews", c_int32), ("reserved", c_int32),
                 ("views", POINTER(TomoView)), ("data_mask", c_void_p), ("map_mask", c_void_p),
-                ("obstacle", POINTER(TomoObstacle))]
+                ("obstacle", POINTER(TomoObstacle)), ("gains", POINTER(c_double))]
+
+
+class TomoHeight(ctypes.Structure):
+    _fields_ = [("center", c_double * 3), ("offset", c_double)]
 
 
 class ThomsonParams(ctypes.Structure):
@@ -72,7 +76,8 @@ class CgParams(ctypes.Structure):
                 ("x0_given", c_int32), ("rtol", c_double), ("check_every", c_int32),
                 ("use_graph", c_int32), ("precond", c_void_p), ("fallback_window", c_int32),
                 ("bp_strategy", c_int32), ("min_drop", c_double), ("record_x", c_void_p),
-                ("record_r", c_void_p), ("record_count", c_int32), ("reserved", c_int32)]
+                ("record_r", c_void_p), ("record_count", c_int32), ("reserved", c_int32),
+                ("height", POINTER(TomoHeight))]
 
 
 class CgReport(ctypes.Structure):
@@ -87,7 +92,7 @@ class CgReport(ctypes.Structure):
 EXPORTS = [
     "tomo_project", "tomo_backproject", "tomo_backproject_ex", "tomo_count_crossings",
     "tomo_thomson_project", "tomo_thomson_backproject",
-    "tomo_trace_ray", "tomo_apply_prior", "tomo_cg_solve", "tomo_cg_default_params",
+    "tomo_trace_ray", "tomo_apply_prior", "tomo_apply_height_prior", "tomo_cg_solve", "tomo_cg_default_params",
     "tomo_view_from_wcs", "tomo_validate_geometry", "tomo_geometry_pixels",
     "tomo_release_cache", "tomo_status_string", "tomo_last_error", "tomo_binning_spills",
     "tomo_get_tuning", "tomo_set_tuning", "tomo_convnet_workspace_bytes", "tomo_convnet_forward",
@@ -122,6 +127,8 @@ def lib():
                                      c_int32, POINTER(c_int32)]
         L.tomo_apply_prior.argtypes = [POINTER(TomoCube), c_double, c_double, c_void_p, c_void_p,
                                        ctypes.c_int, c_void_p]
+        L.tomo_apply_height_prior.argtypes = [POINTER(TomoCube), POINTER(TomoHeight), c_double, c_double,
+                                              c_void_p, c_void_p, ctypes.c_int, c_void_p]
         L.tomo_cg_solve.argtypes = [POINTER(TomoGeometry), c_void_p, c_void_p, POINTER(CgParams),
                                     POINTER(CgReport), c_void_p]
         L.tomo_cg_default_params.argtypes = [POINTER(CgParams)]
@@ -188,8 +195,8 @@ class DeviceGeometry:
     tomo_geometry.  ``geom`` needs the attributes n, lo, hi, views (V x 16:
     obs, w, u, v, cdelt, crpix), npix (V x 2), view_frame (or None), nframes,
     data_mask (or None) and map_mask (or None), and may have obstacle
-    ((cx, cy, cz, R) of an opaque sphere, or None); masks are copied to the
-    device once."""
+    ((cx, cy, cz, R) of an opaque sphere, or None) and gains (one per view,
+    or None); masks are copied to the device once."""
 
     def __init__(self, geom, device="cuda"):
         self.n = tuple(int(k) for k in geom.n)
@@ -221,10 +228,18 @@ class DeviceGeometry:
         if ob is not None:
             ob = np.asarray(ob, dtype=np.float64).reshape(4)
             self._obstacle = TomoObstacle((c_double * 3)(*ob[:3]), float(ob[3]))
+        gn = getattr(geom, "gains", None)
+        self._gains = None
+        if gn is not None:
+            gn = np.asarray(gn, dtype=np.float64).reshape(-1)
+            if gn.size != self.nviews:
+                raise ValueError(f"{gn.size} gains for {self.nviews} views")
+            self._gains = (c_double * self.nviews)(*gn)
         self.g = TomoGeometry(cube, self.nviews, 0, arr,
                               None if self.data_mask is None else self.data_mask.data_ptr(),
                               None if self.map_mask is None else self.map_mask.data_ptr(),
-                              None if self._obstacle is None else ctypes.pointer(self._obstacle))
+                              None if self._obstacle is None else ctypes.pointer(self._obstacle),
+                              None if self._gains is None else self._gains)
 
     @staticmethod
     def _mask(m, numel, device):
@@ -326,11 +341,25 @@ def _ptrs(tensors, numels, name):
     return arr
 
 
-def _cg_params(lam_r, lam_t, max_iter, rtol, check_every, use_graph, x0_given):
+def _height(height):
+    """tomo_height from (cx, cy, cz, offset), or None."""
+    if height is None:
+        return None
+    h = np.asarray(height, dtype=np.float64).reshape(4)
+    return TomoHeight((c_double * 3)(*h[:3]), float(h[3]))
+
+
+def _cg_params(lam_r, lam_t, max_iter, rtol, check_every, use_graph, x0_given, height=None, keep=None):
+    """CgParams; a height struct is appended to ``keep`` (the caller holds it
+    until the call returns)."""
     p = CgParams()
     lib().tomo_cg_default_params(ctypes.byref(p))
     p.lambda_r, p.lambda_t, p.max_iter, p.rtol = lam_r, lam_t, int(max_iter), rtol
     p.check_every, p.use_graph, p.x0_given = int(check_every), int(bool(use_graph)), int(bool(x0_given))
+    h = _height(height)
+    if h is not None:
+        keep.append(h)
+        p.height = ctypes.pointer(h)
     return p
 
 
@@ -387,18 +416,22 @@ class Batch:
         return outs
 
     def cg_solve(self, ys, x0s=None, *, lam_r=1e-2, lam_t=0.0, max_iter=50, rtol=0.0, check_every=10,
-                 use_graph=False, outs=None):
+                 use_graph=False, outs=None, heights=None):
         """CG on every system at once; lam_r, lam_t, max_iter, rtol may be
-        per-system lists.  Returns (xs, reports)."""
+        per-system lists, heights a per-system list of (cx, cy, cz, offset)
+        or None (height-weighted spatial prior).  Returns (xs, reports)."""
         n = len(self.geoms)
         per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * n  # noqa: E731
         lr, lt, mi, rt = per(lam_r), per(lam_t), per(max_iter), per(rtol)
+        hs = [None] * n if heights is None else list(heights)
+        keep = []
         if outs is None:
             outs = [torch.empty(g.cube_shape, dtype=torch.float32, device=y.device) for g, y in zip(self.geoms, ys)]
         if x0s is not None:
             for o, x0 in zip(outs, x0s):
                 o.copy_(x0.reshape(o.shape))
-        params = (CgParams * n)(*[_cg_params(lr[k], lt[k], mi[k], rt[k], check_every, use_graph, x0s is not None)
+        params = (CgParams * n)(*[_cg_params(lr[k], lt[k], mi[k], rt[k], check_every, use_graph, x0s is not None,
+                                             hs[k], keep)
                                   for k in range(n)])
         hists = [(c_double * (int(mi[k]) + 1))() for k in range(n)]
         reps = (CgReport * n)()
@@ -476,13 +509,20 @@ def thomson_backproject(geom: DeviceGeometry, images: torch.Tensor, u: float = 0
 
 
 def apply_prior(geom: DeviceGeometry, x: torch.Tensor, lam_r: float, lam_t: float = 0.0,
-                out: torch.Tensor | None = None, accumulate: bool = False):
-    """out (+)= lam_r D^T D x + lam_t D_t^T D_t x."""
+                out: torch.Tensor | None = None, accumulate: bool = False, height=None):
+    """out (+)= lam_r D^T D x + lam_t D_t^T D_t x, or with height = (cx, cy,
+    cz, offset) lam_r R D^T D R x + lam_t D_t^T D_t x (R the voxel heights)."""
     if out is None:
         out = torch.empty_like(x)
     n = geom.nvox * geom.nframes
-    _check(lib().tomo_apply_prior(ctypes.byref(geom.g.cube), lam_r, lam_t, _dev_f32(x, n, "x"),
-                                  _dev_f32(out, n, "out"), int(bool(accumulate)), _stream()))
+    if height is None:
+        _check(lib().tomo_apply_prior(ctypes.byref(geom.g.cube), lam_r, lam_t, _dev_f32(x, n, "x"),
+                                      _dev_f32(out, n, "out"), int(bool(accumulate)), _stream()))
+    else:
+        h = _height(height)
+        _check(lib().tomo_apply_height_prior(ctypes.byref(geom.g.cube), ctypes.byref(h), lam_r, lam_t,
+                                             _dev_f32(x, n, "x"), _dev_f32(out, n, "out"),
+                                             int(bool(accumulate)), _stream()))
     return out
 
 
@@ -491,11 +531,15 @@ def cg_solve(geom: DeviceGeometry, y: torch.Tensor, x0: torch.Tensor | None = No
              check_every: int = 10, use_graph: bool = False, precond: torch.Tensor | None = None,
              fallback_window: int = 3, min_drop: float = 1e-6, bp_strategy: int = BP_AUTO,
              time_kernels: bool = False, out: torch.Tensor | None = None,
-             record_x: torch.Tensor | None = None, record_r: torch.Tensor | None = None):
-    """Solve M (P^T P + lam_r D^T D + lam_t D_t^T D_t) M x = M P^T y.
-    Returns (x, report dict)."""
+             record_x: torch.Tensor | None = None, record_r: torch.Tensor | None = None, height=None):
+    """Solve M (P^T G^2 P + lam_r R D^T D R + lam_t D_t^T D_t) M x = M P^T G y
+    (G the geometry's gains; R the voxel heights for height = (cx, cy, cz,
+    offset), else the identity).  Returns (x, report dict)."""
     p = CgParams()
     lib().tomo_cg_default_params(ctypes.byref(p))
+    h = _height(height)
+    if h is not None:
+        p.height = ctypes.pointer(h)
     p.lambda_r, p.lambda_t, p.max_iter, p.rtol = lam_r, lam_t, int(max_iter), rtol
     p.check_every, p.use_graph = int(check_every), int(bool(use_graph))
     p.fallback_window, p.min_drop, p.bp_strategy = int(fallback_window), min_drop, int(bp_strategy)

@@ -1,4 +1,6 @@
 """Helpers shared by the GPU parity tests (not collected as tests)."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -98,13 +100,17 @@ CODES = {"blocked": 3, "binned": 2, "atomic": 1}
 
 def parity_full(tomo, ora, g, x, y, strategies=STRATEGIES):
     """Every pixel of P and every voxel of P^T (each back-projection
-    strategy) against the oracle."""
+    strategy) against the oracle.  With gains the bounds scale with |gain|
+    (the operators on |x| and |y| taken with |gains|)."""
     dg = tomo.DeviceGeometry(g)
-    res = length_resolution(g)
+    gains = getattr(g, "gains", None)
+    gmax = 1.0 if gains is None else float(np.abs(gains).max())
+    ga = g if gains is None else dataclasses.replace(g, gains=np.abs(np.asarray(gains, dtype=np.float64)))
+    res = length_resolution(g) * gmax
     img = to_host(tomo.project(dg, to_dev(x)))
     xm = x if g.map_mask is None else x * (g.map_mask if g.nframes == 1 else g.map_mask[None])
-    assert_p_close(img, ora.project(g, x), ora.project(g, np.abs(xm)), atol=res * np.abs(x).max())
-    ref, refa = ora.backproject(g, y), ora.backproject(g, np.abs(y))
+    assert_p_close(img, ora.project(g, x), ora.project(ga, np.abs(xm)), atol=res * np.abs(x).max())
+    ref, refa = ora.backproject(g, y), ora.backproject(ga, np.abs(y))
     for strat in strategies:
         code = CODES[strat]
         bp = to_host(tomo.backproject(dg, to_dev(y), strategy=code))

@@ -158,3 +158,34 @@ def test_thomson_parameters_rejected(tomo, case):
                                          None)
     assert rc == tomo.tomo.TOMO_EINVAL
     assert tomo.lib().tomo_last_error()
+
+
+@pytest.mark.parametrize("bad", [float("nan"), float("inf")])
+def test_non_finite_gain_rejected(tomo, bad):
+    g = _geom()
+    gains = np.ones(g.nviews)
+    gains[3] = bad
+    dg = tomo.DeviceGeometry(ts.Geometry(g.n, g.lo, g.hi, g.views, g.npix, gains=gains), device="cpu")
+    assert tomo.validate(dg) == tomo.tomo.TOMO_EINVAL
+    assert b"gain" in tomo.lib().tomo_last_error()
+
+
+def test_gains_accepted_and_checked_for_length(tomo):
+    g = _geom()
+    gains = np.linspace(0.5, 2.0, g.nviews)
+    dg = tomo.DeviceGeometry(ts.Geometry(g.n, g.lo, g.hi, g.views, g.npix, gains=gains), device="cpu")
+    assert tomo.validate(dg) == 0
+    with pytest.raises(ValueError):
+        tomo.DeviceGeometry(ts.Geometry(g.n, g.lo, g.hi, g.views, g.npix, gains=gains[:-1]), device="cpu")
+
+
+@pytest.mark.parametrize("height", [(np.nan, 0.0, 0.0, 0.0), (0.0, 0.0, 0.0, np.inf)])
+def test_height_parameters_rejected(tomo, height):
+    """A non-finite height centre or offset returns TOMO_EINVAL before any
+    device work."""
+    dg = tomo.DeviceGeometry(_geom(), device="cpu")
+    h = tomo.tomo._height(height)
+    rc = tomo.lib().tomo_apply_height_prior(ctypes.byref(dg.g.cube), ctypes.byref(h), 1.0, 0.0,
+                                            ctypes.c_void_p(16), ctypes.c_void_p(32), 0, None)
+    assert rc == tomo.tomo.TOMO_EINVAL
+    assert b"height" in tomo.lib().tomo_last_error()
