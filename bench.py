@@ -17,8 +17,10 @@ CG on held-out problems of its own family (time_to_rel_res_1e-3), and the
 COR1-like batch (five systems of uneven size in persistent launches with
 autotuned shapes) is timed against solving its systems one after another
 (batched), the obstacle variant (lines of sight ending at the photosphere)
-is measured on the headline workload (obstacle), and the Thomson-scattering
-operators pB and B on a COR1-like frame (thomson).
+is measured on the headline workload (obstacle), the Thomson-scattering
+operators pB and B on a COR1-like frame (thomson), and the headline
+workload as two instruments with gains and the height-weighted prior
+(height_gain).
 """
 from __future__ import annotations
 
@@ -83,6 +85,8 @@ def parse():
                     help="skip the obstacle-variant measurement")
     ap.add_argument("--no-thomson", action="store_true",
                     help="skip the Thomson-scattering operator measurement")
+    ap.add_argument("--no-height-gain", action="store_true",
+                    help="skip the two-instrument, height-weighted-prior measurement")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the timed steps, run 3 device-to-device copies of MIB MiB: the "
                          "known-size kernel that calibrates hardware byte counters")
@@ -263,6 +267,63 @@ def thomson_cor1(tomo, ts, reps=5):
     return res
 
 
+def height_gain_euvi(tomo, ts, wl, y, reps=10):
+    """The multi-spacecraft inversion with the height-weighted prior on the
+    EUVI-like workload: observer A's 14 views and observer B's 14 views as
+    two instruments with gains 1 and 1.27 (B's data scaled to match), prior
+    lambda R D^T D R with R the distance from the Sun's centre.  P and P^T
+    with gains and the weighted prior per launch (HIP events on the launch
+    stream, median of `reps`) next to the plain ones, and one 50-iteration
+    CG step."""
+    import torch
+
+    g0 = wl.geom
+    gains = np.where(np.arange(g0.nviews) % 2 == 1, 1.27, 1.0)
+    g = ts.Geometry(g0.n, g0.lo, g0.hi, g0.views, g0.npix, map_mask=g0.map_mask, gains=gains)
+    dg, d0 = tomo.DeviceGeometry(g), tomo.DeviceGeometry(g0)
+    cross = tomo.count_crossings(dg)
+    ray_gain = torch.as_tensor(np.repeat(gains, g0.npix[:, 0] * g0.npix[:, 1]).astype(np.float32)).cuda()
+    y_ab = y * ray_gain
+    height = (0.0, 0.0, 0.0, 0.0)
+    x = torch.as_tensor(wl.x.astype(np.float32)).cuda()
+    out = torch.empty_like(x)
+    img = torch.empty_like(y)
+
+    def per_launch(f):
+        f()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            f()
+            e1.record()
+            e1.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return float(np.median(t))
+
+    ms = {"project_gains": per_launch(lambda: tomo.project(dg, x, out=img)),
+          "project_plain": per_launch(lambda: tomo.project(d0, x, out=img)),
+          "backproject_gains": per_launch(lambda: tomo.backproject(dg, y_ab, out=out)),
+          "backproject_plain": per_launch(lambda: tomo.backproject(d0, y, out=out)),
+          "prior_height": per_launch(lambda: tomo.apply_prior(dg, x, wl.lam_r, out=out, height=height)),
+          "prior_plain": per_launch(lambda: tomo.apply_prior(dg, x, wl.lam_r, out=out))}
+    vox = int(np.prod(g0.n))
+    tomo.cg_solve(dg, y_ab, lam_r=wl.lam_r, max_iter=wl.cg_iters, out=out, height=height)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, rep = tomo.cg_solve(dg, y_ab, lam_r=wl.lam_r, max_iter=wl.cg_iters, out=out, height=height)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    apps = rep["n_project"] + rep["n_backproject"]
+    return {"workload": "EUVI-like (as the headline) as two instruments, observer B at gain 1.27, "
+                        "height-weighted prior (R = distance from the Sun's centre), lambda 1e-2",
+            "crossings_per_application": cross,
+            "kernel_ms": ms,
+            "prior_height_gbs": 8.0 * vox / (ms["prior_height"] * 1e-3) / 1e9,
+            "ms_per_step": 1e3 * dt, "crossings_per_s": apps * cross / dt, "final_rel_res": rep["rel_res"]}
+
+
 def cpu_baseline(wl, reps):
     """The FP64 oracle (as it stands) on a bounded sample: `reps` passes of
     P and P^T over the full geometry (the CG's operator pair), all host
@@ -386,6 +447,9 @@ def main():
     if not args.no_thomson:
         out["thomson"] = thomson_cor1(tomo, ts)
         log("Thomson operators done")
+    if not args.no_height_gain:
+        out["height_gain"] = height_gain_euvi(tomo, ts, wl, y)
+        log("two instruments with the height-weighted prior done")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_reps)
         log("cpu baseline done")

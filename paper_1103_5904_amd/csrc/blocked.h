@@ -8,9 +8,10 @@ namespace tomo {
 
 constexpr int kYmaxParts = 64;  // partial maxima per view (64 workgroups per view keep the pass short)
 
-// max |y| over the share `part` of view v's unmasked pixels, as an FP32 bit
-// pattern (bit patterns of magnitudes order like the magnitudes; anything
-// >= 0x7f800000 is non-finite).  Valid in thread 0.
+// max |gain y| over the share `part` of view v's unmasked pixels, as an
+// FP32 bit pattern (bit patterns of magnitudes order like the magnitudes;
+// anything >= 0x7f800000 is non-finite).  The product is rounded to FP32,
+// which the scale's margin of 1e-7 covers.  Valid in thread 0.
 template <bool kDataMask>
 __device__ inline uint32_t view_absmax_part(const ViewDev &v, int part, const float *__restrict__ images,
                                             const uint8_t *__restrict__ data_mask, uint32_t *red /* LDS [4] */)
@@ -32,6 +33,8 @@ __device__ inline uint32_t view_absmax_part(const ViewDev &v, int part, const fl
     if (threadIdx.x == 0) {
         r = red[0];
         for (int k = 1; k < kThreads / 64; ++k) r = red[k] > r ? red[k] : r;
+        if (r < 0x7f800000u)  // a product that overflows FP32 reads as non-finite
+            r = __builtin_bit_cast(uint32_t, (float)((double)__builtin_bit_cast(float, r) * fabs(v.gain)));
     }
     __syncthreads();
     return r;
@@ -93,22 +96,18 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
 
     // ---- fixed-point scale from the views this owner handles (uniform):
     // the largest |gain y| among them
-    bool finite = true;
-    double ymax = 0.0;
+    uint32_t ybits = 0u;
     double rays = 0.0;
     for (int k = v0 + split; k < v1; k += bd.splits) {
         const int vi = frame_views[k];
-        uint32_t ybits = 0u;
         for (int p = 0; p < kYmaxParts; ++p) {
             const uint32_t b = ymax_parts[vi * kYmaxParts + p];
             ybits = b > ybits ? b : ybits;
         }
-        if (ybits < 0x7f800000u)
-            ymax = fmax(ymax, (double)__builtin_bit_cast(float, ybits) * fabs(views[vi].gain));
-        else
-            finite = false;
         rays += (double)views[vi].ncol * (double)views[vi].nrow;
     }
+    const bool finite = ybits < 0x7f800000u;
+    const double ymax = (double)__builtin_bit_cast(float, ybits);
     const double vdiag = sqrt(g.delta[0] * g.delta[0] + g.delta[1] * g.delta[1] + g.delta[2] * g.delta[2]);
     // scale 2^(61 - eb): every bin below 2^61 (at most `rays` contributions
     // of at most vdiag max|y| each) and every single contribution below 2^50,
@@ -185,6 +184,8 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
             const ViewDev &v = views[frame_views[v0 + split + (cs + j) * bd.splits]];
             const int c0 = sh.rect[j][0], c1 = sh.rect[j][1], r0 = sh.rect[j][2], r1 = sh.rect[j][3];
             if (c0 > c1 || r0 > r1) continue;  // uniform
+            // the view's gain times the bin scale (a power of two: exact)
+            const double vscale = v.gain * (finite ? fx_scale : 1.0);
 
             // ---- rays of the rectangle, a 16x16 tile per pass; each pass loads
             // the next pass's pixel value so that its latency is hidden by the walk
@@ -274,7 +275,7 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                     ++spills;
                     continue;
                 }
-                const double wys = (double)yv * (r.dn * v.gain) * (finite ? fx_scale : 1.0);
+                const double wys = (double)yv * r.dn * vscale;
                 // four steps per loop body, as in ray_walk; the clamp to the
                 // dummy bin nbins only guards the LDS range
                 auto walk = [&](auto deposit) {
