@@ -18,9 +18,9 @@ COR1-like batch (five systems of uneven size in persistent launches with
 autotuned shapes) is timed against solving its systems one after another
 (batched), the obstacle variant (lines of sight ending at the photosphere)
 is measured on the headline workload (obstacle), the Thomson-scattering
-operators pB and B on a COR1-like frame (thomson), and the headline
-workload as two instruments with gains and the height-weighted prior
-(height_gain).
+operators pB and B on a COR1-like frame (thomson), the headline workload
+as two instruments with gains and the height-weighted prior (height_gain),
+and the paper's image-size and cube-size projector sweeps (sweep).
 """
 from __future__ import annotations
 
@@ -87,6 +87,11 @@ def parse():
                     help="skip the Thomson-scattering operator measurement")
     ap.add_argument("--no-height-gain", action="store_true",
                     help="skip the two-instrument, height-weighted-prior measurement")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the paper's image-size and cube-size projector sweeps")
+    ap.add_argument("--sweep-only", type=int, nargs=2, metavar=("CUBE", "IMAGE"), default=None,
+                    help="run only the sweep point with this cube side and image side, and print "
+                         "its line (for profiling it alone)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the timed steps, run 3 device-to-device copies of MIB MiB: the "
                          "known-size kernel that calibrates hardware byte counters")
@@ -324,6 +329,71 @@ def height_gain_euvi(tomo, ts, wl, y, reps=10):
             "ms_per_step": 1e3 * dt, "crossings_per_s": apps * cross / dt, "final_rel_res": rep["rel_res"]}
 
 
+# The paper's projector timings (Sec. "Performance", image-size and cube-size
+# tables; 64 images, no mask, no obstacle; two quad-core Opteron 2380), in
+# seconds per projection and back-projection, for context only.
+PAPER_IMAGE_S = {128: (0.95, 1.61), 256: (3.64, 6.17), 512: (14.53, 24.69), 1024: (58.75, 99.54)}
+PAPER_CUBE_S = {128: (13.84, 24.71), 256: (44.56, 56.64), 512: (195.69, 214.55), 1024: (587.56, 610.75)}
+
+
+def sweeps(tomo, ts, reps=5, only=None):
+    """The paper's projector scaling sweeps on the GPU: 64 views, no mask,
+    no obstacle; image sides 128..1024 on a 128^3 cube, then cube sides
+    128..1024 (up to 2^30 voxels, 4 GiB) under 256^2 images.  Per point:
+    crossings, P and blocked P^T per launch (HIP events on the launch
+    stream, median of `reps`), crossings/s, algorithmic GB/s (4 B per
+    crossing + 4 B per ray for P, 8 B + 4 B for P^T) and the paper's
+    seconds.  only = (cube side, image side) runs that single point."""
+    import torch
+
+    def per_launch(f):
+        f()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            f()
+            e1.record()
+            e1.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return float(np.median(t))
+
+    def point(n, npix, paper):
+        g = ts.sweep_geometry(n, npix)
+        dg = tomo.DeviceGeometry(g)
+        x = torch.as_tensor(ts.sweep_cube(ts.sweep_cube_parts(n))).cuda()
+        y = tomo.project(dg, x)
+        out = torch.empty_like(x)
+        cross = tomo.count_crossings(dg)
+        ms_p = per_launch(lambda: tomo.project(dg, x, out=y))
+        ms_b = per_launch(lambda: tomo.backproject(dg, y, out=out, strategy=tomo.BP_BLOCKED))
+        rays = g.nrays
+        res = {"cube": n, "image": npix, "rays": rays, "crossings": cross,
+               "project_ms": ms_p, "backproject_ms": ms_b,
+               "project_crossings_per_s": cross / (ms_p * 1e-3),
+               "backproject_crossings_per_s": cross / (ms_b * 1e-3),
+               "project_gbs": (4.0 * cross + 4.0 * rays) / (ms_p * 1e-3) / 1e9,
+               "backproject_gbs": (8.0 * cross + 4.0 * rays) / (ms_b * 1e-3) / 1e9,
+               "paper_project_s": paper[0], "paper_backproject_s": paper[1]}
+        del x, y, out, dg
+        torch.cuda.empty_cache()
+        return res
+
+    if only is not None:
+        n, npix = only
+        paper = PAPER_CUBE_S.get(n) if npix == 256 else PAPER_IMAGE_S.get(npix) if n == 128 else None
+        image, cube = [], [point(n, npix, paper or (None, None))]
+    else:
+        image = [point(128, s, PAPER_IMAGE_S[s]) for s in ts.SWEEP_IMAGE_SIDES]
+        log("image-size sweep done")
+        cube = [point(s, 256, PAPER_CUBE_S[s]) for s in ts.SWEEP_CUBE_SIDES]
+        log("cube-size sweep done")
+    return {"workload": "the paper's projector benchmark: 64 views at 215 R_sun around the equator, FOV 3.2, "
+                        "cube on [-1.5,1.5]^3, no mask, no obstacle; paper times for context (other hardware)",
+            "image_size": image, "cube_size": cube}
+
+
 def cpu_baseline(wl, reps):
     """The FP64 oracle (as it stands) on a bounded sample: `reps` passes of
     P and P^T over the full geometry (the CG's operator pair), all host
@@ -356,6 +426,16 @@ def main():
     import tomo_synth as ts
 
     torch.cuda.set_device(0)
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.sweep_only is not None:
+        print(json.dumps({"sweep": sweeps(tomo, ts, only=tuple(args.sweep_only))}), flush=True)
+        return
     wl = ts.euvi()
     g = wl.geom
     dg = tomo.DeviceGeometry(g)
@@ -374,13 +454,6 @@ def main():
         return tomo.cg_solve(dg, y, lam_r=wl.lam_r, max_iter=wl.cg_iters, time_kernels=True, out=x,
                              bp_strategy=bp)
 
-    if args.copy_probe > 0:
-        src = torch.ones(args.copy_probe << 18, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -450,6 +523,8 @@ def main():
     if not args.no_height_gain:
         out["height_gain"] = height_gain_euvi(tomo, ts, wl, y)
         log("two instruments with the height-weighted prior done")
+    if not args.no_sweep:
+        out["sweep"] = sweeps(tomo, ts)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_reps)
         log("cpu baseline done")

@@ -70,7 +70,7 @@ typedef enum tomo_status {
 } tomo_status;
 
 typedef struct tomo_cube {
-    int32_t nx, ny, nz; /* voxels per axis, each in [1, 2^24], product < 2^30 */
+    int32_t nx, ny, nz; /* voxels per axis, each in [1, 2^24], product <= 2^30 */
     int32_t nframes;    /* time frames held by a cube argument (>= 1)           */
     double box_min[3];  /* box lower corner (box units, e.g. R_sun)             */
     double box_max[3];  /* box upper corner, > box_min on every axis            */

@@ -61,7 +61,7 @@ int validate_cube(const tomo_cube *c)
     if (c->nx > (1 << 24) || c->ny > (1 << 24) || c->nz > (1 << 24))
         return set_error(TOMO_EINVAL, "cube side exceeds 2^24 voxels (got %d x %d x %d)", c->nx, c->ny, c->nz);
     const int64_t nvox = (int64_t)c->nx * c->ny * c->nz;
-    if (nvox >= (int64_t)1 << 30)
+    if (nvox > (int64_t)1 << 30)
         return set_error(TOMO_EINVAL, "cube of %lld voxels exceeds the 2^30 limit", (long long)nvox);
     for (int a = 0; a < 3; ++a)
         if (!isfinite(c->box_min[a]) || !isfinite(c->box_max[a]) || !(c->box_max[a] > c->box_min[a]))

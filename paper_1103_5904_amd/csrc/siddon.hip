@@ -240,6 +240,10 @@ int launch_backproject_tuned(const Plan &p, const tomo_geometry *g, const float 
         (void)hipFreeAsync(tmp, s);
         return rc;
     }
+    // the atomic kernels address a frame through a buffer resource, whose
+    // byte range is 32-bit
+    if (p.grid.nvox >= ((int64_t)1 << 30))
+        return set_error(TOMO_EUNSUPPORTED, "binned and atomic back-projection need frames below 2^30 voxels");
     if (!accumulate) {
         int rc = launch_fill(cube, p.grid.nvox * p.grid.nframes, 0.0f, s);
         if (rc) return rc;

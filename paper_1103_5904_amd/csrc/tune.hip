@@ -113,13 +113,13 @@ int tomo_autotune(const tomo_geometry *g, int32_t reps, tomo_tuning *out, tomo_s
                 t.bp_bundle = bun;
                 bc.push_back(t);
             }
-    for (int bun : {2, 3, 4}) {
-        tomo_tuning t = base;
-        t.bp_default = TOMO_BP_BINNED;
-        t.bp_bundle = bun;
-        bc.push_back(t);
-    }
-    {
+    if (p.grid.nvox < ((int64_t)1 << 30)) {  // the atomic strategies' frame limit
+        for (int bun : {2, 3, 4}) {
+            tomo_tuning t = base;
+            t.bp_default = TOMO_BP_BINNED;
+            t.bp_bundle = bun;
+            bc.push_back(t);
+        }
         tomo_tuning t = base;
         t.bp_default = TOMO_BP_ATOMIC;
         bc.push_back(t);

@@ -286,7 +286,13 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
     float out = 0.0f;
     RayState r;
     if ((!kDataMask || data_mask[pix]) && ray_setup<kObstacle>(g, v, lp.col, lp.row, r)) {
-        const auto rc = make_rsrc(cube + (int64_t)v.frame * g.nvox, (uint32_t)(g.nvox * 4));
+        const float *__restrict__ base = cube + (int64_t)v.frame * g.nvox;
+        // a buffer resource spans below 2^32 bytes: a frame of 2^30 voxels
+        // takes plain global loads, their offsets clamped into the frame as
+        // the buffer's range check would
+        const bool wide = g.nvox >= ((int64_t)1 << 30);
+        const uint32_t last = (uint32_t)(g.nvox - 1);
+        const auto rc = make_rsrc(base, wide ? 0u : (uint32_t)(g.nvox * 4));
         // software-pipelined by one segment: a step issues its voxel's gather
         // and adds the previous segment, so each load has a whole step to land
         double acc = 0.0, dl_prev = 0.0;
@@ -294,13 +300,25 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
         if constexpr (kMapMask) {
             const auto rm = make_rsrc(map_mask, (uint32_t)g.nvox);
             uint32_t m_prev = 0u;
+            auto walk_masked = [&](auto load) {
+                ray_walk(r, maxit, [&](int32_t off, double dl) {
+                    acc = fma(dl_prev, m_prev ? (double)x_prev : 0.0, acc);
+                    x_prev = load((uint32_t)off);
+                    m_prev = buf_load_u8(rm, (uint32_t)off);
+                    dl_prev = dl;
+                });
+            };
+            if (wide)
+                walk_masked([&](uint32_t o) { return base[min(o, last)]; });
+            else
+                walk_masked([&](uint32_t o) { return buf_load_f32(rc, o * 4u); });
+            if (!m_prev) x_prev = 0.0f;
+        } else if (wide) {
             ray_walk(r, maxit, [&](int32_t off, double dl) {
-                acc = fma(dl_prev, m_prev ? (double)x_prev : 0.0, acc);
-                x_prev = buf_load_f32(rc, (uint32_t)off * 4u);
-                m_prev = buf_load_u8(rm, (uint32_t)off);
+                acc = fma(dl_prev, (double)x_prev, acc);
+                x_prev = base[min((uint32_t)off, last)];
                 dl_prev = dl;
             });
-            if (!m_prev) x_prev = 0.0f;
         } else if (g.nvox < ((int64_t)1 << 29)) {
             // offsets in bytes from here on (below 2^31, so int32 holds them)
             r.off *= 4;

@@ -63,6 +63,11 @@ def test_validation_accepts_the_tiny_geometry(tomo):
     assert tomo.lib().tomo_geometry_pixels(dg.ref) == 8 * 32 * 32
 
 
+def test_validation_accepts_a_cube_of_2_30_voxels(tomo):
+    dg = tomo.DeviceGeometry(_geom(n=(1024, 1024, 1024)), device="cpu")
+    assert tomo.validate(dg) == 0
+
+
 @pytest.mark.parametrize("case", ["zero_dim", "inverted_box", "non_unit_w", "non_orthogonal",
                                   "zero_cdelt", "empty_image", "bad_frame", "nan_obs", "huge_cube",
                                   "long_side"])
@@ -86,8 +91,8 @@ def test_validation_rejects(tomo, case):
         kw["view_frame"] = np.full(g.nviews, 1, dtype=np.int32)
     elif case == "nan_obs":
         views[0, 0] = np.nan
-    elif case == "huge_cube":
-        kw["n"] = (1024, 1024, 1024)
+    elif case == "huge_cube":  # one voxel plane above 2^30
+        kw["n"] = (1024, 1024, 1025)
     elif case == "long_side":  # under 2^30 voxels, but a side above 2^24
         kw["n"] = (1, (1 << 24) + 1, 1)
     dg = tomo.DeviceGeometry(_geom(views=views, npix=npix, **kw), device="cpu")

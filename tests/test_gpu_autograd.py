@@ -113,3 +113,28 @@ def test_backward_of_a_composite(setup):
     ref = tomo.backproject(dg, w)
     torch.cuda.synchronize()
     assert torch.allclose(x.grad, ref, rtol=1e-5, atol=1e-6 * float(ref.abs().max()))
+
+
+def test_height_prior_and_gains(setup, ora):
+    """The loss with two instruments (gains 0.7 and 1.6) and the
+    height-weighted prior on the tiny problem: value against the oracle's
+    criterion terms and gradient against its normal equations,
+    grad = P^T G (G P x - y) + 2 lambda R D^T D R x."""
+    tomo, ag, _, _ = setup
+    wl = ts.tiny()
+    g = wl.geom.subset(np.arange(wl.geom.nviews))
+    g.gains = np.where(np.arange(g.nviews) < 4, 0.7, 1.6)
+    h = (0.0, 0.0, 0.0, 0.0)
+    dg = tomo.DeviceGeometry(g)
+    xf = (wl.x * 1.1).astype(np.float32).astype(np.float64)
+    y = ora.project(g, wl.x).astype(np.float32).astype(np.float64)
+    x = to_dev(xf).requires_grad_(True)
+    loss = ag.data_loss(x, dg, to_dev(y), wl.lam_r, height=h)
+    loss.backward()
+    got = to_host(x.grad)
+    ref = ora.normal_operator(g, 2.0 * wl.lam_r, height=h)(xf) - ora.rhs(g, y)
+    assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref)
+    r = ora.project(g, xf) - y
+    hv = ora.voxel_heights(g, h)
+    ref_loss = 0.5 * float(r @ r) + wl.lam_r * sum(float(np.sum(np.diff(hv * xf, axis=a) ** 2)) for a in range(3))
+    assert abs(float(loss) - ref_loss) <= 1e-5 * ref_loss

@@ -311,3 +311,49 @@ def cor1_extras() -> list:
         x = blob_cube(nn, lo, hi, draw_blobs(np.random.default_rng(300 + i), 16))
         out.append(Workload(f"extra-{n}^3", Geometry(nn, lo, hi, views, pix), x, 1e-2))
     return out
+
+
+# ------------------------------------------ the paper's projector scaling sweeps
+
+
+SWEEP_IMAGE_SIDES = (128, 256, 512, 1024)  # 64 views, 128^3 cube (Sec. "Performance", image-size table)
+SWEEP_CUBE_SIDES = (128, 256, 512, 1024)  # 64 views of 256^2 (Sec. "Performance", cube-size table)
+
+
+def sweep_geometry(n: int = 128, npix: int = 256, nviews: int = 64) -> Geometry:
+    """The projector benchmark set-up of the paper's Performance section: an
+    n^3 cube (here on [-1.5, 1.5]^3 R_sun) and `nviews` images of npix^2,
+    no mask and no obstacle.  The paper gives no pointing; the views here sit
+    at 215 R_sun, equally spaced in longitude around the equator starting half
+    a step from longitude 0 (no observer on an axis or a diagonal of the grid,
+    whose rays would run exactly along voxel edges), FOV 3.2."""
+    nn, lo, hi = box(n, 1.5)
+    step = 360.0 / nviews
+    views, pix = make_views(0.5 * step + step * np.arange(nviews), (npix, npix), 3.2)
+    return Geometry(nn, lo, hi, views, pix)
+
+
+def sweep_cube_parts(n: int, seed: int = 11) -> tuple:
+    """Three seeded float32 vectors (a over x, b over y, c over z) of the
+    separable sweep phantom x[k, j, i] = (c[k] + b[j]) + a[i], values in
+    [0.5, 1.5]: cheap to hold at 1024^3 and to evaluate at single voxels."""
+    rng = np.random.default_rng(seed)
+    a, b, c = (rng.uniform(1.0 / 6.0, 0.5, size=n).astype(np.float32) for _ in range(3))
+    return a, b, c
+
+
+def sweep_cube(parts) -> np.ndarray:
+    """The whole sweep phantom, float32 (nz, ny, nx), summed in float32 as
+    (c + b) + a."""
+    a, b, c = parts
+    return (c[:, None, None] + b[None, :, None]) + a[None, None, :]
+
+
+def sweep_values(parts, flat_idx) -> np.ndarray:
+    """The sweep phantom at flat voxel indices (k n + j) n + i, float32
+    arithmetic in the same order as sweep_cube."""
+    a, b, c = parts
+    n = a.size
+    idx = np.asarray(flat_idx, dtype=np.int64)
+    i, j, k = idx % n, (idx // n) % n, idx // (n * n)
+    return (c[k] + b[j]) + a[i]
