@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--sweep-only", type=int, nargs=2, metavar=("CUBE", "IMAGE"), default=None,
                     help="run only the sweep point with this cube side and image side, and print "
                          "its line (for profiling it alone)")
+    ap.add_argument("--sweep-no-autotune", action="store_true",
+                    help="time the sweep with the default launch shapes only")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the timed steps, run 3 device-to-device copies of MIB MiB: the "
                          "known-size kernel that calibrates hardware byte counters")
@@ -336,14 +338,16 @@ PAPER_IMAGE_S = {128: (0.95, 1.61), 256: (3.64, 6.17), 512: (14.53, 24.69), 1024
 PAPER_CUBE_S = {128: (13.84, 24.71), 256: (44.56, 56.64), 512: (195.69, 214.55), 1024: (587.56, 610.75)}
 
 
-def sweeps(tomo, ts, reps=5, only=None):
+def sweeps(tomo, ts, reps=5, only=None, tune=True):
     """The paper's projector scaling sweeps on the GPU: 64 views, no mask,
     no obstacle; image sides 128..1024 on a 128^3 cube, then cube sides
     128..1024 (up to 2^30 voxels, 4 GiB) under 256^2 images.  Per point:
-    crossings, P and blocked P^T per launch (HIP events on the launch
-    stream, median of `reps`), crossings/s, algorithmic GB/s (4 B per
-    crossing + 4 B per ray for P, 8 B + 4 B for P^T) and the paper's
-    seconds.  only = (cube side, image side) runs that single point."""
+    crossings, P and blocked P^T per launch with the default launch shapes
+    and after tomo_autotune on the point (HIP events on the launch stream,
+    median of `reps`), crossings/s and algorithmic GB/s of the tuned launches
+    (4 B per crossing + 4 B per ray for P, 8 B + 4 B for P^T), and the
+    paper's seconds.  only = (cube side, image side) runs that single point;
+    tune = False keeps the default shapes (for profiling one shape)."""
     import torch
 
     def per_launch(f):
@@ -366,11 +370,19 @@ def sweeps(tomo, ts, reps=5, only=None):
         y = tomo.project(dg, x)
         out = torch.empty_like(x)
         cross = tomo.count_crossings(dg)
-        ms_p = per_launch(lambda: tomo.project(dg, x, out=y))
-        ms_b = per_launch(lambda: tomo.backproject(dg, y, out=out, strategy=tomo.BP_BLOCKED))
+        ms_p0 = per_launch(lambda: tomo.project(dg, x, out=y))
+        ms_b0 = per_launch(lambda: tomo.backproject(dg, y, out=out, strategy=tomo.BP_BLOCKED))
+        tuned, t_tune, ms_p, ms_b = None, 0.0, ms_p0, ms_b0
+        if tune:
+            t0 = time.perf_counter()
+            tuned = tomo.autotune(dg, reps=5)
+            t_tune = time.perf_counter() - t0
+            ms_p = per_launch(lambda: tomo.project(dg, x, out=y))
+            ms_b = per_launch(lambda: tomo.backproject(dg, y, out=out))
         rays = g.nrays
         res = {"cube": n, "image": npix, "rays": rays, "crossings": cross,
-               "project_ms": ms_p, "backproject_ms": ms_b,
+               "default_project_ms": ms_p0, "default_backproject_ms": ms_b0,
+               "project_ms": ms_p, "backproject_ms": ms_b, "tuning": tuned, "autotune_s": t_tune,
                "project_crossings_per_s": cross / (ms_p * 1e-3),
                "backproject_crossings_per_s": cross / (ms_b * 1e-3),
                "project_gbs": (4.0 * cross + 4.0 * rays) / (ms_p * 1e-3) / 1e9,
@@ -389,6 +401,7 @@ def sweeps(tomo, ts, reps=5, only=None):
         log("image-size sweep done")
         cube = [point(s, 256, PAPER_CUBE_S[s]) for s in ts.SWEEP_CUBE_SIDES]
         log("cube-size sweep done")
+    tomo.autotune_clear()
     return {"workload": "the paper's projector benchmark: 64 views at 215 R_sun around the equator, FOV 3.2, "
                         "cube on [-1.5,1.5]^3, no mask, no obstacle; paper times for context (other hardware)",
             "image_size": image, "cube_size": cube}
@@ -434,7 +447,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     if args.sweep_only is not None:
-        print(json.dumps({"sweep": sweeps(tomo, ts, only=tuple(args.sweep_only))}), flush=True)
+        print(json.dumps({"sweep": sweeps(tomo, ts, only=tuple(args.sweep_only),
+                                          tune=not args.sweep_no_autotune)}), flush=True)
         return
     wl = ts.euvi()
     g = wl.geom
@@ -524,7 +538,7 @@ def main():
         out["height_gain"] = height_gain_euvi(tomo, ts, wl, y)
         log("two instruments with the height-weighted prior done")
     if not args.no_sweep:
-        out["sweep"] = sweeps(tomo, ts)
+        out["sweep"] = sweeps(tomo, ts, tune=not args.sweep_no_autotune)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, args.cpu_reps)
         log("cpu baseline done")
