@@ -42,9 +42,9 @@ HBM_PEAK_GBS = 8000.0
 # 256 MiB copy's counts; profiles/euvi128_cg50_blocked_backprojection.md), valid only for the kernel
 # sources they were taken on: sha256 over the listed files, first 16 hex digits.
 TRAFFIC = {
-    "k_backproject_blocked": (210.4e6, "fe5b511e3b8cd75c",
+    "k_backproject_blocked": (142.7e6, "92f777d3e350d00f",
                               ["blocked.h", "blocked.hip", "walk.h", "common.h"]),
-    "k_project": (264.4e6, "527070eb3ceae80e", ["siddon.hip", "walk.h", "common.h"]),
+    "k_project": (264.4e6, "b67fa33185477f40", ["siddon.hip", "walk.h", "common.h"]),
 }
 
 
