@@ -40,11 +40,12 @@ HBM_PEAK_GBS = 8000.0
 
 # HBM bytes per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE passes on this workload (scaled by a
 # 256 MiB copy's counts; profiles/euvi128_cg50_blocked_backprojection.md), valid only for the kernel
-# sources they were taken on: sha256 over the listed files, first 16 hex digits.
+# sources and default launch shapes (api.hip) they were taken on: sha256 over the listed files, first
+# 16 hex digits.
 TRAFFIC = {
-    "k_backproject_blocked": (142.7e6, "92f777d3e350d00f",
-                              ["blocked.h", "blocked.hip", "walk.h", "common.h"]),
-    "k_project": (264.4e6, "b67fa33185477f40", ["siddon.hip", "walk.h", "common.h"]),
+    "k_backproject_blocked": (163.0e6, "4a4a91f6269e39d2",
+                              ["blocked.h", "blocked.hip", "walk.h", "common.h", "api.hip"]),
+    "k_project": (264.4e6, "222f1ff3e05d4e67", ["siddon.hip", "walk.h", "common.h", "api.hip"]),
 }
 
 
