@@ -10,10 +10,14 @@ generated once and resident in HBM before timing.
 value = (P and P^T applications in the step) x (voxel crossings per
 application) / step time.  The roofline entry is for the kernel that takes
 most of the step time, timed per launch with HIP events recorded on the
-stream the library launches it on.  The CPU baseline is the FP64 oracle on a
-bounded sample of the same workload.  After the timed steps, the learned
-preconditioner's wall time to relative residual 1e-3 is compared with plain
-CG on held-out problems of its own family (time_to_rel_res_1e-3), and the
+stream the library launches it on.  Next to it, the achieved algorithmic
+bandwidth as a fraction of device copies that stream from HBM and from the
+Infinity Cache (achievable), and the crossing rate as a fraction of the VALU
+ceiling of the walk loops' instruction counts (valu).  The CPU baseline is the
+FP64 oracle on a bounded sample of the same workload.  After the timed steps,
+the learned preconditioner's wall time to relative residual 1e-3 is compared
+with plain CG on held-out problems of its own family (time_to_rel_res_1e-3),
+and the
 COR1-like batch (five systems of uneven size in persistent launches with
 autotuned shapes) is timed against solving its systems one after another
 (batched), the obstacle variant (lines of sight ending at the photosphere)
@@ -47,6 +51,45 @@ TRAFFIC = {
                               ["blocked.h", "blocked.hip", "walk.h", "common.h", "api.hip"]),
     "k_project": (264.4e6, "222f1ff3e05d4e67", ["siddon.hip", "walk.h", "common.h", "api.hip"]),
 }
+
+
+# VALU instructions per voxel crossing in the walk loops of the built gfx950
+# code (one loop step per crossing: the min of four crossing parameters, the
+# segment length, tie tests and FMA updates of the three axes, the offset
+# advance, and the gather (P) or the fixed-point LDS deposit (P^T)), read from
+# `hipcc --cuda-device-only -S` of siddon.hip and blocked.hip; the set-ups are
+# not counted.  With FP64 at the full wave64 rate, the chip issues 256 CUs x 64
+# lanes x 2.4 GHz = 39.3e12 such instructions per second.
+VALU_PER_CROSSING = {"k_project": 21, "k_backproject_blocked": 23}
+VALU_LANE_RATE = 256 * 64 * 2.4e9
+
+
+def probes(reps=5):
+    """Achievable bandwidths measured with plain device copies (torch): a
+    2 GiB buffer (HBM; the cube and images of the headline are far smaller)
+    and a 32 MiB buffer copied 20 times over (resident in the 256 MB Infinity
+    Cache).  Bytes read + written per second, median of `reps`."""
+    import torch
+
+    def rate(nbytes, inner):
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(inner):
+                dst.copy_(src)
+            e1.record()
+            e1.synchronize()
+            t.append(e0.elapsed_time(e1))
+        del src, dst
+        torch.cuda.empty_cache()
+        return 2.0 * nbytes * inner / (float(np.median(t)) * 1e-3) / 1e9
+
+    return {"hbm_copy_gbs": rate(2 << 30, 1), "mall_copy_gbs": rate(32 << 20, 20)}
 
 
 def measured_traffic(kernel):
@@ -522,6 +565,21 @@ def main():
         "roofline": {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(dom)},
     }
+    pr = probes()
+    gbs_p, gbs_bp = bytes_p / (ms_p * 1e-3) / 1e9, bytes_bp / (ms_bp * 1e-3) / 1e9
+    out["achievable"] = {**pr,
+                         "project_gbs": gbs_p, "backproject_gbs": gbs_bp,
+                         "project_frac_hbm": gbs_p / pr["hbm_copy_gbs"],
+                         "project_frac_mall": gbs_p / pr["mall_copy_gbs"],
+                         "backproject_frac_hbm": gbs_bp / pr["hbm_copy_gbs"],
+                         "backproject_frac_mall": gbs_bp / pr["mall_copy_gbs"]}
+    ceil_p = VALU_LANE_RATE / VALU_PER_CROSSING["k_project"]
+    ceil_bp = VALU_LANE_RATE / VALU_PER_CROSSING["k_backproject_blocked"]
+    out["valu"] = {"instr_per_crossing": VALU_PER_CROSSING,
+                   "project_ceiling_crossings_per_s": ceil_p,
+                   "project_frac": crossings / (ms_p * 1e-3) / ceil_p,
+                   "backproject_ceiling_crossings_per_s": ceil_bp,
+                   "backproject_frac": crossings / (ms_bp * 1e-3) / ceil_bp}
     log(f"timed steps done: {ms_step:.1f} ms per step")
     if not args.no_learned:
         out["time_to_rel_res_1e-3"] = learned_vs_plain(tomo, ts)
