@@ -465,7 +465,9 @@ def cpu_baseline(wl, reps):
         ora.project(g, wl.x)
         ora.backproject(g, y)
     dt = time.perf_counter() - t0
-    # one host thread on a smaller sample: two of the views, one pass
+    cores = ora.max_threads()
+    # one host thread on a smaller sample: two of the views, one pass (the
+    # oracle's thread count persists, so it is set back afterwards)
     g2 = g.subset([0, 1])
     c2 = ora.count_crossings(g2)
     y2 = y[:g2.nrays]
@@ -473,8 +475,9 @@ def cpu_baseline(wl, reps):
     ora.project(g2, wl.x, nthreads=1)
     ora.backproject(g2, y2, nthreads=1)
     dt1 = time.perf_counter() - t1
+    ora.count_crossings(g2, nthreads=cores)
     return {"value": 2.0 * reps * cross / dt, "unit": "voxel-crossings/s",
-            "cores": ora.max_threads(), "kind": "oracle",
+            "cores": cores, "kind": "oracle",
             "sample": f"{reps} x (P + P^T) over all 28 views of 512x512 and the 128^3 EUVI-like "
                       f"cube ({cross} crossings per application), {dt:.1f} s",
             "one_thread": {"value": 2.0 * c2 / dt1, "cores": 1,
