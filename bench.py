@@ -24,7 +24,8 @@ autotuned shapes) is timed against solving its systems one after another
 is measured on the headline workload (obstacle), the Thomson-scattering
 operators pB and B on a COR1-like frame (thomson), the headline workload
 as two instruments with gains and the height-weighted prior (height_gain),
-and the paper's image-size and cube-size projector sweeps (sweep).
+P and P^T on the other configurations' geometries (configs), and the
+paper's image-size and cube-size projector sweeps (sweep).
 """
 from __future__ import annotations
 
@@ -131,6 +132,8 @@ def parse():
                     help="skip the Thomson-scattering operator measurement")
     ap.add_argument("--no-height-gain", action="store_true",
                     help="skip the two-instrument, height-weighted-prior measurement")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip P and P^T on the other configurations' geometries")
     ap.add_argument("--no-sweep", action="store_true",
                     help="skip the paper's image-size and cube-size projector sweeps")
     ap.add_argument("--sweep-only", type=int, nargs=2, metavar=("CUBE", "IMAGE"), default=None,
@@ -453,6 +456,46 @@ def sweeps(tomo, ts, reps=5, only=None, tune=True):
             "image_size": image, "cube_size": cube}
 
 
+def per_config(tomo, ts, reps=20):
+    """P and the default P^T per launch on the other configurations' geometries
+    (HIP events on the launch stream, median of `reps` after 3 warm-ups):
+    the tiny 32^3 problem, one COR1-like 256^3 frame with its masks, the
+    differentiable 128^3 / 32 x 256^2 set-up and a learned-preconditioner
+    problem (128^3, 28 x 256^2)."""
+    import torch
+
+    def per_launch(f):
+        for _ in range(3):
+            f()
+        torch.cuda.synchronize()
+        t = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            f()
+            e1.record()
+            e1.synchronize()
+            t.append(e0.elapsed_time(e1))
+        return float(np.median(t))
+
+    out = {}
+    for name, wl in (("tiny", ts.tiny()), ("cor1_frame", ts.cor1_frames(K=1)),
+                     ("differentiable", ts.differentiable()), ("learned", ts.learned(2003))):
+        dg = tomo.DeviceGeometry(wl.geom)
+        x = torch.as_tensor(wl.x.reshape(dg.cube_shape).astype(np.float32)).cuda()
+        y = tomo.project(dg, x)
+        back = torch.empty_like(x)
+        cross = tomo.count_crossings(dg)
+        ms_p = per_launch(lambda: tomo.project(dg, x, out=y))
+        ms_b = per_launch(lambda: tomo.backproject(dg, y, out=back))
+        out[name] = {"geometry": wl.name, "crossings": cross, "project_ms": ms_p, "backproject_ms": ms_b,
+                     "project_crossings_per_s": cross / (ms_p * 1e-3),
+                     "backproject_crossings_per_s": cross / (ms_b * 1e-3)}
+        del dg, x, y, back
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_baseline(wl, reps):
     """The FP64 oracle (as it stands) on a bounded sample: `reps` passes of
     P and P^T over the full geometry (the CG's operator pair), all host
@@ -611,6 +654,9 @@ def main():
     if not args.no_height_gain:
         out["height_gain"] = height_gain_euvi(tomo, ts, wl, y)
         log("two instruments with the height-weighted prior done")
+    if not args.no_configs:
+        out["configs"] = per_config(tomo, ts)
+        log("per-configuration P and P^T done")
     if not args.no_sweep:
         out["sweep"] = sweeps(tomo, ts, tune=not args.sweep_no_autotune)
     if not args.no_cpu_baseline:
