@@ -496,7 +496,7 @@ def per_config(tomo, ts, reps=20):
     return out
 
 
-def cpu_baseline(wl, reps):
+def cpu_baseline(wl, reps, ts_mod):
     """The FP64 oracle (as it stands) on a bounded sample: `reps` passes of
     P and P^T over the full geometry (the CG's operator pair), all host
     cores."""
@@ -521,12 +521,25 @@ def cpu_baseline(wl, reps):
     ora.backproject(g2, y2, nthreads=1)
     dt1 = time.perf_counter() - t1
     ora.count_crossings(g2, nthreads=cores)
+    # the other configurations, one P + P^T pass each on all cores (one
+    # COR1-like frame for the batched configuration)
+    others = {}
+    for name, w2 in (("tiny", ts_mod.tiny()), ("differentiable", ts_mod.differentiable()),
+                     ("learned", ts_mod.learned(2003)), ("cor1_frame", ts_mod.cor1_frames(K=1))):
+        gg = w2.geom
+        cc = ora.count_crossings(gg)
+        yy = np.random.default_rng(1).normal(size=gg.nrays)
+        t2 = time.perf_counter()
+        ora.project(gg, w2.x)
+        ora.backproject(gg, yy)
+        others[name] = {"crossings_per_s": 2.0 * cc / (time.perf_counter() - t2), "crossings": cc}
     return {"value": 2.0 * reps * cross / dt, "unit": "voxel-crossings/s",
             "cores": cores, "kind": "oracle",
             "sample": f"{reps} x (P + P^T) over all 28 views of 512x512 and the 128^3 EUVI-like "
                       f"cube ({cross} crossings per application), {dt:.1f} s",
             "one_thread": {"value": 2.0 * c2 / dt1, "cores": 1,
-                           "sample": f"1 x (P + P^T) over 2 of the views ({c2} crossings), {dt1:.1f} s"}}
+                           "sample": f"1 x (P + P^T) over 2 of the views ({c2} crossings), {dt1:.1f} s"},
+            "other_configs": others}
 
 
 def main():
@@ -660,7 +673,7 @@ def main():
     if not args.no_sweep:
         out["sweep"] = sweeps(tomo, ts, tune=not args.sweep_no_autotune)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_reps)
+        out["cpu_baseline"] = cpu_baseline(wl, args.cpu_reps, ts)
         log("cpu baseline done")
     print(json.dumps(out), flush=True)
 
