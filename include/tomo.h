@@ -189,8 +189,12 @@ int tomo_trace_ray(const tomo_geometry *g, int32_t view, int32_t col,
  * suit MI355X; tomo_autotune() (or a caller) may change them.
  *   p_bundle, bp_bundle: shape of the pixel bundle one 64-lane wavefront
  *     walks inside a 16x16 workgroup tile: 2 = 4x16, 3 = 8x8, 4 = 16x4 pixels,
- *     0 = the 64 lanes interleaved at a 2-pixel pitch over the whole tile.
- *   p_xcd_remap, bp_xcd_remap: 1 = give each XCD a contiguous run of tiles.
+ *     0 = the 64 lanes interleaved at a 2-pixel pitch over the whole tile
+ *     (p_bundle: P; bp_bundle: the binned and atomic back-projections; the
+ *     blocked one walks each footprint 256 pixels at a time in row-major
+ *     order and takes no bundle shape).
+ *   p_xcd_remap, bp_xcd_remap: 1 = give each XCD a contiguous run of tiles
+ *     (of voxel-block items for the blocked back-projection).
  *   bp_lds_bins: 64-bit LDS bins per workgroup of the binned
  *     back-projection (512..8192, i.e. 4..64 KiB; larger boxes mean fewer
  *     flushes but fewer resident workgroups).
@@ -423,7 +427,7 @@ void tomo_cg_default_params(tomo_cg_params *p);
 /*
  * Autotuner.  Times, on this geometry with synthetic data, the P wavefront
  * bundles with and without the XCD remap, and the P^T strategies (blocked
- * over several block shapes, owner counts and bundles; binned; atomic), each
+ * over several block shapes, owner counts and the XCD remap; binned; atomic), each
  * over `reps` launches after one warm-up, and keeps the fastest P shape and
  * P^T strategy/shape as the tuning of the geometry's size class: the cube's
  * largest side, the pixels per view and the view count, each rounded up to

@@ -23,7 +23,6 @@ struct SysDev {
     BlockDev bd;
     int32_t nviews;
     int32_t p_log2_bw;
-    int32_t bp_log2_bw;
     int32_t maxit;
     int32_t view_begin;   // first row of this system in the max|y| table
     int64_t tile_begin;   // first P item

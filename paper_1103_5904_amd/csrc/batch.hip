@@ -149,8 +149,8 @@ __global__ __launch_bounds__(kThreads) void k_batch_backproject(const SysDev *__
         const uint32_t *ym = ymax + (int64_t)sd.view_begin * kYmaxParts;
         const bool mm = ops.map && sd.map_mask, dm = sd.data_mask != nullptr;
 #define TOMO_ITEM(M, D, O)                                                                                 \
-    blocked_item<M, D, O>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, sd.bp_log2_bw, li,      \
-                          ops.src[k], sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh)
+    blocked_item<M, D, O>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, li, ops.src[k],         \
+                          sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh)
         if (sd.grid.has_sph) {  // the obstacle's variant: one code path for every mask combination
             if (mm && dm) TOMO_ITEM(true, true, true);
             else if (mm) TOMO_ITEM(true, false, true);
@@ -276,7 +276,6 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
         sd.bd.maxit = bs.b[0] + bs.b[1] + bs.b[2] + 3;
         sd.nviews = p->nviews;
         sd.p_log2_bw = tu.p_bundle;
-        sd.bp_log2_bw = tu.bp_bundle;
         sd.maxit = p->max_steps;
         sd.view_begin = b->nviews;
         sd.tile_begin = b->ntiles;

@@ -40,21 +40,6 @@ __device__ inline uint32_t view_absmax_part(const ViewDev &v, int part, const fl
     return r;
 }
 
-// Offsets (dc, dr) of this lane's pixel inside a 16x16 pixel tile, by the
-// same wave bundles as the tile kernels.
-__device__ inline void tile_lane(int log2_bw, int &dc, int &dr)
-{
-    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-    if (log2_bw == 0) {
-        dc = (l & 7) * 2 + (w & 1);
-        dr = (l >> 3) * 2 + (w >> 1);
-        return;
-    }
-    const int bw = 1 << log2_bw, bh = 64 >> log2_bw, wpr = kTile >> log2_bw;
-    dc = (w % wpr) * bw + (l & (bw - 1));
-    dr = (w / wpr) * bh + (l >> log2_bw);
-}
-
 // Shared-memory scratch of one item besides the bins: the pixel rectangles
 // of up to kViewChunk of the owner's views, computed together so that the
 // wavefronts then run through all of them without workgroup barriers.
@@ -71,7 +56,7 @@ template <bool kMapMask, bool kDataMask, bool kObstacle>
 __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict__ views,
                                     const int32_t *__restrict__ frame_views,
                                     const int32_t *__restrict__ frame_voff, const BlockDev &bd,
-                                    int log2_bw, int64_t item, const float *__restrict__ images,
+                                    int64_t item, const float *__restrict__ images,
                                     const uint8_t *__restrict__ map_mask,
                                     const uint8_t *__restrict__ data_mask,
                                     const uint32_t *__restrict__ ymax_parts, float *__restrict__ out,
@@ -124,8 +109,6 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
     for (int i = threadIdx.x; i <= nbins; i += kThreads) bins[i] = 0ull;  // + the dummy bin
     unsigned spills = 0u;
 
-    int dc = 0, dr = 0;
-    tile_lane(log2_bw, dc, dr);
     const int nvi = v1 - v0 > split ? (v1 - v0 - split + bd.splits - 1) / bd.splits : 0;  // owner's views
     for (int cs = 0; cs < nvi; cs += kViewChunk) {
         const int nch = min(kViewChunk, nvi - cs);
@@ -187,12 +170,17 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
             // the view's gain times the bin scale (a power of two: exact)
             const double vscale = v.gain * (finite ? fx_scale : 1.0);
 
-            // ---- rays of the rectangle, a 16x16 tile per pass; each pass loads
-            // the next pass's pixel value so that its latency is hidden by the walk
-            const int tx = (c1 - c0) / kTile + 1, ntile = tx * ((r1 - r0) / kTile + 1);
-            int tcx = 0, tcy = 0;
-            int col = c0 + dc, row = r0 + dr;
-            bool ok = col <= c1 && row <= r1;
+            // ---- rays of the rectangle, 256 per pass in row-major order (thread
+            // i takes pixel i of each pass: a wavefront walks a run of 64
+            // neighbouring pixels, and only the last pass is ragged, where 16x16
+            // tiles left every pass ragged at the rectangle's edges); each pass
+            // loads the next pass's pixel value so that its latency is hidden by
+            // the walk
+            const int W = c1 - c0 + 1, npx = W * (r1 - r0 + 1), ntile = (npx + kThreads - 1) / kThreads;
+            const int adv_r = kThreads / W, adv_c = kThreads - adv_r * W;  // a pass moves kThreads pixels
+            int lin = threadIdx.x;
+            int col = c0 + lin % W, row = r0 + lin / W;
+            bool ok = lin < npx;
             float ynext = 0.0f;
             bool mnext = true;
             if (ok) {
@@ -204,13 +192,14 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 const int pcol = col, prow = row;
                 const bool pok = ok, pm = mnext;
                 const float yv = ynext;
-                if (++tcx == tx) {
-                    tcx = 0;
-                    ++tcy;
+                lin += kThreads;
+                col += adv_c;
+                row += adv_r;
+                if (col > c1) {
+                    col -= W;
+                    ++row;
                 }
-                col = c0 + tcx * kTile + dc;
-                row = r0 + tcy * kTile + dr;
-                ok = t + 1 < ntile && col <= c1 && row <= r1;
+                ok = lin < npx;
                 if (ok) {
                     const int64_t pix = v.pix_off + (int64_t)row * v.ncol + col;
                     ynext = images[pix];

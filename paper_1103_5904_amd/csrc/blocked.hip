@@ -65,9 +65,8 @@ __global__ __launch_bounds__(kThreads) void k_backproject_blocked(
     const int64_t nitems = (int64_t)bd.nb[0] * bd.nb[1] * bd.nb[2] * g.nframes * bd.splits;
     const int64_t item = bun.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     if (item >= nitems) return;
-    blocked_item<kMapMask, kDataMask, kObstacle>(g, views, frame_views, frame_voff, bd, bun.log2_bw, item,
-                                                 images, map_mask, data_mask, ymax_parts, out, accumulate,
-                                                 spill, bins, sh);
+    blocked_item<kMapMask, kDataMask, kObstacle>(g, views, frame_views, frame_voff, bd, item, images, map_mask,
+                                                 data_mask, ymax_parts, out, accumulate, spill, bins, sh);
 }
 
 // out[i] = M (sum over owners of part[s][i]) (+ out[i]), owners in order.

@@ -12,8 +12,9 @@
 // entry (tuning_for); other classes keep the process-wide tuning.
 //
 // Candidates: P - the four wavefront bundles x XCD remap on/off; P^T - the
-// owner-computes strategy over five block shapes, three owner counts and two
-// bundles, the LDS-binned strategy over three bundles, and the atomic one.
+// owner-computes strategy over five block shapes, three owner counts and the
+// XCD remap on/off, the LDS-binned strategy over three bundles, and the
+// atomic one.
 // The workgroup size is not searched (every kernel is built for 256 lanes,
 // four wavefronts), nor is the cube layout (x fastest is the ABI's).
 #include <math.h>
@@ -103,14 +104,14 @@ int tomo_autotune(const tomo_geometry *g, int32_t reps, tomo_tuning *out, tomo_s
     const int blocks[5][3] = {{16, 16, 16}, {32, 16, 8}, {16, 32, 8}, {16, 16, 8}, {32, 32, 4}};
     for (const auto &b : blocks)
         for (int sp : {0, 4, 8})
-            for (int bun : {2, 4}) {
+            for (int xr : {0, 1}) {  // (the blocked kernel takes no bundle shape)
                 tomo_tuning t = base;
                 t.bp_default = TOMO_BP_BLOCKED;
                 t.bp_block[0] = b[0];
                 t.bp_block[1] = b[1];
                 t.bp_block[2] = b[2];
                 t.bp_splits = sp;
-                t.bp_bundle = bun;
+                t.bp_xcd_remap = xr;
                 bc.push_back(t);
             }
     if (p.grid.nvox < ((int64_t)1 << 30)) {  // the atomic strategies' frame limit
@@ -190,6 +191,7 @@ int tomo_autotune(const tomo_geometry *g, int32_t reps, tomo_tuning *out, tomo_s
             best_b = ms;
             win.bp_default = t.bp_default;
             win.bp_bundle = t.bp_bundle;
+            win.bp_xcd_remap = t.bp_xcd_remap;
             win.bp_block[0] = t.bp_block[0];
             win.bp_block[1] = t.bp_block[1];
             win.bp_block[2] = t.bp_block[2];
