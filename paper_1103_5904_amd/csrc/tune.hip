@@ -12,9 +12,9 @@
 // entry (tuning_for); other classes keep the process-wide tuning.
 //
 // Candidates: P - the four wavefront bundles x XCD remap on/off; P^T - the
-// owner-computes strategy over five block shapes, three owner counts and the
-// XCD remap on/off, the LDS-binned strategy over three bundles, and the
-// atomic one.
+// owner-computes strategy over seven block shapes (flat to cubic), two owner
+// counts and the XCD remap on/off, the LDS-binned strategy over three
+// bundles, and the atomic one.
 // The workgroup size is not searched (every kernel is built for 256 lanes,
 // four wavefronts), nor is the cube layout (x fastest is the ABI's).
 #include <math.h>
@@ -101,9 +101,12 @@ int tomo_autotune(const tomo_geometry *g, int32_t reps, tomo_tuning *out, tomo_s
             t.p_xcd_remap = xr;
             pc.push_back(t);
         }
-    const int blocks[5][3] = {{16, 16, 16}, {32, 16, 8}, {16, 32, 8}, {16, 16, 8}, {32, 32, 4}};
+    // flat blocks suit lines of sight near one plane (solar observers near the
+    // ecliptic); cubic ones suit views from all directions
+    const int blocks[7][3] = {{64, 32, 2}, {64, 64, 1}, {64, 16, 4}, {32, 32, 4},
+                              {32, 16, 8}, {16, 32, 8}, {16, 16, 16}};
     for (const auto &b : blocks)
-        for (int sp : {0, 4, 8})
+        for (int sp : {0, 8})
             for (int xr : {0, 1}) {  // (the blocked kernel takes no bundle shape)
                 tomo_tuning t = base;
                 t.bp_default = TOMO_BP_BLOCKED;
