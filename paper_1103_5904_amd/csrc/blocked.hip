@@ -11,8 +11,9 @@
 //   bounding rectangle of the block's eight corners projected through the
 //   pinhole (plus one pixel of margin); corners behind the observer widen it
 //   to the whole detector.
-// * Each lane takes one of those rays, sets it up exactly as P does and
-//   walks only its part inside the block.  The walk's crossing parameters
+// * The rectangle is walked 256 pixels per pass in row-major order; each
+//   lane takes one of those rays, sets it up exactly as P does and walks
+//   only its part inside the block.  The walk's crossing parameters
 //   live on a power-of-two grid on which every sum the walk forms is exact:
 //   the k-th crossing of axis a is s_a + k ds_a whatever the order of
 //   additions.  So the parameter interval [E, X) in which the ray is inside
@@ -22,7 +23,7 @@
 //   P's.
 // * Contributions go to 64-bit fixed-point LDS bins (integer LDS atomics;
 //   sums are exact and order-independent).  The scale is a power of two from
-//   the largest |y| of the views involved and the number of their pixels, a
+//   the largest |gain y| of the views involved and the number of their pixels, a
 //   bound on the rays that can reach one voxel, so no bin can overflow.
 //   Items whose views hold a non-finite value accumulate in FP32 LDS bins
 //   instead.
