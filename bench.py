@@ -419,6 +419,7 @@ def sweeps(tomo, ts, reps=5, only=None, tune=True):
         g = ts.sweep_geometry(n, npix)
         dg = tomo.DeviceGeometry(g)
         x = torch.as_tensor(ts.sweep_cube(ts.sweep_cube_parts(n))).cuda()
+        tomo.autotune_clear()  # the default shapes, whatever an earlier point of this class tuned
         y = tomo.project(dg, x)
         out = torch.empty_like(x)
         cross = tomo.count_crossings(dg)

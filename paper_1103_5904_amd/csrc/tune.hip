@@ -129,8 +129,9 @@ int tomo_autotune(const tomo_geometry *g, int32_t reps, tomo_tuning *out, tomo_s
         bc.push_back(t);
     }
 
-    // synthetic operands and the largest scratch any candidate needs
-    size_t scratch_bytes = 0;
+    // synthetic operands and the largest scratch any candidate (or the
+    // current tuning) needs
+    size_t scratch_bytes = blocked_scratch_bytes(p, blocked_shape(p, base));
     for (const auto &t : bc) {
         const size_t b = blocked_scratch_bytes(p, blocked_shape(p, t));
         scratch_bytes = b > scratch_bytes ? b : scratch_bytes;
@@ -171,8 +172,30 @@ int tomo_autotune(const tomo_geometry *g, int32_t reps, tomo_tuning *out, tomo_s
         if (!e) e = hip_fail(hipEventElapsedTime(&ms, tm.a, tm.b), "event time");
         return e;
     };
+    // bring the clocks up before anything is timed: the current tuning's P
+    // (and P^T, unless this geometry refuses its strategy) repeated for at
+    // least 30 ms; then the current tuning is the one to beat, by at least 2%
+    // (differences below that are within the timing noise)
+    const tomo_tuning base_b = base.bp_default != TOMO_BP_BLOCKED && p.grid.nvox >= ((int64_t)1 << 30)
+                                   ? bc.front()  // a blocked candidate: the atomic strategies refuse this frame
+                                   : base;
     float best_p = INFINITY, best_b = INFINITY;
     tomo_tuning win = base;
+    {
+        float warm = 0.f, a = 0.f, b = 0.f;
+        for (int k = 0; k < 64 && warm < 30.f; ++k) {
+            rc = time_it([&] { return launch_project_tuned(p, g, cube, img, true, s, nullptr, base); }, a);
+            if (!rc)
+                rc = time_it([&] {
+                    return launch_backproject_tuned(p, g, img, cube, false, true, base_b.bp_default, s, nullptr,
+                                                    scratch, scratch_bytes, base_b);
+                }, b);
+            if (rc) return rc;
+            warm += a + b;
+        }
+        best_p = 0.98f * a;
+        if (base_b.bp_default == base.bp_default) best_b = 0.98f * b;  // else a candidate must set it
+    }
     for (const auto &t : pc) {
         float ms = 0.f;
         rc = time_it([&] { return launch_project_tuned(p, g, cube, img, true, s, nullptr, t); }, ms);
