@@ -5,8 +5,11 @@
 //
 // GPU design: FP32 vectors, FP64 dot products and scalars.  Every scalar of
 // the recurrence (alpha, beta, residual norms) lives in device memory and is
-// produced by the last workgroup of the kernel that reduces it, in a fixed
-// order (deterministic).  A device "done" flag, raised when the residual
+// summed in a fixed order (deterministic).  In the plain CG iteration each
+// workgroup leaves its partial of p.q or r.r, and every workgroup of the
+// next kernel sums them itself; elsewhere the last workgroup to finish sums
+// them (a counter and a device-scope fence per workgroup, which costs a
+// write-back of the XCD's L2 each).  A device "done" flag, raised when the residual
 // target or the iteration limit is reached, makes every later kernel of the
 // iteration return at once, so the host enqueues iterations in chunks and
 // synchronises only between chunks.  The vector updates are fused into
@@ -33,6 +36,7 @@ struct CgState {
     double res2;      // r.r of the current iterate
     double aux;       // scratch result of the last reduction
     double res_prev;  // flexible CG: r.r of the previous iterate (stall test)
+    double rr_prev;   // rr as the x/r update read it (beta's denominator)
     double drop2;     // flexible CG: (1 - min_drop)^2
     int32_t iter;     // iterations completed
     int32_t max_iter; // iteration limit
@@ -49,6 +53,7 @@ struct CgState {
 struct Workspace {
     double *partials;   // [kRedBlocks][4]
     unsigned *counter;  // last-block detection
+    double *cpart;      // [2][kRedBlocks]: p.q and r.r per workgroup, summed by the next kernel
     CgState *st;
     double *hist;       // [max_iter + 1]
 };
@@ -220,7 +225,74 @@ __device__ inline bool grid_reduce2(double a, double b, const Workspace &ws, dou
     return last;
 }
 
+// Total of the per-workgroup partials that the previous kernel left in
+// part[0 .. nb), summed in the same fixed order as grid_reduce
+// (deterministic) by every workgroup that needs it: the launch boundary has
+// made them visible, so their producer needs no fence and no counter (a
+// device-scope release per workgroup writes back the XCD's L2).  Valid in
+// every thread.
+__device__ inline double sum_partials(const double *__restrict__ part, int nb)
+{
+    __shared__ double lds[4];
+    __shared__ double tot;
+    constexpr int kPer = kRedBlocks / kThreads;
+    double v[kPer];
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) {
+        const int i = threadIdx.x + u * kThreads;
+        v[u] = i < nb ? part[i] : 0.0;
+    }
+    double pa = 0.0;
+#pragma unroll
+    for (int u = 0; u < kPer; ++u) pa += v[u];
+    const double t = block_sum(pa, lds);
+    if (threadIdx.x == 0) tot = t;
+    __syncthreads();
+    return tot;
+}
+
+// This workgroup's share of a sum, for sum_partials in the next kernel.
+__device__ inline void put_partial(double a, double *part)
+{
+    __shared__ double lds[4];
+    const double t = block_sum(a, lds);
+    if (threadIdx.x == 0) part[blockIdx.x] = t;
+}
+
 __device__ inline bool bad(double v) { return !isfinite(v); }
+
+// The stop flag as this workgroup's thread 0 reads it, the same in all of
+// its threads: workgroup 0 of the running kernel may raise it while the
+// others start, and their threads must agree before a workgroup barrier.
+__device__ inline bool stopped(const CgState *st)
+{
+    __shared__ int f;
+    if (threadIdx.x == 0) f = st->done;
+    __syncthreads();
+    return f != 0;
+}
+
+// alpha = rr / p.q from k_cg_q's partials, the same in every workgroup;
+// workgroup 0 records it.  Returns false (every workgroup alike) when the
+// step is not usable, and then raises the stop flag.
+__device__ inline bool take_alpha(const Workspace &ws, double &alpha)
+{
+    CgState &s = *ws.st;
+    const double tpq = sum_partials(ws.cpart, gridDim.x);
+    const double rr = s.rr;
+    alpha = rr / tpq;
+    const bool ok = !bad(alpha) && tpq > 0.0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s.pq = tpq;
+        s.alpha = alpha;
+        s.rr_prev = rr;
+        if (!ok) {
+            s.nonfinite = 1;
+            s.done = 1;
+        }
+    }
+    return ok;
+}
 
 // r = b - q (or r = b), p = r, q = 0; state from r.r and b.b.
 __global__ __launch_bounds__(kThreads) void k_cg_start(const float *__restrict__ b,
@@ -255,7 +327,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_start(const float *__restrict__
     }
 }
 
-// q = M (q + prior(p)); pq = p.q; alpha = rr / pq.
+// q = M (q + prior(p)); per-workgroup partials of p.q.
 template <bool kHeight>
 __global__ __launch_bounds__(kThreads) void k_cg_q(const float *__restrict__ p,
                                                    float *__restrict__ q,
@@ -272,25 +344,18 @@ __global__ __launch_bounds__(kThreads) void k_cg_q(const float *__restrict__ p,
         q[i] = v;
         pq += (double)p[i] * v;
     }
-    double tpq, unused;
-    if (grid_reduce2(pq, 0.0, ws, tpq, unused) && threadIdx.x == 0) {
-        CgState &s = *ws.st;
-        s.pq = tpq;
-        s.alpha = s.rr / tpq;
-        if (bad(s.alpha) || !(tpq > 0.0)) {
-            s.nonfinite = 1;
-            s.done = 1;
-        }
-    }
+    put_partial(pq, ws.cpart);
 }
 
-// x += alpha p; r -= alpha q; q = 0; rr_new = r.r; beta = rr_new / rr.
+// alpha = rr / p.q; x += alpha p; r -= alpha q; q = 0; per-workgroup
+// partials of the new r.r.
 __global__ __launch_bounds__(kThreads) void k_cg_xr(float *__restrict__ x, float *__restrict__ r,
                                                     const float *__restrict__ p,
                                                     float *__restrict__ q, int64_t n, Workspace ws)
 {
-    if (ws.st->done) return;
-    const double alpha = ws.st->alpha;
+    if (stopped(ws.st)) return;
+    double alpha;
+    if (!take_alpha(ws, alpha)) return;
     double rr = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kThreads) {
@@ -301,26 +366,30 @@ __global__ __launch_bounds__(kThreads) void k_cg_xr(float *__restrict__ x, float
         q[i] = 0.0f;
         rr += (double)rv * rv;
     }
-    double trr, unused;
-    if (grid_reduce2(rr, 0.0, ws, trr, unused) && threadIdx.x == 0) {
-        CgState &s = *ws.st;
-        s.beta = trr / s.rr;
+    put_partial(rr, ws.cpart + kRedBlocks);
+}
+
+// rr_new = r.r from k_cg_xr's partials; beta = rr_new / rr; p = r + beta p.
+// Workgroup 0 commits the iteration (rr, history, stop test).  rr itself is
+// not read here (beta takes rr_prev), so that commit races with no reader;
+// a workgroup that already sees the stop flag leaves p alone, which no later
+// step reads (a restart rebuilds p from r).
+__global__ __launch_bounds__(kThreads) void k_cg_p(const float *__restrict__ r,
+                                                   float *__restrict__ p, int64_t n, Workspace ws)
+{
+    if (stopped(ws.st)) return;
+    CgState &s = *ws.st;
+    const double trr = sum_partials(ws.cpart + kRedBlocks, gridDim.x);
+    const double beta = trr / s.rr_prev;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        s.beta = beta;
         s.rr = trr;
         s.res2 = trr;
         s.iter += 1;
         ws.hist[s.iter] = sqrt(trr / s.bb);
-        if (bad(trr) || bad(s.beta)) s.nonfinite = 1;
+        if (bad(trr) || bad(beta)) s.nonfinite = 1;
         s.done = s.nonfinite || trr <= s.thresh2 || s.iter >= s.max_iter;
     }
-}
-
-// p = r + beta p.
-__global__ __launch_bounds__(kThreads) void k_cg_p(const float *__restrict__ r,
-                                                   float *__restrict__ p, int64_t n,
-                                                   const CgState *__restrict__ st)
-{
-    if (st->done) return;
-    const double beta = st->beta;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kThreads)
         p[i] = (float)((double)r[i] + beta * p[i]);
@@ -348,8 +417,9 @@ __global__ __launch_bounds__(kThreads) void k_fcg_xr(float *__restrict__ x, floa
                                                      const float *__restrict__ q, int64_t n,
                                                      Workspace ws)
 {
-    if (ws.st->done) return;
-    const double alpha = ws.st->alpha;
+    if (stopped(ws.st)) return;
+    double alpha;
+    if (!take_alpha(ws, alpha)) return;
     double rr = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kThreads) {
@@ -664,6 +734,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     Workspace ws;
     ws.partials = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
     ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
+    ws.cpart = (double *)buf.alloc(sizeof(double) * 2 * kRedBlocks);
     ws.st = (CgState *)buf.alloc(sizeof(CgState));
     ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)maxit + 1));
     // back-projection strategy and its scratch, fixed for the whole solve
@@ -677,7 +748,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     }
     float *z = fcg ? (float *)buf.alloc(sizeof(float) * n) : nullptr;
     void *netws = fcg ? buf.alloc(convnet_forward_ws_bytes(d.nvox)) : nullptr;
-    if (!b || !r || !p || !q || !img || !ws.partials || !ws.counter || !ws.st || !ws.hist ||
+    if (!b || !r || !p || !q || !img || !ws.partials || !ws.counter || !ws.cpart || !ws.st || !ws.hist ||
         (fcg && (!z || !netws)))
         return set_error(TOMO_ENOMEM, "tomo_cg_solve: device allocation failed");
     int rc = hip_fail(hipMemsetAsync(ws.counter, 0, sizeof(unsigned), s), "counter init");
@@ -797,7 +868,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         launch_cg_q(hw, eb, s, p, q, g->map_mask, d, lr, lt, ws, hd);
         if (!fcg) {
             hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
-            hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, s, r, p, n, ws.st);
+            hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, s, r, p, n, ws);
         } else {
             hipLaunchKernelGGL(k_fcg_xr, dim3(eb), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
             e = convnet_forward_dev(g->cube, prm->precond, r, z, &ws.st->res2, g->map_mask, netws, s,
@@ -966,9 +1037,10 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
         c.img = (float *)buf.alloc(sizeof(float) * c.npix);
         c.ws.partials = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
         c.ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
+        c.ws.cpart = (double *)buf.alloc(sizeof(double) * 2 * kRedBlocks);
         c.ws.st = states + k;
         c.ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)c.maxit + 1));
-        if (!c.b || !c.r || !c.p || !c.q || !c.img || !c.ws.partials || !c.ws.counter || !c.ws.hist)
+        if (!c.b || !c.r || !c.p || !c.q || !c.img || !c.ws.partials || !c.ws.counter || !c.ws.cpart || !c.ws.hist)
             return set_error(TOMO_ENOMEM, "tomo_batch_cg_solve: device allocation failed");
         int rc = hip_fail(hipMemsetAsync(c.ws.counter, 0, sizeof(unsigned), s), "counter init");
         if (rc) return rc;
@@ -1098,7 +1170,7 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
             const unsigned eb = elem_blocks(c.n);
             launch_cg_q(c.hw, eb, st, c.p, c.q, c.mm, c.d, c.lr, c.lt, c.ws, c.hd);
             hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, st, x_d[k], c.r, c.p, c.q, c.n, c.ws);
-            hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, st, c.r, c.p, c.n, c.ws.st);
+            hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, st, c.r, c.p, c.n, c.ws);
         }
         return hip_fail(hipGetLastError(), "batched cg iteration launch");
     };
