@@ -47,13 +47,15 @@ struct CgState {
     int32_t fellback; // 1 once the solver has switched to plain CG
     int32_t fb_iter;  // iteration of the switch
     int32_t restart;  // 1: the next direction restarts (beta = 0)
+    int32_t fb_snap;  // fellback and restart as the dot-product pass found them
+    int32_t rs_snap;  //   (read by the direction update while it rewrites them)
     int32_t net_off;  // 1: skip the network (done, or fallen back)
 };
 
 struct Workspace {
     double *partials;   // [kRedBlocks][4]
     unsigned *counter;  // last-block detection
-    double *cpart;      // [2][kRedBlocks]: p.q and r.r per workgroup, summed by the next kernel
+    double *cpart;      // [4][kRedBlocks]: per-workgroup partials summed by the next kernel
     CgState *st;
     double *hist;       // [max_iter + 1]
 };
@@ -403,6 +405,7 @@ __global__ void k_fcg_init(Workspace ws, int32_t window, double min_drop)
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     CgState &s = *ws.st;
     s.alpha = 0.0;
+    s.rr_prev = s.rr;
     s.window = window;
     s.drop2 = (1.0 - min_drop) * (1.0 - min_drop);
     s.res_prev = s.res2;
@@ -448,15 +451,14 @@ __global__ __launch_bounds__(kThreads) void k_fcg_xr(float *__restrict__ x, floa
     }
 }
 
-// z.r, z.q, r.r, r.q; q = 0; beta: Polak-Ribiere -alpha z.q / (z.r)_old, or
-// plain CG after the fall-back (and 0 on a restart).  A direction with
-// z.r <= 0 (or non-finite) triggers the fall-back.
+// z.r, z.q, r.r, r.q per workgroup (for k_fcg_p); q = 0.  Workgroup 0
+// snapshots the fall-back state that k_fcg_p reads while it rewrites it.
 __global__ __launch_bounds__(kThreads) void k_fcg_dots(const float *__restrict__ z,
                                                        const float *__restrict__ r,
                                                        float *__restrict__ q, int64_t n,
                                                        Workspace ws)
 {
-    if (ws.st->done) return;
+    if (stopped(ws.st)) return;
     const bool usez = !ws.st->fellback;
     double a[4] = {0.0, 0.0, 0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
@@ -469,23 +471,46 @@ __global__ __launch_bounds__(kThreads) void k_fcg_dots(const float *__restrict__
         a[3] += rv * qv;
         q[i] = 0.0f;
     }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) put_partial(a[k], ws.cpart + k * kRedBlocks);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        ws.st->fb_snap = ws.st->fellback;
+        ws.st->rs_snap = ws.st->restart;
+    }
+}
+
+// beta from k_fcg_dots' totals: Polak-Ribiere -alpha z.q / (z.r)_old, or
+// plain CG after the fall-back (and 0 on a restart); a direction with
+// z.r <= 0 (or non-finite) triggers the fall-back.  Every workgroup takes
+// the same decisions from the same totals and the snapshot; workgroup 0
+// commits them.  Then p = z + beta p (or r + beta p after the fall-back).
+__global__ __launch_bounds__(kThreads) void k_fcg_p(const float *__restrict__ z,
+                                                    const float *__restrict__ r,
+                                                    float *__restrict__ p, int64_t n, Workspace ws)
+{
+    if (stopped(ws.st)) return;
+    CgState &s = *ws.st;
     double t[4];
-    if (grid_reduce<4>(a, ws, t) && threadIdx.x == 0) {
-        CgState &s = *ws.st;
-        if (!s.fellback && !(t[0] > 0.0 && !bad(t[0]))) {
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] = sum_partials(ws.cpart + k * kRedBlocks, gridDim.x);
+    const bool fb0 = s.fb_snap != 0;
+    const bool fb = fb0 || !(t[0] > 0.0 && !bad(t[0]));
+    const bool rs = s.rs_snap != 0 || fb != fb0;
+    double num, beta;
+    if (fb) {
+        num = t[2];
+        beta = rs ? 0.0 : num / s.rr_prev;
+    } else {
+        num = t[0];
+        beta = -s.alpha * t[1] / s.rr_prev;
+    }
+    const bool stop = bad(beta) || bad(num);
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (fb && !fb0) {
             s.fellback = 1;
             s.fb_iter = s.iter;
-            s.restart = 1;
         }
-        double num, beta;
-        if (s.fellback) {
-            num = t[2];
-            beta = s.restart ? 0.0 : num / s.rr;
-        } else {
-            num = t[0];
-            beta = -s.alpha * t[1] / s.rr;
-        }
-        if (bad(beta) || bad(num)) {
+        if (stop) {
             s.nonfinite = 1;
             s.done = 1;
         }
@@ -494,17 +519,8 @@ __global__ __launch_bounds__(kThreads) void k_fcg_dots(const float *__restrict__
         s.restart = 0;
         s.net_off = s.done || s.fellback;
     }
-}
-
-// p = z + beta p (or r + beta p after the fall-back).
-__global__ __launch_bounds__(kThreads) void k_fcg_p(const float *__restrict__ z,
-                                                    const float *__restrict__ r,
-                                                    float *__restrict__ p, int64_t n,
-                                                    const CgState *__restrict__ st)
-{
-    if (st->done) return;
-    const double beta = st->beta;
-    const float *src = st->fellback ? r : z;
+    if (stop) return;
+    const float *src = fb ? r : z;
     for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * kThreads)
         p[i] = (float)((double)src[i] + beta * p[i]);
@@ -734,7 +750,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     Workspace ws;
     ws.partials = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
     ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
-    ws.cpart = (double *)buf.alloc(sizeof(double) * 2 * kRedBlocks);
+    ws.cpart = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
     ws.st = (CgState *)buf.alloc(sizeof(CgState));
     ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)maxit + 1));
     // back-projection strategy and its scratch, fixed for the whole solve
@@ -824,7 +840,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         frags_ready = true;
         if (e) return e;
         hipLaunchKernelGGL(k_fcg_dots, dim3(eb), dim3(kThreads), 0, s, z, r, q, n, ws);
-        hipLaunchKernelGGL(k_fcg_p, dim3(eb), dim3(kThreads), 0, s, z, r, p, n, ws.st);
+        hipLaunchKernelGGL(k_fcg_p, dim3(eb), dim3(kThreads), 0, s, z, r, p, n, ws);
         return hip_fail(hipGetLastError(), "fcg start");
     };
     if (fcg) {
@@ -875,7 +891,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
                                     false, &ws.st->net_off);
             if (e) return e;
             hipLaunchKernelGGL(k_fcg_dots, dim3(eb), dim3(kThreads), 0, s, z, r, q, n, ws);
-            hipLaunchKernelGGL(k_fcg_p, dim3(eb), dim3(kThreads), 0, s, z, r, p, n, ws.st);
+            hipLaunchKernelGGL(k_fcg_p, dim3(eb), dim3(kThreads), 0, s, z, r, p, n, ws);
         }
         return hip_fail(hipGetLastError(), "cg iteration launch");
     };
@@ -1037,7 +1053,7 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
         c.img = (float *)buf.alloc(sizeof(float) * c.npix);
         c.ws.partials = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
         c.ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
-        c.ws.cpart = (double *)buf.alloc(sizeof(double) * 2 * kRedBlocks);
+        c.ws.cpart = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
         c.ws.st = states + k;
         c.ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)c.maxit + 1));
         if (!c.b || !c.r || !c.p || !c.q || !c.img || !c.ws.partials || !c.ws.counter || !c.ws.cpart || !c.ws.hist)
