@@ -125,11 +125,9 @@ __global__ __launch_bounds__(kThreads) void k_batch_absmax(const SysDev *__restr
     if (threadIdx.x == 0) ymax[blockIdx.x] = m;
 }
 
-__global__ __launch_bounds__(kThreads) void k_batch_backproject(const SysDev *__restrict__ sys, int32_t nsys,
-                                                                Operands ops, int64_t nitems,
-                                                                const uint32_t *__restrict__ ymax,
-                                                                unsigned long long *q,
-                                                                unsigned *__restrict__ spill)
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_backproject(
+    const SysDev *__restrict__ sys, int32_t nsys, Operands ops, int64_t nitems, const uint32_t *__restrict__ ymax,
+    unsigned long long *q, unsigned *__restrict__ spill)
 {
     extern __shared__ unsigned long long bins[];
     __shared__ BlockedShared sh;

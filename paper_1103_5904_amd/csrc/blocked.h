@@ -40,13 +40,89 @@ __device__ inline uint32_t view_absmax_part(const ViewDev &v, int part, const fl
     return r;
 }
 
-// Shared-memory scratch of one item besides the bins: the pixel rectangles
-// of up to kViewChunk of the owner's views, computed together so that the
-// wavefronts then run through all of them without workgroup barriers.
-constexpr int kViewChunk = 16;
+// Shared-memory scratch of one item besides the bins: the footprints of up
+// to kViewChunk of the owner's views, computed together so that the
+// wavefronts then run through all of them without workgroup barriers.  A
+// footprint is the bounding rectangle of the block's projection and, when
+// the rectangle has at most kRowsMax rows, one column interval per row
+// (the projection of a box is convex, so the pixels of one row whose rays
+// meet it form an interval) with the running pixel count.
+constexpr int kViewChunk = 8;
+constexpr int kRowsMax = 64;
 struct BlockedShared {
-    int rect[kViewChunk][4];  // c0, c1, r0, r1 (c0 > c1: the block is not seen)
+    int rect[kViewChunk][4];             // c0, c1, r0, r1 (c0 > c1: the block is not seen)
+    int rows[kViewChunk];                // 1: walk the row intervals, 0: the whole rectangle
+    uint16_t cs[kViewChunk][kRowsMax];   // first column of each row's interval
+    int32_t pre[kViewChunk][kRowsMax + 1];  // pixels in the rows before (pre[H]: all)
 };
+
+// Column interval [cs, ce] of image row `row` of view v whose rays can meet
+// the box [o + lo, o + hi].  The rays of the row, d = e + x u with
+// e = w + y v, fill the plane through the observer with normal n = e x u,
+// and the box meets that plane in a convex polygon whose corners lie on the
+// box's edges; a point p of the plane lies on the ray of
+// x = -(p . (e x n)) / (p . (u x n)) (any basis, orthonormal or not), so the
+// polygon's corners bound the row's columns.  FP32: the caller pads the box
+// by far more than its rounding, and the interval is widened by one pixel
+// each side and clipped to [c0, c1]; ce < cs: none.  Returns false if a
+// corner is not in front of the observer (the caller then keeps the whole
+// row).
+__device__ inline bool row_interval(const ViewDev &v, int row, const float (&lo)[3], const float (&hi)[3],
+                                    int c0, int c1, int &cs, int &ce)
+{
+    const float y = (float)(((double)row - v.cp[1]) * v.cd[1]);
+    const float w[3] = {(float)v.w[0], (float)v.w[1], (float)v.w[2]};
+    const float u[3] = {(float)v.u[0], (float)v.u[1], (float)v.u[2]};
+    const float vv[3] = {(float)v.v[0], (float)v.v[1], (float)v.v[2]};
+    const float e[3] = {w[0] + y * vv[0], w[1] + y * vv[1], w[2] + y * vv[2]};
+    const float n[3] = {e[1] * u[2] - e[2] * u[1], e[2] * u[0] - e[0] * u[2], e[0] * u[1] - e[1] * u[0]};
+    const float an[3] = {u[1] * n[2] - u[2] * n[1], u[2] * n[0] - u[0] * n[2], u[0] * n[1] - u[1] * n[0]};
+    const float bn[3] = {e[1] * n[2] - e[2] * n[1], e[2] * n[0] - e[0] * n[2], e[0] * n[1] - e[1] * n[0]};
+    // a corner's S = p.n, W = p.(u x n), U = -p.(e x n) as sums of one
+    // low-or-high term per axis
+    float ts[2][3], tw[2][3], tu[2][3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        ts[0][a] = lo[a] * n[a];
+        ts[1][a] = hi[a] * n[a];
+        tw[0][a] = lo[a] * an[a];
+        tw[1][a] = hi[a] * an[a];
+        tu[0][a] = -(lo[a] * bn[a]);
+        tu[1][a] = -(hi[a] * bn[a]);
+    }
+    auto corner = [&](int k, float (&t)[2][3]) { return t[k & 1][0] + t[(k >> 1) & 1][1] + t[k >> 2][2]; };
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (!(corner(k, tw) > 0.0f)) return false;
+    float xmin = 3.0e38f, xmax = -3.0e38f;
+    // the 12 edges: corner k without bit b to corner k | b
+#pragma unroll
+    for (int ed = 0; ed < 12; ++ed) {
+        const int b = 1 << (ed >> 2), q = ed & 3;
+        const int k = b == 1 ? q << 1 : (b == 2 ? (q & 1) | ((q & 2) << 1) : q), l = k | b;
+        const float sk = corner(k, ts), sl = corner(l, ts);
+        if (sk > 0.0f ? sl > 0.0f : (sk < 0.0f && sl < 0.0f)) continue;  // no crossing
+        const float uk = corner(k, tu), ul = corner(l, tu), wk = corner(k, tw), wl = corner(l, tw);
+        if (sk == sl) {  // both zero: the edge lies in the plane
+            const float xa = uk / wk, xb = ul / wl;
+            xmin = fminf(xmin, fminf(xa, xb));
+            xmax = fmaxf(xmax, fmaxf(xa, xb));
+        } else {  // the crossing at t = sk / (sk - sl) along the edge
+            const float x = (sk * ul - sl * uk) / (sk * wl - sl * wk);
+            xmin = fminf(xmin, x);
+            xmax = fmaxf(xmax, x);
+        }
+    }
+    if (!(xmin <= xmax)) {
+        cs = c0;
+        ce = c0 - 1;
+        return true;
+    }
+    const double ca = v.cp[0] + (double)xmin / v.cd[0], cb = v.cp[0] + (double)xmax / v.cd[0];
+    cs = (int)fmax(floor(fmin(ca, cb)) - 1.0, (double)c0);
+    ce = (int)fmin(ceil(fmax(ca, cb)) + 1.0, (double)c1);
+    return true;
+}
 
 // One owner item of the blocked P^T: (frame, block, split) from the item
 // index, every ray of the owner's views that can cross the block walked
@@ -159,7 +235,43 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 sh.rect[j][1] = c1;
                 sh.rect[j][2] = r0;
                 sh.rect[j][3] = r1;
+                sh.rows[j] = !bad && c0 <= c1 && r1 - r0 < kRowsMax;
             }
+        }
+        __syncthreads();
+
+        // ---- row intervals: one row per thread, widths first (in pre[row + 1])
+        for (int t = threadIdx.x; t < nch * kRowsMax; t += kThreads) {
+            const int j = t / kRowsMax, rr = t % kRowsMax;
+            const int c0 = sh.rect[j][0], c1 = sh.rect[j][1], r0 = sh.rect[j][2], r1 = sh.rect[j][3];
+            if (!sh.rows[j] || rr > r1 - r0) continue;
+            const ViewDev &v = views[frame_views[v0 + split + (cs + j) * bd.splits]];
+            // the block's box less the observer, padded by 1e-3 of a voxel
+            // plus 1e-5 of the largest coordinate in play: far above the FP32
+            // rounding of the interval (relative 1e-7 of these magnitudes) and
+            // the rays' FP64 set-up, so that every ray the exact set-up finds
+            // inside the block is kept
+            float lo[3], hi[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const double big = fmax(fmax(fabs(g.lo[a]), fabs(g.hi[a])), fabs(v.o[a]));
+                const double pad = 1e-3 * g.delta[a] + 1e-5 * big;
+                lo[a] = (float)((g.lo[a] + (double)blo[a] * g.delta[a] - pad) - v.o[a]);
+                hi[a] = (float)((g.lo[a] + (double)bhi[a] * g.delta[a] + pad) - v.o[a]);
+            }
+            int a0 = c0, a1 = c1;
+            if (!row_interval(v, r0 + rr, lo, hi, c0, c1, a0, a1)) {
+                a0 = c0;
+                a1 = c1;
+            }
+            sh.cs[j][rr] = (uint16_t)a0;
+            sh.pre[j][rr + 1] = a1 >= a0 ? a1 - a0 + 1 : 0;
+        }
+        __syncthreads();
+        if (threadIdx.x < nch && sh.rows[threadIdx.x]) {  // running counts
+            const int j = threadIdx.x, h = sh.rect[j][3] - sh.rect[j][2] + 1;
+            sh.pre[j][0] = 0;
+            for (int rr = 1; rr <= h; ++rr) sh.pre[j][rr] += sh.pre[j][rr - 1];
         }
         __syncthreads();
 
@@ -170,16 +282,25 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
             // the view's gain times the bin scale (a power of two: exact)
             const double vscale = v.gain * (finite ? fx_scale : 1.0);
 
-            // ---- rays of the rectangle, 256 per pass in row-major order (thread
-            // i takes pixel i of each pass: a wavefront walks a run of 64
-            // neighbouring pixels, and only the last pass is ragged, where 16x16
-            // tiles left every pass ragged at the rectangle's edges); each pass
-            // loads the next pass's pixel value so that its latency is hidden by
-            // the walk
-            const int W = c1 - c0 + 1, npx = W * (r1 - r0 + 1), ntile = (npx + kThreads - 1) / kThreads;
-            const int adv_r = kThreads / W, adv_c = kThreads - adv_r * W;  // a pass moves kThreads pixels
+            // ---- rays of the footprint, 256 per pass in row-major order over
+            // the row intervals (or the whole rectangle): thread i takes pixel
+            // i of each pass, so a wavefront walks a run of 64 neighbouring
+            // pixels and only the last pass is ragged; each pass loads the
+            // next pass's pixel value so that its latency is hidden by the walk
+            const bool rows = sh.rows[j] != 0;
+            const int H = r1 - r0 + 1, W = c1 - c0 + 1;
+            const int npx = rows ? sh.pre[j][H] : W * H, ntile = (npx + kThreads - 1) / kThreads;
+            const int adv_r = kThreads / W, adv_c = kThreads - adv_r * W;  // rectangle: a pass moves kThreads pixels
             int lin = threadIdx.x;
-            int col = c0 + lin % W, row = r0 + lin / W;
+            int col, row, rr = 0;
+            if (rows) {
+                while (rr < H - 1 && lin >= sh.pre[j][rr + 1]) ++rr;
+                col = (int)sh.cs[j][rr] + (lin - sh.pre[j][rr]);
+                row = r0 + rr;
+            } else {
+                col = c0 + lin % W;
+                row = r0 + lin / W;
+            }
             bool ok = lin < npx;
             float ynext = 0.0f;
             bool mnext = true;
@@ -193,11 +314,17 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 const bool pok = ok, pm = mnext;
                 const float yv = ynext;
                 lin += kThreads;
-                col += adv_c;
-                row += adv_r;
-                if (col > c1) {
-                    col -= W;
-                    ++row;
+                if (rows) {
+                    while (rr < H - 1 && lin >= sh.pre[j][rr + 1]) ++rr;
+                    col = (int)sh.cs[j][rr] + (lin - sh.pre[j][rr]);
+                    row = r0 + rr;
+                } else {
+                    col += adv_c;
+                    row += adv_r;
+                    if (col > c1) {
+                        col -= W;
+                        ++row;
+                    }
                 }
                 ok = lin < npx;
                 if (ok) {

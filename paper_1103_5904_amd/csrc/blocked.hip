@@ -10,8 +10,14 @@
 // * For every view, the pixels whose rays can cross the block lie in the
 //   bounding rectangle of the block's eight corners projected through the
 //   pinhole (plus one pixel of margin); corners behind the observer widen it
-//   to the whole detector.
-// * The rectangle is walked 256 pixels per pass in row-major order; each
+//   to the whole detector.  Within a rectangle of at most 64 rows, each row
+//   keeps only the column interval whose rays meet the block's box: the
+//   rays of a row fill a plane through the observer, which cuts the box in
+//   a convex polygon, and the polygon's corners on the box's edges bound the
+//   interval (FP32, on a box padded far beyond that rounding, plus one pixel
+//   each side).  A flat block seen edge-on projects to a slanted band that
+//   fills about 60% of its rectangle, and every ray dropped saves a set-up.
+// * The footprint is walked 256 pixels per pass in row-major order; each
 //   lane takes one of those rays, sets it up exactly as P does and walks
 //   only its part inside the block.  The walk's crossing parameters
 //   live on a power-of-two grid on which every sum the walk forms is exact:
@@ -53,7 +59,7 @@ __global__ __launch_bounds__(kThreads) void k_view_absmax(const ViewDev *__restr
 }
 
 template <bool kMapMask, bool kDataMask, bool kObstacle>
-__global__ __launch_bounds__(kThreads) void k_backproject_blocked(
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_backproject_blocked(
     GridDev g, const ViewDev *__restrict__ views, const int32_t *__restrict__ frame_views,
     const int32_t *__restrict__ frame_voff, BlockDev bd, Bundle bun, const float *__restrict__ images,
     const uint8_t *__restrict__ map_mask, const uint8_t *__restrict__ data_mask,

@@ -212,6 +212,43 @@ def test_blocked_shapes(tuning, ora, block, splits):
     _parity_full(tomo, ora, gm, x3, rng.normal(size=g.nrays), strategies=["blocked"])
 
 
+def test_blocked_footprint_rows_drop_no_ray(tuning):
+    """With one owner per block the fixed-point bins sum every voxel exactly,
+    so the blocked P^T cannot depend on the block shape.  Flat blocks seen
+    from the ecliptic walk one column interval per footprint row; 8x8x64
+    blocks there have footprints taller than the row table and walk whole
+    rectangles (and the other way round from the poles).  Any ray an
+    interval dropped would change some voxel: the outputs must agree bit for
+    bit on aligned, close, odd-sized, off-ecliptic and random views."""
+    import torch
+
+    tomo = tuning
+    rng = np.random.default_rng(41)
+    rows, pix = [], []
+    specs = [(ts.observer(lon), (0.0, 0.0, 0.0), (128, 128), 3.2) for lon in (0.0, 45.0, 90.0)]
+    specs += [(ts.observer(20.0, 0.0, 3.0), (0.0, 0.0, 0.0), (97, 61), 3.0)]
+    specs += [(ts.observer(rng.uniform(0, 360), lat), (0.0, 0.0, 0.0), (120, 100), 3.2) for lat in (30.0, 60.0, 89.0)]
+    for _ in range(3):
+        d = rng.normal(size=3)
+        specs.append((d / np.linalg.norm(d) * rng.uniform(2.5, 40.0), tuple(rng.uniform(-0.3, 0.3, 3)),
+                      (int(rng.integers(40, 160)), int(rng.integers(40, 160))), rng.uniform(1.0, 5.0)))
+    for obs, target, npix, fov in specs:
+        r, p = ts.pinhole_view(np.asarray(obs, dtype=np.float64), target=target, npix=npix, fov=fov)
+        rows.append(r)
+        pix.append(p)
+    g = ts.Geometry((64, 64, 64), np.full(3, -1.5), np.full(3, 1.5), np.array(rows), np.array(pix, np.int32))
+    dg = tomo.DeviceGeometry(g)
+    y = torch.as_tensor(rng.normal(size=g.nrays).astype(np.float32)).cuda()
+    outs = {}
+    for block in ((8, 8, 64), (64, 32, 2), (32, 32, 4), (16, 16, 16), (64, 8, 16)):
+        tomo.set_tuning(bp_block=block, bp_splits=1)
+        outs[block] = tomo.backproject(dg, y, strategy=tomo.BP_BLOCKED).clone()
+    ref = outs[(8, 8, 64)]
+    assert float(ref.abs().max()) > 0
+    for block, out in outs.items():
+        assert torch.equal(out, ref), block
+
+
 @pytest.mark.parametrize("block", [(4, 4, 4), (5, 3, 7)])
 def test_blocked_one_hot_rays_match_the_walk(tuning, block):
     """P^T of a one-hot image through the blocked strategy is that ray's
