@@ -48,7 +48,7 @@ HBM_PEAK_GBS = 8000.0
 # sources and default launch shapes (api.hip) they were taken on: sha256 over the listed files, first
 # 16 hex digits.
 TRAFFIC = {
-    "k_backproject_blocked": (156.6e6, "4cdfd39122ee1b3c",
+    "k_backproject_blocked": (158.4e6, "5a4d3aee7b9b894b",
                               ["blocked.h", "blocked.hip", "walk.h", "common.h", "api.hip"]),
     "k_project": (264.4e6, "29359e89484eb5d3", ["siddon.hip", "walk.h", "common.h", "api.hip"]),
 }

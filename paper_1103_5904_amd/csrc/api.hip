@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -205,6 +206,27 @@ static int build_plan(const tomo_geometry *g, int64_t npix, Plan &p)
     p.npix = npix;
     p.max_steps = c.nx + c.ny + c.nz + 3;
     p.size_class = size_class_of(g, npix);
+    // The blocked P^T's footprint row intervals pay where footprints span
+    // several passes of pixels, i.e. where pixels are finer than voxels at the
+    // cube: the median over the views of voxel size / pixel size at the cube's
+    // centre (measured: 1.8 and up faster with intervals, 0.94 and below
+    // faster with whole rectangles).
+    {
+        std::vector<double> ratio((size_t)g->nviews);
+        const double vox = (gd.delta[0] + gd.delta[1] + gd.delta[2]) / 3.0;
+        for (int k = 0; k < g->nviews; ++k) {
+            const tomo_view &v = g->views[k];
+            double d2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                const double t = 0.5 * (gd.lo[a] + gd.hi[a]) - v.obs[a];
+                d2 += t * t;
+            }
+            const double px = sqrt(fabs(v.cdelt[0] * v.cdelt[1])) * sqrt(d2);
+            ratio[(size_t)k] = px > 0.0 ? vox / px : 0.0;
+        }
+        std::nth_element(ratio.begin(), ratio.begin() + ratio.size() / 2, ratio.end());
+        p.bp_rows = ratio[ratio.size() / 2] >= 1.4;
+    }
     hipError_t e = hipMalloc((void **)&p.views_d, sizeof(ViewDev) * hv.size());
     if (e != hipSuccess) return set_error(TOMO_ENOMEM, "view table allocation: %s", hipGetErrorString(e));
     e = hipMemcpy(p.views_d, hv.data(), sizeof(ViewDev) * hv.size(), hipMemcpyHostToDevice);

@@ -125,9 +125,11 @@ __global__ __launch_bounds__(kThreads) void k_batch_absmax(const SysDev *__restr
     if (threadIdx.x == 0) ymax[blockIdx.x] = m;
 }
 
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_backproject(
-    const SysDev *__restrict__ sys, int32_t nsys, Operands ops, int64_t nitems, const uint32_t *__restrict__ ymax,
-    unsigned long long *q, unsigned *__restrict__ spill)
+__global__ __launch_bounds__(kThreads) void k_batch_backproject(const SysDev *__restrict__ sys, int32_t nsys,
+                                                                Operands ops, int64_t nitems,
+                                                                const uint32_t *__restrict__ ymax,
+                                                                unsigned long long *q,
+                                                                unsigned *__restrict__ spill)
 {
     extern __shared__ unsigned long long bins[];
     __shared__ BlockedShared sh;
@@ -147,7 +149,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         const uint32_t *ym = ymax + (int64_t)sd.view_begin * kYmaxParts;
         const bool mm = ops.map && sd.map_mask, dm = sd.data_mask != nullptr;
 #define TOMO_ITEM(M, D, O)                                                                                 \
-    blocked_item<M, D, O>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, li, ops.src[k],         \
+    blocked_item<M, D, O, false>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, li, ops.src[k],  \
                           sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh)
         if (sd.grid.has_sph) {  // the obstacle's variant: one code path for every mask combination
             if (mm && dm) TOMO_ITEM(true, true, true);

@@ -44,16 +44,17 @@ __device__ inline uint32_t view_absmax_part(const ViewDev &v, int part, const fl
 // to kViewChunk of the owner's views, computed together so that the
 // wavefronts then run through all of them without workgroup barriers.  A
 // footprint is the bounding rectangle of the block's projection and, when
-// the rectangle has at most kRowsMax rows, one column interval per row
-// (the projection of a box is convex, so the pixels of one row whose rays
-// meet it form an interval) with the running pixel count.
-constexpr int kViewChunk = 8;
+// the rectangle has at most kRowsMax rows, one column interval per row (the
+// projection of a box is convex, so the pixels of one row whose rays meet it
+// form an interval) with the running pixel count.
+constexpr int kViewChunk = 16;     // views per chunk walking whole rectangles
+constexpr int kViewChunkRows = 8;  // views per chunk with row intervals
 constexpr int kRowsMax = 64;
 struct BlockedShared {
-    int rect[kViewChunk][4];             // c0, c1, r0, r1 (c0 > c1: the block is not seen)
-    int rows[kViewChunk];                // 1: walk the row intervals, 0: the whole rectangle
-    uint16_t cs[kViewChunk][kRowsMax];   // first column of each row's interval
-    int32_t pre[kViewChunk][kRowsMax + 1];  // pixels in the rows before (pre[H]: all)
+    int rect[kViewChunk][4];                    // c0, c1, r0, r1 (c0 > c1: the block is not seen)
+    int rows[kViewChunk];                       // 1: walk the row intervals, 0: the whole rectangle
+    uint16_t cs[kViewChunkRows][kRowsMax];      // first column of each row's interval
+    int32_t pre[kViewChunkRows][kRowsMax + 1];  // pixels in the rows before (pre[H]: all)
 };
 
 // Column interval [cs, ce] of image row `row` of view v whose rays can meet
@@ -128,7 +129,7 @@ __device__ inline bool row_interval(const ViewDev &v, int row, const float (&lo)
 // index, every ray of the owner's views that can cross the block walked
 // inside it, and the block written once.  bins: nbins 64-bit LDS words.
 // Called by all threads of the workgroup.
-template <bool kMapMask, bool kDataMask, bool kObstacle>
+template <bool kMapMask, bool kDataMask, bool kObstacle, bool kRows>
 __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict__ views,
                                     const int32_t *__restrict__ frame_views,
                                     const int32_t *__restrict__ frame_voff, const BlockDev &bd,
@@ -186,12 +187,13 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
     unsigned spills = 0u;
 
     const int nvi = v1 - v0 > split ? (v1 - v0 - split + bd.splits - 1) / bd.splits : 0;  // owner's views
-    for (int cs = 0; cs < nvi; cs += kViewChunk) {
-        const int nch = min(kViewChunk, nvi - cs);
+    constexpr int kChunk = kRows ? kViewChunkRows : kViewChunk;
+    for (int cs = 0; cs < nvi; cs += kChunk) {
+        const int nch = min(kChunk, nvi - cs);
         // ---- footprints: thread 8 j + c projects corner c of the chunk's
         // view j; the 8 lanes of a view reduce with shuffles
         __syncthreads();  // the previous chunk's rectangles are no longer in use
-        if (threadIdx.x < 8 * kViewChunk) {
+        if (threadIdx.x < 8 * kChunk) {
             const int j = threadIdx.x >> 3, c = threadIdx.x & 7;
             const bool live = j < nch;
             const ViewDev &v = views[frame_views[v0 + split + (cs + (live ? j : 0)) * bd.splits]];
@@ -235,45 +237,47 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 sh.rect[j][1] = c1;
                 sh.rect[j][2] = r0;
                 sh.rect[j][3] = r1;
-                sh.rows[j] = !bad && c0 <= c1 && r1 - r0 < kRowsMax;
+                sh.rows[j] = kRows && !bad && c0 <= c1 && r1 - r0 < kRowsMax;
             }
         }
         __syncthreads();
 
-        // ---- row intervals: one row per thread, widths first (in pre[row + 1])
-        for (int t = threadIdx.x; t < nch * kRowsMax; t += kThreads) {
-            const int j = t / kRowsMax, rr = t % kRowsMax;
-            const int c0 = sh.rect[j][0], c1 = sh.rect[j][1], r0 = sh.rect[j][2], r1 = sh.rect[j][3];
-            if (!sh.rows[j] || rr > r1 - r0) continue;
-            const ViewDev &v = views[frame_views[v0 + split + (cs + j) * bd.splits]];
-            // the block's box less the observer, padded by 1e-3 of a voxel
-            // plus 1e-5 of the largest coordinate in play: far above the FP32
-            // rounding of the interval (relative 1e-7 of these magnitudes) and
-            // the rays' FP64 set-up, so that every ray the exact set-up finds
-            // inside the block is kept
-            float lo[3], hi[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                const double big = fmax(fmax(fabs(g.lo[a]), fabs(g.hi[a])), fabs(v.o[a]));
-                const double pad = 1e-3 * g.delta[a] + 1e-5 * big;
-                lo[a] = (float)((g.lo[a] + (double)blo[a] * g.delta[a] - pad) - v.o[a]);
-                hi[a] = (float)((g.lo[a] + (double)bhi[a] * g.delta[a] + pad) - v.o[a]);
+        if constexpr (kRows) {
+            // ---- row intervals: one row per thread, widths first (in pre[row + 1])
+            for (int t = threadIdx.x; t < nch * kRowsMax; t += kThreads) {
+                const int j = t / kRowsMax, rr = t % kRowsMax;
+                const int c0 = sh.rect[j][0], c1 = sh.rect[j][1], r0 = sh.rect[j][2], r1 = sh.rect[j][3];
+                if (!sh.rows[j] || rr > r1 - r0) continue;
+                const ViewDev &v = views[frame_views[v0 + split + (cs + j) * bd.splits]];
+                // the block's box less the observer, padded by 1e-3 of a voxel
+                // plus 1e-5 of the largest coordinate in play: far above the FP32
+                // rounding of the interval (relative 1e-7 of these magnitudes) and
+                // the rays' FP64 set-up, so that every ray the exact set-up finds
+                // inside the block is kept
+                float lo[3], hi[3];
+    #pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const double big = fmax(fmax(fabs(g.lo[a]), fabs(g.hi[a])), fabs(v.o[a]));
+                    const double pad = 1e-3 * g.delta[a] + 1e-5 * big;
+                    lo[a] = (float)((g.lo[a] + (double)blo[a] * g.delta[a] - pad) - v.o[a]);
+                    hi[a] = (float)((g.lo[a] + (double)bhi[a] * g.delta[a] + pad) - v.o[a]);
+                }
+                int a0 = c0, a1 = c1;
+                if (!row_interval(v, r0 + rr, lo, hi, c0, c1, a0, a1)) {
+                    a0 = c0;
+                    a1 = c1;
+                }
+                sh.cs[j][rr] = (uint16_t)a0;
+                sh.pre[j][rr + 1] = a1 >= a0 ? a1 - a0 + 1 : 0;
             }
-            int a0 = c0, a1 = c1;
-            if (!row_interval(v, r0 + rr, lo, hi, c0, c1, a0, a1)) {
-                a0 = c0;
-                a1 = c1;
+            __syncthreads();
+            if (threadIdx.x < nch && sh.rows[threadIdx.x]) {  // running counts
+                const int j = threadIdx.x, h = sh.rect[j][3] - sh.rect[j][2] + 1;
+                sh.pre[j][0] = 0;
+                for (int rr = 1; rr <= h; ++rr) sh.pre[j][rr] += sh.pre[j][rr - 1];
             }
-            sh.cs[j][rr] = (uint16_t)a0;
-            sh.pre[j][rr + 1] = a1 >= a0 ? a1 - a0 + 1 : 0;
+            __syncthreads();
         }
-        __syncthreads();
-        if (threadIdx.x < nch && sh.rows[threadIdx.x]) {  // running counts
-            const int j = threadIdx.x, h = sh.rect[j][3] - sh.rect[j][2] + 1;
-            sh.pre[j][0] = 0;
-            for (int rr = 1; rr <= h; ++rr) sh.pre[j][rr] += sh.pre[j][rr - 1];
-        }
-        __syncthreads();
 
         for (int j = 0; j < nch; ++j) {
             const ViewDev &v = views[frame_views[v0 + split + (cs + j) * bd.splits]];
@@ -287,7 +291,7 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
             // i of each pass, so a wavefront walks a run of 64 neighbouring
             // pixels and only the last pass is ragged; each pass loads the
             // next pass's pixel value so that its latency is hidden by the walk
-            const bool rows = sh.rows[j] != 0;
+            const bool rows = kRows && sh.rows[j] != 0;
             const int H = r1 - r0 + 1, W = c1 - c0 + 1;
             const int npx = rows ? sh.pre[j][H] : W * H, ntile = (npx + kThreads - 1) / kThreads;
             const int adv_r = kThreads / W, adv_c = kThreads - adv_r * W;  // rectangle: a pass moves kThreads pixels

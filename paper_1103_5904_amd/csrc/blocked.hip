@@ -58,7 +58,7 @@ __global__ __launch_bounds__(kThreads) void k_view_absmax(const ViewDev *__restr
     if (threadIdx.x == 0) ymax[blockIdx.x] = m;
 }
 
-template <bool kMapMask, bool kDataMask, bool kObstacle>
+template <bool kMapMask, bool kDataMask, bool kObstacle, bool kRows>
 __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_backproject_blocked(
     GridDev g, const ViewDev *__restrict__ views, const int32_t *__restrict__ frame_views,
     const int32_t *__restrict__ frame_voff, BlockDev bd, Bundle bun, const float *__restrict__ images,
@@ -72,7 +72,7 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
     const int64_t nitems = (int64_t)bd.nb[0] * bd.nb[1] * bd.nb[2] * g.nframes * bd.splits;
     const int64_t item = bun.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     if (item >= nitems) return;
-    blocked_item<kMapMask, kDataMask, kObstacle>(g, views, frame_views, frame_voff, bd, item, images, map_mask,
+    blocked_item<kMapMask, kDataMask, kObstacle, kRows>(g, views, frame_views, frame_voff, bd, item, images, map_mask,
                                                  data_mask, ymax_parts, out, accumulate, spill, bins, sh);
 }
 
@@ -155,10 +155,15 @@ int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const floa
     const size_t lds = sizeof(unsigned long long) * ((size_t)bs.b[0] * bs.b[1] * bs.b[2] + 1);  // + dummy bin
     float *dst = bs.splits == 1 ? cube : part;
     const int acc = accumulate ? 1 : 0;
-#define TOMO_LAUNCH_BK3(M, D, O)                                                                           \
-    hipLaunchKernelGGL((k_backproject_blocked<M, D, O>), dim3((unsigned)bs.items), dim3(kThreads), lds, s, \
-                       p.grid, p.views_d, p.frame_views_d, p.frame_voff_d, bd, bun, images,               \
+#define TOMO_LAUNCH_BK4(M, D, O, R)                                                                           \
+    hipLaunchKernelGGL((k_backproject_blocked<M, D, O, R>), dim3((unsigned)bs.items), dim3(kThreads), lds, s, \
+                       p.grid, p.views_d, p.frame_views_d, p.frame_voff_d, bd, bun, images,                  \
                        g->map_mask, g->data_mask, ymax, dst, acc, done_flag, p.spill_d)
+#define TOMO_LAUNCH_BK3(M, D, O)                       \
+    do {                                               \
+        if (p.bp_rows) TOMO_LAUNCH_BK4(M, D, O, true); \
+        else TOMO_LAUNCH_BK4(M, D, O, false);          \
+    } while (0)
 #define TOMO_LAUNCH_BK(M, D)                                                                            \
     do {                                                                                                \
         if (p.grid.has_sph) TOMO_LAUNCH_BK3(M, D, true);                                                \
@@ -170,6 +175,7 @@ int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const floa
     else TOMO_LAUNCH_BK(false, false);
 #undef TOMO_LAUNCH_BK
 #undef TOMO_LAUNCH_BK3
+#undef TOMO_LAUNCH_BK4
     int rc = hip_fail(hipGetLastError(), "blocked back-projection kernel launch");
     if (rc || bs.splits == 1) return rc;
     const int64_t total = p.grid.nvox * p.grid.nframes;

@@ -139,6 +139,7 @@ struct Plan {
     int32_t *frame_views_d = nullptr;  // device [nviews]: view indices grouped by frame
     int32_t *frame_voff_d = nullptr;   // device [nframes + 1]: offsets into frame_views_d
     int32_t min_frame_views = 0;       // fewest views any frame has
+    bool bp_rows = false;              // blocked P^T walks footprint row intervals (pixels finer than voxels)
     uint64_t size_class = 0;           // key of the autotuner's cache (size_class_of)
     Plan() = default;
     Plan(const Plan &) = delete;
