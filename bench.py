@@ -48,9 +48,9 @@ HBM_PEAK_GBS = 8000.0
 # sources and default launch shapes (api.hip) they were taken on: sha256 over the listed files, first
 # 16 hex digits.
 TRAFFIC = {
-    "k_backproject_blocked": (158.4e6, "5a4d3aee7b9b894b",
+    "k_backproject_blocked": (158.4e6, "09199c508949126a",
                               ["blocked.h", "blocked.hip", "walk.h", "common.h", "api.hip"]),
-    "k_project": (264.4e6, "29359e89484eb5d3", ["siddon.hip", "walk.h", "common.h", "api.hip"]),
+    "k_project": (264.4e6, "870940f8054ca25a", ["siddon.hip", "walk.h", "common.h", "api.hip"]),
 }
 
 

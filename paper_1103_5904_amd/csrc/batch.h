@@ -59,5 +59,6 @@ struct tomo_batch_s {
     unsigned *spill = nullptr;
     size_t lds_bytes = 0;
     unsigned grid_p = 0, grid_b = 0;
+    bool rows = false;  // P^T walks footprint row intervals (most systems' plans ask for them)
     ~tomo_batch_s();
 };

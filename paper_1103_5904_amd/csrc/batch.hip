@@ -125,11 +125,10 @@ __global__ __launch_bounds__(kThreads) void k_batch_absmax(const SysDev *__restr
     if (threadIdx.x == 0) ymax[blockIdx.x] = m;
 }
 
-__global__ __launch_bounds__(kThreads) void k_batch_backproject(const SysDev *__restrict__ sys, int32_t nsys,
-                                                                Operands ops, int64_t nitems,
-                                                                const uint32_t *__restrict__ ymax,
-                                                                unsigned long long *q,
-                                                                unsigned *__restrict__ spill)
+template <bool kRows>
+__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_backproject(
+    const SysDev *__restrict__ sys, int32_t nsys, Operands ops, int64_t nitems, const uint32_t *__restrict__ ymax,
+    unsigned long long *q, unsigned *__restrict__ spill)
 {
     extern __shared__ unsigned long long bins[];
     __shared__ BlockedShared sh;
@@ -149,7 +148,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_backproject(const SysDev *__
         const uint32_t *ym = ymax + (int64_t)sd.view_begin * kYmaxParts;
         const bool mm = ops.map && sd.map_mask, dm = sd.data_mask != nullptr;
 #define TOMO_ITEM(M, D, O)                                                                                 \
-    blocked_item<M, D, O, false>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, li, ops.src[k],  \
+    blocked_item<M, D, O, kRows>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, li, ops.src[k],  \
                           sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh)
         if (sd.grid.has_sph) {  // the obstacle's variant: one code path for every mask combination
             if (mm && dm) TOMO_ITEM(true, true, true);
@@ -222,8 +221,12 @@ int batch_backproject_ops(tomo_batch b, const Operands &ops, hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_absmax, dim3((unsigned)(b->nviews * kYmaxParts)), dim3(kThreads), 0, s,
                        b->sys_d, b->nsys, ops, b->ymax);
-    hipLaunchKernelGGL(k_batch_backproject, dim3(b->grid_b), dim3(kThreads), b->lds_bytes, s, b->sys_d,
-                       b->nsys, ops, b->nitems, b->ymax, b->q + (kQueues + 1), b->spill);
+    if (b->rows)
+        hipLaunchKernelGGL(k_batch_backproject<true>, dim3(b->grid_b), dim3(kThreads), b->lds_bytes, s, b->sys_d,
+                           b->nsys, ops, b->nitems, b->ymax, b->q + (kQueues + 1), b->spill);
+    else
+        hipLaunchKernelGGL(k_batch_backproject<false>, dim3(b->grid_b), dim3(kThreads), b->lds_bytes, s, b->sys_d,
+                           b->nsys, ops, b->nitems, b->ymax, b->q + (kQueues + 1), b->spill);
     bool owners = false;
     for (const auto &sd : b->sys_h) owners = owners || sd.bd.splits > 1;
     if (owners) {
@@ -251,6 +254,7 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
     (void)hipGetDevice(&b->device);
     b->nsys = nsystems;
     int64_t part_floats = 0;
+    int nrows = 0;  // systems whose plans ask for footprint row intervals
     for (int k = 0; k < nsystems; ++k) {
         int st = TOMO_OK;
         PlanRef p = get_plan(&systems[k], &st);
@@ -287,6 +291,7 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
         if (bs.splits > 1) part_floats += (int64_t)bs.splits * sd.ntot;
         const size_t lds = sizeof(unsigned long long) * ((size_t)bs.b[0] * bs.b[1] * bs.b[2] + 1);  // + dummy bin
         b->lds_bytes = lds > b->lds_bytes ? lds : b->lds_bytes;
+        nrows += p->bp_rows ? 1 : 0;
         b->plans.push_back(p);
         b->geoms.push_back(systems[k]);
         b->geoms.back().obstacle = nullptr;  // captured in the plan's grid
@@ -323,7 +328,11 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
     int cus = 0, per_p = 0, per_b = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_p, k_batch_project, kThreads, 0);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_b, k_batch_backproject, kThreads, b->lds_bytes);
+    b->rows = 2 * nrows > (int)b->sys_h.size();
+    if (b->rows)
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_b, k_batch_backproject<true>, kThreads, b->lds_bytes);
+    else
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_b, k_batch_backproject<false>, kThreads, b->lds_bytes);
     cus = cus > 0 ? cus : 256;
     per_p = per_p > 0 ? per_p : 1;
     per_b = per_b > 0 ? per_b : 1;
