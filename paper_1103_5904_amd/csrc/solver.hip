@@ -26,6 +26,8 @@
 namespace tomo {
 
 constexpr int kRedBlocks = 1024;  // workgroups of every reducing vector kernel (at most)
+constexpr int kIterBlocks = 2048; // workgroups of the fence-free CG passes (at most): their latency-bound
+                                  // loops want more waves, and their partials cost no fences
 
 struct CgState {
     double rr;        // r.r (plain CG) or z.r (flexible CG) of the current iterate
@@ -55,7 +57,8 @@ struct CgState {
 struct Workspace {
     double *partials;   // [kRedBlocks][4]
     unsigned *counter;  // last-block detection
-    double *cpart;      // [4][kRedBlocks]: per-workgroup partials summed by the next kernel
+    double *cpart;      // [4][kIterBlocks]: per-workgroup partials summed by the next kernel
+    int32_t nq;         // workgroups of k_cg_q (the partials of p.q)
     CgState *st;
     double *hist;       // [max_iter + 1]
 };
@@ -237,7 +240,7 @@ __device__ inline double sum_partials(const double *__restrict__ part, int nb)
 {
     __shared__ double lds[4];
     __shared__ double tot;
-    constexpr int kPer = kRedBlocks / kThreads;
+    constexpr int kPer = kIterBlocks / kThreads;
     double v[kPer];
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
@@ -280,7 +283,7 @@ __device__ inline bool stopped(const CgState *st)
 __device__ inline bool take_alpha(const Workspace &ws, double &alpha)
 {
     CgState &s = *ws.st;
-    const double tpq = sum_partials(ws.cpart, gridDim.x);
+    const double tpq = sum_partials(ws.cpart, ws.nq);
     const double rr = s.rr;
     alpha = rr / tpq;
     const bool ok = !bad(alpha) && tpq > 0.0;
@@ -368,7 +371,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_xr(float *__restrict__ x, float
         q[i] = 0.0f;
         rr += (double)rv * rv;
     }
-    put_partial(rr, ws.cpart + kRedBlocks);
+    put_partial(rr, ws.cpart + kIterBlocks);
 }
 
 // rr_new = r.r from k_cg_xr's partials; beta = rr_new / rr; p = r + beta p.
@@ -381,7 +384,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_p(const float *__restrict__ r,
 {
     if (stopped(ws.st)) return;
     CgState &s = *ws.st;
-    const double trr = sum_partials(ws.cpart + kRedBlocks, gridDim.x);
+    const double trr = sum_partials(ws.cpart + kIterBlocks, gridDim.x);
     const double beta = trr / s.rr_prev;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         s.beta = beta;
@@ -472,7 +475,7 @@ __global__ __launch_bounds__(kThreads) void k_fcg_dots(const float *__restrict__
         q[i] = 0.0f;
     }
 #pragma unroll
-    for (int k = 0; k < 4; ++k) put_partial(a[k], ws.cpart + k * kRedBlocks);
+    for (int k = 0; k < 4; ++k) put_partial(a[k], ws.cpart + k * kIterBlocks);
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         ws.st->fb_snap = ws.st->fellback;
         ws.st->rs_snap = ws.st->restart;
@@ -492,7 +495,7 @@ __global__ __launch_bounds__(kThreads) void k_fcg_p(const float *__restrict__ z,
     CgState &s = *ws.st;
     double t[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) t[k] = sum_partials(ws.cpart + k * kRedBlocks, gridDim.x);
+    for (int k = 0; k < 4; ++k) t[k] = sum_partials(ws.cpart + k * kIterBlocks, gridDim.x);
     const bool fb0 = s.fb_snap != 0;
     const bool fb = fb0 || !(t[0] > 0.0 && !bad(t[0]));
     const bool rs = s.rs_snap != 0 || fb != fb0;
@@ -588,6 +591,12 @@ static unsigned elem_blocks(int64_t n)
 {
     int64_t nb = (n + kThreads - 1) / kThreads;
     return (unsigned)(nb > kRedBlocks ? kRedBlocks : (nb < 1 ? 1 : nb));
+}
+
+static unsigned iter_blocks(int64_t n)
+{
+    int64_t nb = (n + kThreads - 1) / kThreads;
+    return (unsigned)(nb > kIterBlocks ? kIterBlocks : (nb < 1 ? 1 : nb));
 }
 
 // Height parameters of the weighted prior for this cube (h == NULL: none).
@@ -750,7 +759,8 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     Workspace ws;
     ws.partials = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
     ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
-    ws.cpart = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
+    ws.cpart = (double *)buf.alloc(sizeof(double) * 4 * kIterBlocks);
+    ws.nq = (int32_t)iter_blocks(n);
     ws.st = (CgState *)buf.alloc(sizeof(CgState));
     ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)maxit + 1));
     // back-projection strategy and its scratch, fixed for the whole solve
@@ -881,10 +891,10 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
             evB.push_back(e2);
         }
         if (e) return e;
-        launch_cg_q(hw, eb, s, p, q, g->map_mask, d, lr, lt, ws, hd);
+        launch_cg_q(hw, (unsigned)ws.nq, s, p, q, g->map_mask, d, lr, lt, ws, hd);
         if (!fcg) {
-            hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
-            hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, s, r, p, n, ws);
+            hipLaunchKernelGGL(k_cg_xr, dim3(ws.nq), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
+            hipLaunchKernelGGL(k_cg_p, dim3(ws.nq), dim3(kThreads), 0, s, r, p, n, ws);
         } else {
             hipLaunchKernelGGL(k_fcg_xr, dim3(eb), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
             e = convnet_forward_dev(g->cube, prm->precond, r, z, &ws.st->res2, g->map_mask, netws, s,
@@ -1053,7 +1063,8 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
         c.img = (float *)buf.alloc(sizeof(float) * c.npix);
         c.ws.partials = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
         c.ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
-        c.ws.cpart = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
+        c.ws.cpart = (double *)buf.alloc(sizeof(double) * 4 * kIterBlocks);
+        c.ws.nq = (int32_t)iter_blocks(c.n);
         c.ws.st = states + k;
         c.ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)c.maxit + 1));
         if (!c.b || !c.r || !c.p || !c.q || !c.img || !c.ws.partials || !c.ws.counter || !c.ws.cpart || !c.ws.hist)
@@ -1183,7 +1194,7 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
         for (int k = 0; k < ns; ++k) {
             Sys &c = sy[(size_t)k];
             if (c.skip) continue;
-            const unsigned eb = elem_blocks(c.n);
+            const unsigned eb = (unsigned)c.ws.nq;
             launch_cg_q(c.hw, eb, st, c.p, c.q, c.mm, c.d, c.lr, c.lt, c.ws, c.hd);
             hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, st, x_d[k], c.r, c.p, c.q, c.n, c.ws);
             hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, st, c.r, c.p, c.n, c.ws);
