@@ -204,7 +204,20 @@ int tomo_trace_ray(const tomo_geometry *g, int32_t view, int32_t col,
  *     back-projection owns (each 1..64, product <= 8192 64-bit LDS bins).
  *   bp_splits: owners per block in the blocked back-projection, the block's
  *     views dealt round-robin (1..64; 0 = chosen from the block count so
- *     that the launch has about 2048 workgroups, at most 8 owners).
+ *     that the launch has about 2048 x 256 / bp_threads workgroups, at most
+ *     8 owners).
+ *   bp_threads: workgroup size of the blocked back-projection (256, 512 or
+ *     1024 lanes).  Larger workgroups own larger blocks for the same
+ *     occupancy, so each ray is set up for fewer blocks.  The block's bins
+ *     (8 bytes per voxel) must fit the workgroup's LDS with the staging of
+ *     its views, or the launch returns TOMO_EINVAL.
+ *   p_layout: cube layout P gathers from: 0 = the caller's x-fastest array;
+ *     k = 2, 3 or 4 = a bricked copy of it, cubes of 2^k voxels a side (the
+ *     bricks in x-fastest order, x fastest inside each), made in
+ *     stream-ordered scratch at every call.  The copy costs one pass over
+ *     the cube; it pays where the cube is far larger than the caches and
+ *     the rays are sparser than the voxels, so that a ray's consecutive
+ *     gathers would otherwise each fetch a cache line of their own.
  * tomo_set_tuning returns TOMO_EINVAL (and changes nothing) for values out
  * of range.  Not synchronised with launches in flight on other threads.
  */
@@ -217,6 +230,8 @@ typedef struct tomo_tuning {
     int32_t bp_default;
     int32_t bp_block[3];
     int32_t bp_splits;
+    int32_t bp_threads;
+    int32_t p_layout;
 } tomo_tuning;
 
 int tomo_get_tuning(tomo_tuning *out);
@@ -301,8 +316,14 @@ int tomo_apply_height_prior(const tomo_cube *cube, const tomo_height *h,
                             const float *x_d, float *out_d, int accumulate,
                             tomo_stream stream);
 
-/* Learned preconditioner network (a 3x3x3 convolution stack, 1 -> 16 -> 16
- * -> 1 channels with ReLU between layers, zero padding 1).  Parameters are a
+/* Learned preconditioner network for the conjugate-gradient inversion: the
+ * paper names preconditioning as the untried remedy for CG's slow
+ * convergence (Sec. "Smooth Temporal Evolution", closing remarks) and notes
+ * that a well-conditioned problem converges faster (Sec. "Bayesian View on
+ * Linear Inversion").  Here a network approximates the inverse of the normal
+ * operator of Eq. criterion on residuals, inside flexible CG
+ * (tomo_cg_solve with precond).  It is a 3x3x3 convolution stack, 1 -> 16
+ * -> 16 -> 1 channels with ReLU between layers, zero padding 1.  Parameters are a
  * DEVICE float array of TOMO_CONVNET_NPARAMS values, in this order:
  * w1[16][1][27], b1[16], w2[16][16][27], b2[16], w3[1][16][27], b3[1]
  * (w[cout][cin][kz*9 + ky*3 + kx], cross-correlation like torch.conv3d). */
@@ -425,20 +446,30 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d,
 void tomo_cg_default_params(tomo_cg_params *p);
 
 /*
- * Autotuner.  Times, on this geometry with synthetic data, the P wavefront
- * bundles with and without the XCD remap, and the P^T strategies (blocked
- * over several block shapes, owner counts and the XCD remap; binned; atomic), each
- * over `reps` launches after one warm-up, and keeps the fastest P shape and
- * P^T strategy/shape as the tuning of the geometry's size class: the cube's
- * largest side, the pixels per view and the view count, each rounded up to
- * a power of two, and whether the cube has frames.  Later launches on any
- * geometry of that class use it instead of the process-wide tuning.
- *   reps: 1..100.  out: HOST, may be NULL.  Synchronises the stream; takes
- *   stream-ordered scratch of about the cube, the images and the largest
- *   owner partials.
+ * Autotuner (the batched launches of Eq. srt_t and every single-system call
+ * take their launch shapes from it).  Times on this geometry the P
+ * candidates (wavefront bundles, XCD remap on/off, cube layouts) and the
+ * P^T candidates (blocked over block shapes for 256-, 512- and 1024-lane
+ * workgroups, owner counts and the XCD remap; binned; atomic), each over
+ * `reps` launches through the same paths tomo_project and tomo_backproject
+ * take, on a cube of ones and its own projection (tomo_autotune) or on the
+ * caller's cube and images (tomo_autotune_data).  The fastest P and P^T
+ * candidates are then timed against the process-wide tuning in alternation
+ * and kept only if at least 1% faster there; the result becomes the tuning
+ * of the geometry's size class (the cube's largest side, the pixels per
+ * view and the view count, each rounded up to a power of two, and whether
+ * the cube has frames), used by later launches on any geometry of that
+ * class instead of the process-wide tuning.
+ *   reps: 1..100.  out: HOST, may be NULL.  cube_d, images_d: DEVICE, laid
+ *   out as for tomo_project / tomo_backproject, read only.  Synchronises the
+ *   stream; takes stream-ordered scratch of about two cubes, two image sets
+ *   and the largest owner partials.
  */
 int tomo_autotune(const tomo_geometry *g, int32_t reps, tomo_tuning *out,
                   tomo_stream stream);
+int tomo_autotune_data(const tomo_geometry *g, const float *cube_d,
+                       const float *images_d, int32_t reps, tomo_tuning *out,
+                       tomo_stream stream);
 /* Tuning in effect for g (*tuned = 1 if it comes from the autotuner). */
 int tomo_get_class_tuning(const tomo_geometry *g, tomo_tuning *out,
                           int32_t *tuned);
@@ -446,9 +477,11 @@ int tomo_get_class_tuning(const tomo_geometry *g, tomo_tuning *out,
 void tomo_autotune_clear(void);
 
 /*
- * Batched persistent launches over independent systems (for instance the
- * time-frame cubes of one time-dependent reconstruction plus independent
- * reconstructions of other sizes).  One persistent P kernel and one
+ * Batched persistent launches over independent systems: the time-frame
+ * cubes of one time-dependent reconstruction, whose projector is
+ * block-diagonal over the frames (Eq. srt_t, coupled only through the
+ * temporal prior of Eq. stsrt), plus independent reconstructions of other
+ * sizes.  One persistent P kernel and one
  * persistent P^T kernel (owner-computes, as TOMO_BP_BLOCKED) drain device
  * work queues of (system, view, pixel tile) and (system, frame, voxel
  * block, owner) items covering every system; each system uses the launch
@@ -487,6 +520,11 @@ int64_t tomo_batch_items(tomo_batch b, int32_t which);
  * check_every iterations between host checks are captured once as a HIP
  * graph and replayed.  precond and record_* must be unset
  * (TOMO_EUNSUPPORTED); bp_strategy is ignored (always blocked).
+ * With reports[0].time_kernels = 1, every report's ms_project and
+ * ms_backproject receive the total time of the batched P and P^T launches
+ * of the iterations (one launch each per iteration, shared by all systems;
+ * HIP events on the launch stream, recorded as event-record nodes of the
+ * graph under use_graph; NaN if the graph could not hold them).
  *   y_d, x_d: HOST arrays of DEVICE pointers.  params, reports: HOST arrays
  *   of nsystems.  Synchronises the stream.
  */

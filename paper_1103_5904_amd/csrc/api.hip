@@ -28,7 +28,7 @@ static std::mutex g_tuning_mu;
 // fewer rays per deposit (1.47 ms per launch against 1.71 for 32x16x8).
 // The binned strategy, which alone takes the bundle field, prefers 8x8
 // bundles and 4096 bins.
-static tomo_tuning g_tuning = {2, 1, 3, 0, 4096, TOMO_BP_BLOCKED, {64, 32, 2}, 0};
+static tomo_tuning g_tuning = {2, 1, 3, 0, 4096, TOMO_BP_BLOCKED, {64, 32, 2}, 0, 256, 0};
 
 tomo_tuning current_tuning()
 {
@@ -205,6 +205,8 @@ static int build_plan(const tomo_geometry *g, int64_t npix, Plan &p)
     p.ntiles = tiles;
     p.npix = npix;
     p.max_steps = c.nx + c.ny + c.nz + 3;
+    p.max_nrow = 0;
+    for (int k = 0; k < g->nviews; ++k) p.max_nrow = g->views[k].nrow > p.max_nrow ? g->views[k].nrow : p.max_nrow;
     p.size_class = size_class_of(g, npix);
     // The blocked P^T's footprint row intervals pay where footprints span
     // several passes of pixels, i.e. where pixels are finer than voxels at the
@@ -259,7 +261,7 @@ static int build_plan(const tomo_geometry *g, int64_t npix, Plan &p)
     return TOMO_OK;
 }
 
-PlanRef get_plan(const tomo_geometry *g, int *status)
+PlanRef get_plan(const tomo_geometry *g, int *status, bool build)
 {
     int64_t npix = 0;
     int rc = validate_geometry_impl(g, &npix);
@@ -276,6 +278,11 @@ PlanRef get_plan(const tomo_geometry *g, int *status)
     auto &bucket = g_cache[hd];
     for (auto &e : bucket)
         if (e.key == key) return e.plan;
+    if (!build) {
+        *status = set_error(TOMO_EINVAL, "this geometry has no device tables yet: make another call with it "
+                                         "first (for instance tomo_count_crossings or tomo_backproject)");
+        return nullptr;
+    }
     if (g_cache.size() > 256) g_cache.clear();  // bound the cache; plans are rebuilt on demand
     CacheEntry ent;
     ent.key = std::move(key);
@@ -347,12 +354,16 @@ int tomo_set_tuning(const tomo_tuning *in)
         in->bp_default != TOMO_BP_BLOCKED)
         return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_default must be BLOCKED, BINNED or ATOMIC");
     for (int a = 0; a < 3; ++a)
-        if (in->bp_block[a] < 1 || in->bp_block[a] > 64)
-            return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_block entries must be in [1, 64]");
-    if (in->bp_block[0] * in->bp_block[1] * in->bp_block[2] > 8192)
-        return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_block holds more than 8192 voxels");
+        if (in->bp_block[a] < 1 || in->bp_block[a] > 256)
+            return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_block entries must be in [1, 256]");
+    if (in->bp_block[0] * in->bp_block[1] * in->bp_block[2] > 16384)
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_block holds more than 16384 voxels");
     if (in->bp_splits < 0 || in->bp_splits > 64)
         return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_splits must be in [0, 64]");
+    if (in->bp_threads != 256 && in->bp_threads != 512 && in->bp_threads != 1024)
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_threads must be 256, 512 or 1024");
+    if (in->p_layout != 0 && (in->p_layout < 2 || in->p_layout > 4))
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: p_layout must be 0, 2, 3 or 4");
     std::lock_guard<std::mutex> lock(g_tuning_mu);
     g_tuning = *in;
     return TOMO_OK;
@@ -457,3 +468,54 @@ int tomo_view_from_wcs(double dsun, double hgln_deg, double hglt_deg, double crv
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ scratch pool
+
+namespace tomo {
+
+// The library's stream-ordered scratch comes from a private memory pool per
+// device whose release threshold keeps up to kPoolKeep bytes of freed
+// memory mapped between calls: repeated calls (a back-projection inside a
+// caller's loop, the autotuner's candidates) reuse it instead of mapping
+// fresh memory at every call.  Without a pool the default one serves.
+constexpr uint64_t kPoolKeep = (uint64_t)1 << 30;
+constexpr int kPoolDevices = 64;
+static std::mutex g_pool_mu;
+static hipMemPool_t g_pool[kPoolDevices];
+static bool g_pool_tried[kPoolDevices];
+
+static hipMemPool_t scratch_pool()
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kPoolDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_pool_mu);
+    if (!g_pool_tried[dev]) {
+        g_pool_tried[dev] = true;
+        hipMemPoolProps props;
+        memset(&props, 0, sizeof(props));
+        props.allocType = hipMemAllocationTypePinned;
+        props.handleTypes = hipMemHandleTypeNone;
+        props.location.type = hipMemLocationTypeDevice;
+        props.location.id = dev;
+        hipMemPool_t pool = nullptr;
+        if (hipMemPoolCreate(&pool, &props) == hipSuccess) {
+            uint64_t keep = kPoolKeep;
+            (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+            g_pool[dev] = pool;
+        } else {
+            (void)hipGetLastError();
+        }
+    }
+    return g_pool[dev];
+}
+
+hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t s)
+{
+    hipMemPool_t pool = scratch_pool();
+    if (pool) return hipMallocFromPoolAsync(p, bytes, pool, s);
+    return hipMallocAsync(p, bytes, s);
+}
+
+hipError_t scratch_free(void *p, hipStream_t s) { return p ? hipFreeAsync(p, s) : hipSuccess; }
+
+}  // namespace tomo

@@ -20,6 +20,8 @@ struct SysDev {
     const uint8_t *map_mask;
     const uint8_t *data_mask;
     float *part;          // owner partials [splits][ntot] (splits > 1)
+    uint16_t *kept_pre;   // kept-pixel rows of the data mask (row intervals only), or null
+    uint16_t *kept_cols;
     BlockDev bd;
     int32_t nviews;
     int32_t p_log2_bw;
@@ -60,5 +62,7 @@ struct tomo_batch_s {
     size_t lds_bytes = 0;
     unsigned grid_p = 0, grid_b = 0;
     bool rows = false;  // P^T walks footprint row intervals (most systems' plans ask for them)
+    int32_t nt = 256;   // lanes per workgroup of the persistent P^T (the largest any system's tuning asks for)
+    uint16_t *kept = nullptr;  // kept-pixel rows of the systems' data masks
     ~tomo_batch_s();
 };

@@ -125,13 +125,13 @@ __global__ __launch_bounds__(kThreads) void k_batch_absmax(const SysDev *__restr
     if (threadIdx.x == 0) ymax[blockIdx.x] = m;
 }
 
-template <bool kRows>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_backproject(
+template <int NT, bool kRows>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_batch_backproject(
     const SysDev *__restrict__ sys, int32_t nsys, Operands ops, int64_t nitems, const uint32_t *__restrict__ ymax,
     unsigned long long *q, unsigned *__restrict__ spill)
 {
     extern __shared__ unsigned long long bins[];
-    __shared__ BlockedShared sh;
+    __shared__ BlockedShared<NT, kRows> sh;
     __shared__ int64_t s_item;
     int visited = 0;
     for (;;) {
@@ -147,9 +147,10 @@ __global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) v
         float *out = sd.bd.splits == 1 ? ops.dst[k] : sd.part;
         const uint32_t *ym = ymax + (int64_t)sd.view_begin * kYmaxParts;
         const bool mm = ops.map && sd.map_mask, dm = sd.data_mask != nullptr;
-#define TOMO_ITEM(M, D, O)                                                                                 \
-    blocked_item<M, D, O, kRows>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, li, ops.src[k],  \
-                          sd.map_mask, sd.data_mask, ym, out, ops.acc, spill, bins, sh)
+        const KeptRows kept{sd.kept_pre, sd.kept_cols};
+#define TOMO_ITEM(M, D, O)                                                                                      \
+    blocked_item<NT, M, D, O, kRows>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, li, ops.src[k],  \
+                                     sd.map_mask, sd.data_mask, kept, ym, out, ops.acc, spill, bins, sh)
         if (sd.grid.has_sph) {  // the obstacle's variant: one code path for every mask combination
             if (mm && dm) TOMO_ITEM(true, true, true);
             else if (mm) TOMO_ITEM(true, false, true);
@@ -204,6 +205,7 @@ tomo_batch_s::~tomo_batch_s()
     if (q) (void)hipFree(q);
     if (ymax) (void)hipFree(ymax);
     if (part) (void)hipFree(part);
+    if (kept) (void)hipFree(kept);
     if (spill) (void)hipFree(spill);
     (void)hipSetDevice(cur);
 }
@@ -217,16 +219,47 @@ int batch_project_ops(tomo_batch b, const Operands &ops, hipStream_t s)
     return hip_fail(hipGetLastError(), "batched projection launch");
 }
 
+// The persistent P^T kernel for a batch's workgroup size and row mode.
+template <int NT, bool kRows>
+static const void *batch_bp_kernel()
+{
+    return reinterpret_cast<const void *>(k_batch_backproject<NT, kRows>);
+}
+
+static const void *batch_bp_kernel_for(int nt, bool rows)
+{
+    switch (nt) {
+    case 512: return rows ? batch_bp_kernel<512, true>() : batch_bp_kernel<512, false>();
+    case 1024: return rows ? batch_bp_kernel<1024, true>() : batch_bp_kernel<1024, false>();
+    default: return rows ? batch_bp_kernel<256, true>() : batch_bp_kernel<256, false>();
+    }
+}
+
 int batch_backproject_ops(tomo_batch b, const Operands &ops, hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_absmax, dim3((unsigned)(b->nviews * kYmaxParts)), dim3(kThreads), 0, s,
                        b->sys_d, b->nsys, ops, b->ymax);
-    if (b->rows)
-        hipLaunchKernelGGL(k_batch_backproject<true>, dim3(b->grid_b), dim3(kThreads), b->lds_bytes, s, b->sys_d,
-                           b->nsys, ops, b->nitems, b->ymax, b->q + (kQueues + 1), b->spill);
-    else
-        hipLaunchKernelGGL(k_batch_backproject<false>, dim3(b->grid_b), dim3(kThreads), b->lds_bytes, s, b->sys_d,
-                           b->nsys, ops, b->nitems, b->ymax, b->q + (kQueues + 1), b->spill);
+    for (int k = 0; k < b->nsys; ++k) {  // the kept pixels of data masks, for row intervals
+        const SysDev &sd = b->sys_h[(size_t)k];
+        if (!sd.kept_cols) continue;
+        const int rc = kept_rows_launch(*b->plans[(size_t)k], sd.views, sd.nviews, sd.data_mask, sd.kept_pre,
+                                        sd.kept_cols, s, ops.done[k]);
+        if (rc) return rc;
+    }
+#define TOMO_BATCH_BP(NT, R)                                                                                     \
+    hipLaunchKernelGGL((k_batch_backproject<NT, R>), dim3(b->grid_b), dim3(NT), b->lds_bytes, s, b->sys_d, b->nsys, \
+                       ops, b->nitems, b->ymax, b->q + (kQueues + 1), b->spill)
+    if (b->nt == 512) {
+        if (b->rows) TOMO_BATCH_BP(512, true);
+        else TOMO_BATCH_BP(512, false);
+    } else if (b->nt == 1024) {
+        if (b->rows) TOMO_BATCH_BP(1024, true);
+        else TOMO_BATCH_BP(1024, false);
+    } else {
+        if (b->rows) TOMO_BATCH_BP(256, true);
+        else TOMO_BATCH_BP(256, false);
+    }
+#undef TOMO_BATCH_BP
     bool owners = false;
     for (const auto &sd : b->sys_h) owners = owners || sd.bd.splits > 1;
     if (owners) {
@@ -253,7 +286,7 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
     if (!b) return set_error(TOMO_ENOMEM, "tomo_batch_create: host allocation failed");
     (void)hipGetDevice(&b->device);
     b->nsys = nsystems;
-    int64_t part_floats = 0;
+    int64_t part_floats = 0, kept_pix = 0;
     int nrows = 0;  // systems whose plans ask for footprint row intervals
     for (int k = 0; k < nsystems; ++k) {
         int st = TOMO_OK;
@@ -291,7 +324,9 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
         if (bs.splits > 1) part_floats += (int64_t)bs.splits * sd.ntot;
         const size_t lds = sizeof(unsigned long long) * ((size_t)bs.b[0] * bs.b[1] * bs.b[2] + 1);  // + dummy bin
         b->lds_bytes = lds > b->lds_bytes ? lds : b->lds_bytes;
+        b->nt = bs.nt > b->nt ? bs.nt : b->nt;
         nrows += p->bp_rows ? 1 : 0;
+        if (systems[k].data_mask) kept_pix += p->npix;
         b->plans.push_back(p);
         b->geoms.push_back(systems[k]);
         b->geoms.back().obstacle = nullptr;  // captured in the plan's grid
@@ -308,16 +343,27 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
     if (e == hipSuccess) e = hipMalloc((void **)&b->spill, sizeof(unsigned));
     if (e == hipSuccess) e = hipMemset(b->spill, 0, sizeof(unsigned));
     if (e == hipSuccess && part_floats > 0) e = hipMalloc((void **)&b->part, sizeof(float) * (size_t)part_floats);
+    b->rows = 2 * nrows > (int)b->sys_h.size();
+    if (e == hipSuccess && b->rows && kept_pix > 0)
+        e = hipMalloc((void **)&b->kept, 2 * sizeof(uint16_t) * (size_t)kept_pix);
     if (e != hipSuccess) {
         delete b;
         return set_error(TOMO_ENOMEM, "tomo_batch_create: device allocation failed (%s)", hipGetErrorString(e));
     }
-    int64_t off = 0;
-    for (auto &sd : b->sys_h)
+    int64_t off = 0, koff = 0;
+    for (size_t k = 0; k < b->sys_h.size(); ++k) {
+        SysDev &sd = b->sys_h[k];
         if (sd.bd.splits > 1) {
             sd.part = b->part + off;
             off += (int64_t)sd.bd.splits * sd.ntot;
         }
+        if (b->kept && sd.data_mask) {
+            const int64_t np = b->plans[k]->npix;
+            sd.kept_pre = b->kept + koff;
+            sd.kept_cols = b->kept + koff + np;
+            koff += 2 * np;
+        }
+    }
     e = hipMalloc((void **)&b->sys_d, sizeof(SysDev) * b->sys_h.size());
     if (e == hipSuccess) e = hipMemcpy(b->sys_d, b->sys_h.data(), sizeof(SysDev) * b->sys_h.size(), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
@@ -328,11 +374,25 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
     int cus = 0, per_p = 0, per_b = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
     (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_p, k_batch_project, kThreads, 0);
-    b->rows = 2 * nrows > (int)b->sys_h.size();
-    if (b->rows)
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_b, k_batch_backproject<true>, kThreads, b->lds_bytes);
-    else
-        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_b, k_batch_backproject<false>, kThreads, b->lds_bytes);
+    {
+        BlockedShape probe;
+        probe.b[0] = 1;
+        probe.b[1] = 1;
+        probe.b[2] = (int32_t)(b->lds_bytes / sizeof(unsigned long long)) - 1;
+        probe.nt = b->nt;
+        const int lrc = blocked_check_lds(probe, b->rows, nullptr);
+        if (lrc) {
+            delete b;
+            return lrc;
+        }
+        const void *kern = batch_bp_kernel_for(b->nt, b->rows);
+        if (b->lds_bytes > 65536 &&
+            hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)b->lds_bytes) != hipSuccess) {
+            delete b;
+            return set_error(TOMO_EHIP, "tomo_batch_create: dynamic LDS attribute");
+        }
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_b, kern, b->nt, b->lds_bytes);
+    }
     cus = cus > 0 ? cus : 256;
     per_p = per_p > 0 ? per_p : 1;
     per_b = per_b > 0 ? per_b : 1;

@@ -40,21 +40,45 @@ __device__ inline uint32_t view_absmax_part(const ViewDev &v, int part, const fl
     return r;
 }
 
-// Shared-memory scratch of one item besides the bins: the footprints of up
-// to kViewChunk of the owner's views, computed together so that the
-// wavefronts then run through all of them without workgroup barriers.  A
-// footprint is the bounding rectangle of the block's projection and, when
-// the rectangle has at most kRowsMax rows, one column interval per row (the
-// projection of a box is convex, so the pixels of one row whose rays meet it
-// form an interval) with the running pixel count.
-constexpr int kViewChunk = 16;     // views per chunk walking whole rectangles
-constexpr int kViewChunkRows = 8;  // views per chunk with row intervals
+// Kept pixels of a data-masked image, row by row: for pixel (row, col),
+// pre[pix] = kept pixels before col in its row, and the first pre[row end]
+// entries of the row in cols hold the kept columns in order.  With them a
+// footprint row's column interval maps to a run of kept pixels, so masked
+// pixels never take a lane of the blocked P^T's passes.
+struct KeptRows {
+    const uint16_t *pre;
+    const uint16_t *cols;
+};
+
+// One view of a chunk staged in LDS: the pointing fields ray_setup reads,
+// plus what the passes need to address the view's pixels and weigh them.
+struct StagedView {
+    double o[3], w[3], u[3], v[3];
+    double cd[2], cp[2];
+    double vscale;    // gain times the fixed-point scale of the owner's bins
+    int64_t pix_off;  // first pixel of the view in the image vector
+    int32_t ncol, nrow;
+};
+
+// Shared-memory scratch of one item besides the bins: up to C views of the
+// owner, staged with their footprints, so that the passes then run over the
+// footprint pixels of all of them without workgroup barriers.  A footprint is
+// the bounding rectangle of the block's projection and, when the rectangle
+// has at most kRowsMax rows, one column interval per row (the projection of a
+// box is convex, so the pixels of one row whose rays meet it form an
+// interval) with the running pixel count.  vpre holds the pixels of the
+// chunk's views before each view: the passes take the concatenated list 256
+// (or NT) pixels at a time, so a pass is ragged only at the chunk's end.
 constexpr int kRowsMax = 64;
+template <int NT, bool kRows>
 struct BlockedShared {
-    int rect[kViewChunk][4];                    // c0, c1, r0, r1 (c0 > c1: the block is not seen)
-    int rows[kViewChunk];                       // 1: walk the row intervals, 0: the whole rectangle
-    uint16_t cs[kViewChunkRows][kRowsMax];      // first column of each row's interval
-    int32_t pre[kViewChunkRows][kRowsMax + 1];  // pixels in the rows before (pre[H]: all)
+    static constexpr int C = kRows ? (NT >= 512 ? 16 : 8) : 32;  // views per chunk
+    StagedView view[C];
+    int rect[C][4];                      // c0, c1, r0, r1 (c0 > c1: the block is not seen)
+    int rows[C];                         // 1: walk the row intervals, 0: the whole rectangle
+    int64_t vpre[C + 1];                 // pixels of the chunk's views before view j
+    uint16_t cs[kRows ? C : 1][kRowsMax];      // first column (or kept-pixel index) of each row's run
+    int32_t pre[kRows ? C : 1][kRowsMax + 1];  // pixels in the rows before (pre[H]: all)
 };
 
 // Column interval [cs, ce] of image row `row` of view v whose rays can meet
@@ -68,8 +92,9 @@ struct BlockedShared {
 // each side and clipped to [c0, c1]; ce < cs: none.  Returns false if a
 // corner is not in front of the observer (the caller then keeps the whole
 // row).
-__device__ inline bool row_interval(const ViewDev &v, int row, const float (&lo)[3], const float (&hi)[3],
-                                    int c0, int c1, int &cs, int &ce)
+template <class V>
+__device__ inline bool row_interval(const V &v, int row, const float (&lo)[3], const float (&hi)[3], int c0,
+                                    int c1, int &cs, int &ce)
 {
     const float y = (float)(((double)row - v.cp[1]) * v.cd[1]);
     const float w[3] = {(float)v.w[0], (float)v.w[1], (float)v.w[2]};
@@ -127,19 +152,25 @@ __device__ inline bool row_interval(const ViewDev &v, int row, const float (&lo)
 
 // One owner item of the blocked P^T: (frame, block, split) from the item
 // index, every ray of the owner's views that can cross the block walked
-// inside it, and the block written once.  bins: nbins 64-bit LDS words.
-// Called by all threads of the workgroup.
-template <bool kMapMask, bool kDataMask, bool kObstacle, bool kRows>
+// inside it, and the block written once.  bins: nbins 64-bit LDS words plus
+// a dummy.  Called by all NT threads of the workgroup.  kept.cols != null
+// (with kDataMask) takes the passes over kept pixels only, in row-interval
+// footprints.
+template <int NT, bool kMapMask, bool kDataMask, bool kObstacle, bool kRows>
 __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict__ views,
                                     const int32_t *__restrict__ frame_views,
                                     const int32_t *__restrict__ frame_voff, const BlockDev &bd,
                                     int64_t item, const float *__restrict__ images,
                                     const uint8_t *__restrict__ map_mask,
-                                    const uint8_t *__restrict__ data_mask,
+                                    const uint8_t *__restrict__ data_mask, KeptRows kept,
                                     const uint32_t *__restrict__ ymax_parts, float *__restrict__ out,
                                     int32_t accumulate, unsigned *__restrict__ spill,
-                                    unsigned long long *bins, BlockedShared &sh)
+                                    unsigned long long *bins, BlockedShared<NT, kRows> &sh)
 {
+    using Sh = BlockedShared<NT, kRows>;
+    constexpr int C = Sh::C;
+    static_assert(8 * C <= NT, "eight lanes per staged view");
+    const int tid = threadIdx.x;
     // ---- item -> (frame, block, split)
     const int64_t nblk = (int64_t)bd.nb[0] * bd.nb[1] * bd.nb[2];
     const int split = (int)(item % bd.splits);
@@ -183,20 +214,20 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
     float *fbins = reinterpret_cast<float *>(bins);
 
     __syncthreads();  // the previous item of this workgroup is done with the bins
-    for (int i = threadIdx.x; i <= nbins; i += kThreads) bins[i] = 0ull;  // + the dummy bin
+    for (int i = tid; i <= nbins; i += NT) bins[i] = 0ull;  // + the dummy bin
     unsigned spills = 0u;
+    const bool compact = kRows && kDataMask && kept.cols != nullptr;
 
     const int nvi = v1 - v0 > split ? (v1 - v0 - split + bd.splits - 1) / bd.splits : 0;  // owner's views
-    constexpr int kChunk = kRows ? kViewChunkRows : kViewChunk;
-    for (int cs = 0; cs < nvi; cs += kChunk) {
-        const int nch = min(kChunk, nvi - cs);
+    for (int cs0 = 0; cs0 < nvi; cs0 += C) {
+        const int nch = min(C, nvi - cs0);
         // ---- footprints: thread 8 j + c projects corner c of the chunk's
         // view j; the 8 lanes of a view reduce with shuffles
-        __syncthreads();  // the previous chunk's rectangles are no longer in use
-        if (threadIdx.x < 8 * kChunk) {
-            const int j = threadIdx.x >> 3, c = threadIdx.x & 7;
+        __syncthreads();  // the previous chunk's staging is no longer in use
+        if (tid < 8 * C) {
+            const int j = tid >> 3, c = tid & 7;
             const bool live = j < nch;
-            const ViewDev &v = views[frame_views[v0 + split + (cs + (live ? j : 0)) * bd.splits]];
+            const ViewDev &v = views[frame_views[v0 + split + (cs0 + (live ? j : 0)) * bd.splits]];
             double cc = 0.0, cr = 0.0;
             int bad = 0;
             if (live) {
@@ -225,37 +256,61 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 rmx = fmax(rmx, __shfl_xor(rmx, o));
                 bad |= __shfl_xor(bad, o);
             }
-            if (live && c == 0) {
-                int c0 = 0, c1 = v.ncol - 1, r0 = 0, r1 = v.nrow - 1;
-                if (!bad) {  // clamp in double before converting: far-off corners stay finite
-                    c0 = (int)fmax(floor(cmn) - 1.0, 0.0);
-                    c1 = (int)fmin(ceil(cmx) + 1.0, (double)(v.ncol - 1));
-                    r0 = (int)fmax(floor(rmn) - 1.0, 0.0);
-                    r1 = (int)fmin(ceil(rmx) + 1.0, (double)(v.nrow - 1));
+            if (live) {
+                StagedView &sv = sh.view[j];
+                // the eight lanes of the view copy its pointing fields
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    if (c == 0) sv.o[a] = v.o[a];
+                    if (c == 1) sv.w[a] = v.w[a];
+                    if (c == 2) sv.u[a] = v.u[a];
+                    if (c == 3) sv.v[a] = v.v[a];
                 }
-                sh.rect[j][0] = c0;
-                sh.rect[j][1] = c1;
-                sh.rect[j][2] = r0;
-                sh.rect[j][3] = r1;
-                sh.rows[j] = kRows && !bad && c0 <= c1 && r1 - r0 < kRowsMax;
+                if (c == 4) {
+                    sv.cd[0] = v.cd[0];
+                    sv.cd[1] = v.cd[1];
+                    sv.cp[0] = v.cp[0];
+                    sv.cp[1] = v.cp[1];
+                }
+                if (c == 5) {
+                    // the view's gain times the bin scale (a power of two: exact)
+                    sv.vscale = v.gain * (finite ? fx_scale : 1.0);
+                    sv.pix_off = v.pix_off;
+                    sv.ncol = v.ncol;
+                    sv.nrow = v.nrow;
+                }
+                if (c == 0) {
+                    int c0 = 0, c1 = v.ncol - 1, r0 = 0, r1 = v.nrow - 1;
+                    if (!bad) {  // clamp in double before converting: far-off corners stay finite
+                        c0 = (int)fmax(floor(cmn) - 1.0, 0.0);
+                        c1 = (int)fmin(ceil(cmx) + 1.0, (double)(v.ncol - 1));
+                        r0 = (int)fmax(floor(rmn) - 1.0, 0.0);
+                        r1 = (int)fmin(ceil(rmx) + 1.0, (double)(v.nrow - 1));
+                    }
+                    sh.rect[j][0] = c0;
+                    sh.rect[j][1] = c1;
+                    sh.rect[j][2] = r0;
+                    sh.rect[j][3] = r1;
+                    sh.rows[j] = kRows && !bad && c0 <= c1 && r1 - r0 < kRowsMax;
+                }
             }
         }
         __syncthreads();
 
         if constexpr (kRows) {
             // ---- row intervals: one row per thread, widths first (in pre[row + 1])
-            for (int t = threadIdx.x; t < nch * kRowsMax; t += kThreads) {
+            for (int t = tid; t < nch * kRowsMax; t += NT) {
                 const int j = t / kRowsMax, rr = t % kRowsMax;
                 const int c0 = sh.rect[j][0], c1 = sh.rect[j][1], r0 = sh.rect[j][2], r1 = sh.rect[j][3];
                 if (!sh.rows[j] || rr > r1 - r0) continue;
-                const ViewDev &v = views[frame_views[v0 + split + (cs + j) * bd.splits]];
+                const StagedView &v = sh.view[j];
                 // the block's box less the observer, padded by 1e-3 of a voxel
                 // plus 1e-5 of the largest coordinate in play: far above the FP32
                 // rounding of the interval (relative 1e-7 of these magnitudes) and
                 // the rays' FP64 set-up, so that every ray the exact set-up finds
                 // inside the block is kept
                 float lo[3], hi[3];
-    #pragma unroll
+#pragma unroll
                 for (int a = 0; a < 3; ++a) {
                     const double big = fmax(fmax(fabs(g.lo[a]), fabs(g.hi[a])), fabs(v.o[a]));
                     const double pad = 1e-3 * g.delta[a] + 1e-5 * big;
@@ -267,166 +322,200 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                     a0 = c0;
                     a1 = c1;
                 }
-                sh.cs[j][rr] = (uint16_t)a0;
-                sh.pre[j][rr + 1] = a1 >= a0 ? a1 - a0 + 1 : 0;
+                int start = a0, width = a1 >= a0 ? a1 - a0 + 1 : 0;
+                if (compact && width > 0) {  // the run of kept pixels in [a0, a1]
+                    const int64_t rb = v.pix_off + (int64_t)(r0 + rr) * v.ncol;
+                    start = kept.pre[rb + a0];
+                    width = (int)kept.pre[rb + a1] + (data_mask[rb + a1] ? 1 : 0) - start;
+                }
+                sh.cs[j][rr] = (uint16_t)start;
+                sh.pre[j][rr + 1] = width;
             }
             __syncthreads();
-            if (threadIdx.x < nch && sh.rows[threadIdx.x]) {  // running counts
-                const int j = threadIdx.x, h = sh.rect[j][3] - sh.rect[j][2] + 1;
+            if (tid < nch && sh.rows[tid]) {  // running counts
+                const int j = tid, h = sh.rect[j][3] - sh.rect[j][2] + 1;
                 sh.pre[j][0] = 0;
                 for (int rr = 1; rr <= h; ++rr) sh.pre[j][rr] += sh.pre[j][rr - 1];
             }
             __syncthreads();
         }
+        if (tid == 0) {  // the chunk's views back to back
+            int64_t acc = 0;
+            for (int j = 0; j < nch; ++j) {
+                sh.vpre[j] = acc;
+                const int c0 = sh.rect[j][0], c1 = sh.rect[j][1], r0 = sh.rect[j][2], r1 = sh.rect[j][3];
+                if (c0 <= c1 && r0 <= r1)
+                    acc += (kRows && sh.rows[j]) ? (int64_t)sh.pre[j][r1 - r0 + 1]
+                                                 : (int64_t)(c1 - c0 + 1) * (r1 - r0 + 1);
+            }
+            sh.vpre[nch] = acc;
+        }
+        __syncthreads();
+        const int64_t total = sh.vpre[nch];
 
-        for (int j = 0; j < nch; ++j) {
-            const ViewDev &v = views[frame_views[v0 + split + (cs + j) * bd.splits]];
-            const int c0 = sh.rect[j][0], c1 = sh.rect[j][1], r0 = sh.rect[j][2], r1 = sh.rect[j][3];
-            if (c0 > c1 || r0 > r1) continue;  // uniform
-            // the view's gain times the bin scale (a power of two: exact)
-            const double vscale = v.gain * (finite ? fx_scale : 1.0);
-
-            // ---- rays of the footprint, 256 per pass in row-major order over
-            // the row intervals (or the whole rectangle): thread i takes pixel
-            // i of each pass, so a wavefront walks a run of 64 neighbouring
-            // pixels and only the last pass is ragged; each pass loads the
-            // next pass's pixel value so that its latency is hidden by the walk
-            const bool rows = kRows && sh.rows[j] != 0;
-            const int H = r1 - r0 + 1, W = c1 - c0 + 1;
-            const int npx = rows ? sh.pre[j][H] : W * H, ntile = (npx + kThreads - 1) / kThreads;
-            const int adv_r = kThreads / W, adv_c = kThreads - adv_r * W;  // rectangle: a pass moves kThreads pixels
-            int lin = threadIdx.x;
-            int col, row, rr = 0;
-            if (rows) {
+        // ---- the footprint pixels of all the chunk's views, NT per pass: thread
+        // i takes pixel i of each pass, so a wavefront walks a run of 64
+        // neighbouring pixels; each pass loads the next pass's pixel value so
+        // that its latency is hidden by the walk.  A lane's pixel index only
+        // grows, so its view j and row rr are found by scanning forward.
+        int j = 0, rr = 0;
+        // returns true when the pixel comes from a row's run of kept pixels
+        // (its data mask need not be read)
+        auto locate = [&](int64_t L, int &col, int &row) -> bool {
+            while (j < nch - 1 && L >= sh.vpre[j + 1]) {
+                ++j;
+                rr = 0;
+            }
+            const int64_t lin = L - sh.vpre[j];
+            const int c0 = sh.rect[j][0], r0 = sh.rect[j][2];
+            if (kRows && sh.rows[j]) {
+                const int H = sh.rect[j][3] - r0 + 1;
                 while (rr < H - 1 && lin >= sh.pre[j][rr + 1]) ++rr;
-                col = (int)sh.cs[j][rr] + (lin - sh.pre[j][rr]);
+                const int k = (int)sh.cs[j][rr] + ((int)lin - sh.pre[j][rr]);
                 row = r0 + rr;
-            } else {
-                col = c0 + lin % W;
-                row = r0 + lin / W;
+                col = compact ? (int)kept.cols[sh.view[j].pix_off + (int64_t)row * sh.view[j].ncol + k] : k;
+                return compact;
             }
-            bool ok = lin < npx;
-            float ynext = 0.0f;
-            bool mnext = true;
-            if (ok) {
-                const int64_t pix = v.pix_off + (int64_t)row * v.ncol + col;
-                ynext = images[pix];
-                if (kDataMask) mnext = data_mask[pix] != 0;
-            }
-            for (int t = 0; t < ntile; ++t) {
-                const int pcol = col, prow = row;
-                const bool pok = ok, pm = mnext;
-                const float yv = ynext;
-                lin += kThreads;
-                if (rows) {
-                    while (rr < H - 1 && lin >= sh.pre[j][rr + 1]) ++rr;
-                    col = (int)sh.cs[j][rr] + (lin - sh.pre[j][rr]);
-                    row = r0 + rr;
+            {
+                const int W = sh.rect[j][1] - c0 + 1;
+                int q, r;
+                if (lin < (1 << 22)) {  // FP32 holds lin exactly; q is then within one of lin / W
+                    q = (int)((float)lin * (1.0f / (float)W));
+                    r = (int)lin - q * W;
+                    if (r < 0) {
+                        --q;
+                        r += W;
+                    } else if (r >= W) {
+                        ++q;
+                        r -= W;
+                    }
                 } else {
-                    col += adv_c;
-                    row += adv_r;
-                    if (col > c1) {
-                        col -= W;
-                        ++row;
-                    }
+                    q = (int)(lin / W);
+                    r = (int)(lin - (int64_t)q * W);
                 }
-                ok = lin < npx;
-                if (ok) {
-                    const int64_t pix = v.pix_off + (int64_t)row * v.ncol + col;
-                    ynext = images[pix];
-                    if (kDataMask) mnext = data_mask[pix] != 0;
-                }
-                if (!pok || !nonzero_bits(yv) || (kDataMask && !pm)) continue;
-                RayState r;
-                RayAxes ax;
-                if (!ray_setup<kObstacle>(g, v, pcol, prow, r, &ax)) continue;
-                // parameter interval [E, X) inside the block, exact on the ray's grid
-                double E = 0.0, X = r.send;
-                bool hit = true;
+                row = r0 + q;
+                col = c0 + r;
+            }
+            return false;
+        };
+        int64_t L = tid;
+        int col = 0, row = 0;
+        bool ok = L < total;
+        int jn = 0;
+        float ynext = 0.0f;
+        bool mnext = true;
+        if (ok) {
+            const bool known = locate(L, col, row);
+            jn = j;
+            const int64_t pix = sh.view[j].pix_off + (int64_t)row * sh.view[j].ncol + col;
+            ynext = images[pix];
+            if (kDataMask && !known) mnext = data_mask[pix] != 0;
+        }
+        for (int64_t base = 0; base < total; base += NT) {
+            const int pcol = col, prow = row, pj = jn;
+            const bool pok = ok, pm = mnext;
+            const float yv = ynext;
+            L += NT;
+            ok = L < total;
+            if (ok) {
+                const bool known = locate(L, col, row);
+                jn = j;
+                const int64_t pix = sh.view[j].pix_off + (int64_t)row * sh.view[j].ncol + col;
+                ynext = images[pix];
+                mnext = true;
+                if (kDataMask && !known) mnext = data_mask[pix] != 0;
+            }
+            if (!pok || !nonzero_bits(yv) || (kDataMask && !pm)) continue;
+            const StagedView &v = sh.view[pj];
+            RayState r;
+            RayAxes ax;
+            if (!ray_setup<kObstacle>(g, v, pcol, prow, r, &ax)) continue;
+            // parameter interval [E, X) inside the block, exact on the ray's grid
+            double E = 0.0, X = r.send;
+            bool hit = true;
 #pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    if (r.ds[a] == 0.0) {  // index constant along the ray
-                        hit = hit && ax.idx[a] >= blo[a] && ax.idx[a] < bhi[a];
-                        continue;
-                    }
-                    const bool up = r.st[a] > 0;
-                    const int J = up ? blo[a] - ax.idx[a] : ax.idx[a] - (bhi[a] - 1);  // crossings to enter
-                    const int K = up ? bhi[a] - ax.idx[a] : ax.idx[a] - blo[a] + 1;    // crossings to leave
-                    hit = hit && K > 0;
-                    if (J > 0) E = fmax(E, r.s[a] + (double)(J - 1) * r.ds[a]);
-                    X = fmin(X, r.s[a] + (double)(K - 1) * r.ds[a]);
-                }
-                if (!hit || !(X > E)) continue;
-                // walk state at E: crossings with parameter <= E are done
-                int32_t loc = 0;
-                int32_t lst[3];
-                bool inblk = true;
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    int idx = ax.idx[a];
-                    if (r.ds[a] != 0.0) {
-                        int j = 0;
-                        if (E >= r.s[a]) {
-                            // the estimate from the unrounded spacing is within
-                            // one of the count: the grid moves a spacing by at
-                            // most 2^-49 crossings-per-chord of itself, so C
-                            // crossings shift by at most 2^-49 C^2 < 1/2 on a
-                            // cube side of at most 2^24 voxels (a capped
-                            // spacing only makes it smaller, where the count
-                            // is 1); one exact comparison each way settles it
-                            j = max((int)floor((E - r.s[a]) * ax.rds[a]) + 1, 1);
-                            j -= (j > 1 && r.s[a] + (double)(j - 1) * r.ds[a] > E) ? 1 : 0;
-                            j += (r.s[a] + (double)j * r.ds[a] <= E) ? 1 : 0;
-                        }
-                        r.s[a] += (double)j * r.ds[a];
-                        idx += r.st[a] > 0 ? j : -j;
-                        lst[a] = r.st[a] > 0 ? lstride[a] : -lstride[a];
-                    } else {
-                        lst[a] = 0;
-                    }
-                    inblk = inblk && idx >= blo[a] && idx < bhi[a];
-                    loc += (idx - blo[a]) * lstride[a];
-                }
-                // On the exact grid a walk that starts inside the block stays
-                // inside until X (each axis takes fewer crossings than it needs
-                // to leave), so a start outside it is the only possible spill:
-                // counted, and the ray skipped.
-                if (!inblk) {
-                    ++spills;
+            for (int a = 0; a < 3; ++a) {
+                if (r.ds[a] == 0.0) {  // index constant along the ray
+                    hit = hit && ax.idx[a] >= blo[a] && ax.idx[a] < bhi[a];
                     continue;
                 }
-                const double wys = (double)yv * r.dn * vscale;
-                // four steps per loop body, as in ray_walk; the clamp to the
-                // dummy bin nbins only guards the LDS range
-                auto walk = [&](auto deposit) {
-                    double scur = E;
-                    auto step = [&]() {
-                        const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
-                        deposit(min((uint32_t)loc, (uint32_t)nbins), (m - scur) * wys);
-                        if (m >= X) return true;
+                const bool up = r.st[a] > 0;
+                const int J = up ? blo[a] - ax.idx[a] : ax.idx[a] - (bhi[a] - 1);  // crossings to enter
+                const int K = up ? bhi[a] - ax.idx[a] : ax.idx[a] - blo[a] + 1;    // crossings to leave
+                hit = hit && K > 0;
+                if (J > 0) E = fmax(E, r.s[a] + (double)(J - 1) * r.ds[a]);
+                X = fmin(X, r.s[a] + (double)(K - 1) * r.ds[a]);
+            }
+            if (!hit || !(X > E)) continue;
+            // walk state at E: crossings with parameter <= E are done
+            int32_t loc = 0;
+            int32_t lst[3];
+            bool inblk = true;
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            const bool tie = (r.s[a] == m);
-                            r.s[a] = fma(r.ds[a], tie_factor(tie), r.s[a]);
-                            loc += tie ? lst[a] : 0;
-                        }
-                        scur = m;
-                        return false;
-                    };
-                    for (int it = 0; it < bd.maxit; it += 4) {
-                        if (step() || step() || step() || step()) break;
+            for (int a = 0; a < 3; ++a) {
+                int idx = ax.idx[a];
+                if (r.ds[a] != 0.0) {
+                    int jj = 0;
+                    if (E >= r.s[a]) {
+                        // the estimate from the unrounded spacing is within
+                        // one of the count: the grid moves a spacing by at
+                        // most 2^-49 crossings-per-chord of itself, so C
+                        // crossings shift by at most 2^-49 C^2 < 1/2 on a
+                        // cube side of at most 2^24 voxels (a capped
+                        // spacing only makes it smaller, where the count
+                        // is 1); one exact comparison each way settles it
+                        jj = max((int)floor((E - r.s[a]) * ax.rds[a]) + 1, 1);
+                        jj -= (jj > 1 && r.s[a] + (double)(jj - 1) * r.ds[a] > E) ? 1 : 0;
+                        jj += (r.s[a] + (double)jj * r.ds[a] <= E) ? 1 : 0;
                     }
-                };
-                if (finite) {
-                    walk([&](uint32_t l, double v) {
-                        // v + 1.5 * 2^52 rounds v to an integer (|v| < 2^50) in the low bits
-                        const double t = v + 6755399441055744.0;
-                        const long long q = (long long)__builtin_bit_cast(uint64_t, t) - 0x4338000000000000ll;
-                        atomicAdd(&bins[l], (unsigned long long)q);
-                    });
+                    r.s[a] += (double)jj * r.ds[a];
+                    idx += r.st[a] > 0 ? jj : -jj;
+                    lst[a] = r.st[a] > 0 ? lstride[a] : -lstride[a];
                 } else {
-                    walk([&](uint32_t l, double v) { atomicAdd(&fbins[l], (float)v); });
+                    lst[a] = 0;
                 }
+                inblk = inblk && idx >= blo[a] && idx < bhi[a];
+                loc += (idx - blo[a]) * lstride[a];
+            }
+            // On the exact grid a walk that starts inside the block stays
+            // inside until X (each axis takes fewer crossings than it needs
+            // to leave), so a start outside it is the only possible spill:
+            // counted, and the ray skipped.
+            if (!inblk) {
+                ++spills;
+                continue;
+            }
+            const double wys = (double)yv * r.dn * v.vscale;
+            // four steps per loop body, as in ray_walk; the clamp to the
+            // dummy bin nbins only guards the LDS range
+            auto walk = [&](auto deposit) {
+                double scur = E;
+                auto step = [&]() {
+                    const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
+                    deposit(min((uint32_t)loc, (uint32_t)nbins), (m - scur) * wys);
+                    if (m >= X) return true;
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        const bool tie = (r.s[a] == m);
+                        r.s[a] = fma(r.ds[a], tie_factor(tie), r.s[a]);
+                        loc += tie ? lst[a] : 0;
+                    }
+                    scur = m;
+                    return false;
+                };
+                for (int it = 0; it < bd.maxit; it += 4) {
+                    if (step() || step() || step() || step()) break;
+                }
+            };
+            if (finite) {
+                walk([&](uint32_t l, double val) {
+                    // val + 1.5 * 2^52 rounds val to an integer (|val| < 2^50) in the low bits
+                    const double t = val + 6755399441055744.0;
+                    const long long q = (long long)__builtin_bit_cast(uint64_t, t) - 0x4338000000000000ll;
+                    atomicAdd(&bins[l], (unsigned long long)q);
+                });
+            } else {
+                walk([&](uint32_t l, double val) { atomicAdd(&fbins[l], (float)val); });
             }
         }
     }
@@ -438,7 +527,7 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
     const int nin = ex * ey * ez;
     const int64_t fbase = (int64_t)frame * g.nvox;
     const int64_t total = g.nvox * g.nframes;
-    for (int e = threadIdx.x; e < nin; e += kThreads) {
+    for (int e = tid; e < nin; e += NT) {
         const int lx = e % ex, ly = (e / ex) % ey, lz = e / (ex * ey);
         const int l = (lz * bd.b[1] + ly) * bd.b[0] + lx;
         const float val = finite ? (float)((double)(long long)bins[l] * fx_inv) : fbins[l];

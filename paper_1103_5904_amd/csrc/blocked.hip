@@ -61,22 +61,52 @@ __global__ __launch_bounds__(kThreads) void k_view_absmax(const ViewDev *__restr
     if (threadIdx.x == 0) ymax[blockIdx.x] = m;
 }
 
-template <bool kMapMask, bool kDataMask, bool kObstacle, bool kRows>
-__global__ __launch_bounds__(kThreads) __attribute__((amdgpu_waves_per_eu(4))) void k_backproject_blocked(
+// Kept pixels of every image row (see KeptRows): one wavefront per row, 64
+// columns per ballot.
+__global__ __launch_bounds__(kThreads) void k_kept_rows(const ViewDev *__restrict__ views, int32_t nviews,
+                                                        const uint8_t *__restrict__ data_mask,
+                                                        uint16_t *__restrict__ pre, uint16_t *__restrict__ cols,
+                                                        const int *__restrict__ done_flag)
+{
+    if (done_flag && *done_flag) return;
+    const int lane = threadIdx.x & 63;
+    for (int vi = blockIdx.y; vi < nviews; vi += gridDim.y) {
+        const ViewDev &v = views[vi];
+        const int row = blockIdx.x * (kThreads / 64) + (threadIdx.x >> 6);
+        if (row >= v.nrow) continue;
+        const int64_t rb = v.pix_off + (int64_t)row * v.ncol;
+        int base = 0;
+        for (int c0 = 0; c0 < v.ncol; c0 += 64) {
+            const int c = c0 + lane;
+            const bool keep = c < v.ncol && data_mask[rb + c] != 0;
+            const uint64_t bal = __ballot(keep);
+            const int below = __popcll(bal & ((1ull << lane) - 1ull));
+            if (c < v.ncol) {
+                pre[rb + c] = (uint16_t)(base + below);
+                if (keep) cols[rb + base + below] = (uint16_t)c;
+            }
+            base += __popcll(bal);
+        }
+    }
+}
+
+template <int NT, bool kMapMask, bool kDataMask, bool kObstacle, bool kRows>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_backproject_blocked(
     GridDev g, const ViewDev *__restrict__ views, const int32_t *__restrict__ frame_views,
     const int32_t *__restrict__ frame_voff, BlockDev bd, Bundle bun, const float *__restrict__ images,
-    const uint8_t *__restrict__ map_mask, const uint8_t *__restrict__ data_mask,
+    const uint8_t *__restrict__ map_mask, const uint8_t *__restrict__ data_mask, KeptRows kept,
     const uint32_t *__restrict__ ymax_parts, float *__restrict__ out, int32_t accumulate,
     const int *__restrict__ done_flag, unsigned *__restrict__ spill)
 {
     extern __shared__ unsigned long long bins[];  // bx*by*bz fixed-point (or FP32) sums
-    __shared__ BlockedShared sh;
+    __shared__ BlockedShared<NT, kRows> sh;
     if (done_flag && *done_flag) return;
     const int64_t nitems = (int64_t)bd.nb[0] * bd.nb[1] * bd.nb[2] * g.nframes * bd.splits;
     const int64_t item = bun.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     if (item >= nitems) return;
-    blocked_item<kMapMask, kDataMask, kObstacle, kRows>(g, views, frame_views, frame_voff, bd, item, images, map_mask,
-                                                 data_mask, ymax_parts, out, accumulate, spill, bins, sh);
+    blocked_item<NT, kMapMask, kDataMask, kObstacle, kRows>(g, views, frame_views, frame_voff, bd, item, images,
+                                                            map_mask, data_mask, kept, ymax_parts, out, accumulate,
+                                                            spill, bins, sh);
 }
 
 // out[i] = M (sum over owners of part[s][i]) (+ out[i]), owners in order.
@@ -103,6 +133,7 @@ BlockedShape blocked_shape(const Plan &p, const tomo_tuning &tu)
     bs.b[0] = tu.bp_block[0];
     bs.b[1] = tu.bp_block[1];
     bs.b[2] = tu.bp_block[2];
+    bs.nt = tu.bp_threads == 512 || tu.bp_threads == 1024 ? tu.bp_threads : 256;
     int64_t nblk = 1;
     for (int a = 0; a < 3; ++a) {
         bs.nb[a] = (p.grid.n[a] + bs.b[a] - 1) / bs.b[a];
@@ -110,8 +141,8 @@ BlockedShape blocked_shape(const Plan &p, const tomo_tuning &tu)
     }
     nblk *= p.grid.nframes;
     int s = tu.bp_splits;
-    if (s <= 0) {  // enough owners for ~8 workgroups per CU (two rounds of the four resident)
-        const int64_t want = 2048;
+    if (s <= 0) {  // enough owners for about two rounds of the resident workgroups
+        const int64_t want = 2048 * 256 / bs.nt;
         s = (int)((want + nblk - 1) / nblk);
         s = s < 1 ? 1 : (s > 8 ? 8 : s);
     }
@@ -121,56 +152,123 @@ BlockedShape blocked_shape(const Plan &p, const tomo_tuning &tu)
     return bs;
 }
 
-size_t blocked_scratch_bytes(const Plan &p, const BlockedShape &bs)
+static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Scratch layout: per-view partial maxima; the owners' partial sums (when
+// blocks have several owners); the kept-pixel rows (row intervals over a
+// data mask).
+struct BlockedScratch {
+    uint32_t *ymax;
+    float *part;
+    KeptRows kept;
+};
+
+static size_t blocked_layout(const Plan &p, const BlockedShape &bs, bool data_mask, char *base, BlockedScratch *out)
 {
-    size_t bytes = sizeof(uint32_t) * (size_t)p.nviews * kYmaxParts;
-    bytes = (bytes + 255) & ~(size_t)255;
-    if (bs.splits > 1) bytes += sizeof(float) * (size_t)bs.splits * (size_t)(p.grid.nvox * p.grid.nframes);
-    return bytes;
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        char *q = base ? base + off : nullptr;
+        off += align256(bytes);
+        return q;
+    };
+    BlockedScratch sc;
+    sc.ymax = (uint32_t *)take(sizeof(uint32_t) * (size_t)p.nviews * kYmaxParts);
+    sc.part = bs.splits > 1 ? (float *)take(sizeof(float) * (size_t)bs.splits * (size_t)(p.grid.nvox * p.grid.nframes))
+                            : nullptr;
+    sc.kept.pre = sc.kept.cols = nullptr;
+    if (p.bp_rows && data_mask) {
+        sc.kept.pre = (const uint16_t *)take(sizeof(uint16_t) * (size_t)p.npix);
+        sc.kept.cols = (const uint16_t *)take(sizeof(uint16_t) * (size_t)p.npix);
+    }
+    if (out) *out = sc;
+    return off;
 }
 
-int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
-                               bool accumulate, bool use_map_mask, hipStream_t s, const int *done_flag,
-                               void *scratch, size_t scratch_bytes, const tomo_tuning &tu)
+size_t blocked_scratch_bytes(const Plan &p, const BlockedShape &bs, bool data_mask)
 {
-    const BlockedShape bs = blocked_shape(p, tu);
-    const size_t need = blocked_scratch_bytes(p, bs);
-    if (!scratch || scratch_bytes < need)
-        return set_error(TOMO_EINVAL, "blocked back-projection: scratch of %zu bytes needed", need);
-    if (bs.items >= ((int64_t)1 << 31)) return set_error(TOMO_EINVAL, "blocked back-projection: too many blocks");
-    uint32_t *ymax = (uint32_t *)scratch;
-    float *part = (float *)((char *)scratch + ((sizeof(uint32_t) * (size_t)p.nviews * kYmaxParts + 255) & ~(size_t)255));
-    const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;
-    if (dm)
-        hipLaunchKernelGGL(k_view_absmax<true>, dim3((unsigned)(p.nviews * kYmaxParts)), dim3(kThreads), 0, s,
-                           p.views_d, images, g->data_mask, ymax, done_flag);
-    else
-        hipLaunchKernelGGL(k_view_absmax<false>, dim3((unsigned)(p.nviews * kYmaxParts)), dim3(kThreads), 0, s,
-                           p.views_d, images, g->data_mask, ymax, done_flag);
-    BlockDev bd;
-    for (int a = 0; a < 3; ++a) {
-        bd.b[a] = bs.b[a];
-        bd.nb[a] = bs.nb[a];
+    return blocked_layout(p, bs, data_mask, nullptr, nullptr);
+}
+
+int kept_rows_launch(const Plan &p, const ViewDev *views, int32_t nviews, const uint8_t *data_mask, uint16_t *pre,
+                     uint16_t *cols, hipStream_t s, const int *done_flag)
+{
+    const int32_t max_rows = p.max_nrow > 0 ? p.max_nrow : 1;
+    const dim3 grid((unsigned)((max_rows + kThreads / 64 - 1) / (kThreads / 64)),
+                    (unsigned)(nviews < 65535 ? nviews : 65535));
+    hipLaunchKernelGGL(k_kept_rows, grid, dim3(kThreads), 0, s, views, nviews, data_mask, pre, cols, done_flag);
+    return hip_fail(hipGetLastError(), "kept-row kernel launch");
+}
+
+int blocked_static_lds(int nt, bool rows)
+{
+    switch (nt) {
+    case 512: return rows ? (int)sizeof(BlockedShared<512, true>) : (int)sizeof(BlockedShared<512, false>);
+    case 1024: return rows ? (int)sizeof(BlockedShared<1024, true>) : (int)sizeof(BlockedShared<1024, false>);
+    default: return rows ? (int)sizeof(BlockedShared<256, true>) : (int)sizeof(BlockedShared<256, false>);
     }
-    bd.splits = bs.splits;
-    bd.maxit = bs.b[0] + bs.b[1] + bs.b[2] + 3;
-    const Bundle bun{tu.bp_bundle, tu.bp_xcd_remap};
-    const size_t lds = sizeof(unsigned long long) * ((size_t)bs.b[0] * bs.b[1] * bs.b[2] + 1);  // + dummy bin
-    float *dst = bs.splits == 1 ? cube : part;
-    const int acc = accumulate ? 1 : 0;
-#define TOMO_LAUNCH_BK4(M, D, O, R)                                                                           \
-    hipLaunchKernelGGL((k_backproject_blocked<M, D, O, R>), dim3((unsigned)bs.items), dim3(kThreads), lds, s, \
-                       p.grid, p.views_d, p.frame_views_d, p.frame_voff_d, bd, bun, images,                  \
-                       g->map_mask, g->data_mask, ymax, dst, acc, done_flag, p.spill_d)
+}
+
+// Largest LDS a workgroup may take on the current device (static + dynamic).
+static size_t lds_limit()
+{
+    static size_t cached = 0;
+    if (!cached) {
+        int dev = 0, v = 0;
+        (void)hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0)
+            v = 65536;
+        cached = (size_t)v;
+    }
+    return cached;
+}
+
+int blocked_check_lds(const BlockedShape &bs, bool rows, size_t *dyn_out)
+{
+    const size_t dyn = sizeof(unsigned long long) * ((size_t)bs.b[0] * bs.b[1] * bs.b[2] + 1);  // + dummy bin
+    if (dyn_out) *dyn_out = dyn;
+    if (dyn + (size_t)blocked_static_lds(bs.nt, rows) > lds_limit())
+        return set_error(TOMO_EINVAL, "blocked back-projection: a %dx%dx%d block with %d lanes needs %zu bytes of "
+                                      "LDS, above the %zu a workgroup may take",
+                         bs.b[0], bs.b[1], bs.b[2], bs.nt, dyn + (size_t)blocked_static_lds(bs.nt, rows),
+                         lds_limit());
+    return TOMO_OK;
+}
+
+// Raises a kernel's dynamic-LDS limit when a launch needs more than the
+// default 64 KiB.
+template <class K>
+static int allow_lds(K kernel, size_t dyn)
+{
+    if (dyn <= 65536) return TOMO_OK;
+    return hip_fail(hipFuncSetAttribute(reinterpret_cast<const void *>(kernel),
+                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)dyn),
+                    "dynamic LDS attribute");
+}
+
+template <int NT>
+static int launch_blocked_nt(const Plan &p, const tomo_geometry *g, const BlockDev &bd, const Bundle &bun,
+                             const BlockedShape &bs, size_t lds, const float *images, const KeptRows &kept,
+                             const uint32_t *ymax, float *dst, int acc, bool mm, bool dm, hipStream_t s,
+                             const int *done_flag)
+{
+    int rc = TOMO_OK;
+#define TOMO_LAUNCH_BK4(M, D, O, R)                                                                             \
+    do {                                                                                                        \
+        rc = allow_lds(k_backproject_blocked<NT, M, D, O, R>, lds);                                             \
+        if (!rc)                                                                                                \
+            hipLaunchKernelGGL((k_backproject_blocked<NT, M, D, O, R>), dim3((unsigned)bs.items), dim3(NT), lds, \
+                               s, p.grid, p.views_d, p.frame_views_d, p.frame_voff_d, bd, bun, images,          \
+                               g->map_mask, g->data_mask, kept, ymax, dst, acc, done_flag, p.spill_d);         \
+    } while (0)
 #define TOMO_LAUNCH_BK3(M, D, O)                       \
     do {                                               \
         if (p.bp_rows) TOMO_LAUNCH_BK4(M, D, O, true); \
         else TOMO_LAUNCH_BK4(M, D, O, false);          \
     } while (0)
-#define TOMO_LAUNCH_BK(M, D)                                                                            \
-    do {                                                                                                \
-        if (p.grid.has_sph) TOMO_LAUNCH_BK3(M, D, true);                                                \
-        else TOMO_LAUNCH_BK3(M, D, false);                                                              \
+#define TOMO_LAUNCH_BK(M, D)                             \
+    do {                                                 \
+        if (p.grid.has_sph) TOMO_LAUNCH_BK3(M, D, true); \
+        else TOMO_LAUNCH_BK3(M, D, false);               \
     } while (0)
     if (mm && dm) TOMO_LAUNCH_BK(true, true);
     else if (mm) TOMO_LAUNCH_BK(true, false);
@@ -179,16 +277,65 @@ int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const floa
 #undef TOMO_LAUNCH_BK
 #undef TOMO_LAUNCH_BK3
 #undef TOMO_LAUNCH_BK4
-    int rc = hip_fail(hipGetLastError(), "blocked back-projection kernel launch");
+    return rc ? rc : hip_fail(hipGetLastError(), "blocked back-projection kernel launch");
+}
+
+int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
+                               bool accumulate, bool use_map_mask, hipStream_t s, const int *done_flag,
+                               void *scratch, size_t scratch_bytes, const tomo_tuning &tu)
+{
+    const BlockedShape bs = blocked_shape(p, tu);
+    const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;
+    const size_t need = blocked_scratch_bytes(p, bs, dm);
+    if (!scratch || scratch_bytes < need)
+        return set_error(TOMO_EINVAL, "blocked back-projection: scratch of %zu bytes needed", need);
+    if (bs.items >= ((int64_t)1 << 31)) return set_error(TOMO_EINVAL, "blocked back-projection: too many blocks");
+    size_t lds = 0;
+    int rc = blocked_check_lds(bs, p.bp_rows, &lds);
+    if (rc) return rc;
+    BlockedScratch sc;
+    blocked_layout(p, bs, dm, (char *)scratch, &sc);
+    if (dm)
+        hipLaunchKernelGGL(k_view_absmax<true>, dim3((unsigned)(p.nviews * kYmaxParts)), dim3(kThreads), 0, s,
+                           p.views_d, images, g->data_mask, sc.ymax, done_flag);
+    else
+        hipLaunchKernelGGL(k_view_absmax<false>, dim3((unsigned)(p.nviews * kYmaxParts)), dim3(kThreads), 0, s,
+                           p.views_d, images, g->data_mask, sc.ymax, done_flag);
+    if (sc.kept.cols) {
+        rc = kept_rows_launch(p, p.views_d, p.nviews, g->data_mask, const_cast<uint16_t *>(sc.kept.pre),
+                              const_cast<uint16_t *>(sc.kept.cols), s, done_flag);
+        if (rc) return rc;
+    }
+    BlockDev bd;
+    for (int a = 0; a < 3; ++a) {
+        bd.b[a] = bs.b[a];
+        bd.nb[a] = bs.nb[a];
+    }
+    bd.splits = bs.splits;
+    bd.maxit = bs.b[0] + bs.b[1] + bs.b[2] + 3;
+    const Bundle bun{tu.bp_bundle, tu.bp_xcd_remap};
+    float *dst = bs.splits == 1 ? cube : sc.part;
+    const int acc = accumulate ? 1 : 0;
+    switch (bs.nt) {
+    case 512:
+        rc = launch_blocked_nt<512>(p, g, bd, bun, bs, lds, images, sc.kept, sc.ymax, dst, acc, mm, dm, s, done_flag);
+        break;
+    case 1024:
+        rc = launch_blocked_nt<1024>(p, g, bd, bun, bs, lds, images, sc.kept, sc.ymax, dst, acc, mm, dm, s,
+                                     done_flag);
+        break;
+    default:
+        rc = launch_blocked_nt<256>(p, g, bd, bun, bs, lds, images, sc.kept, sc.ymax, dst, acc, mm, dm, s, done_flag);
+    }
     if (rc || bs.splits == 1) return rc;
     const int64_t total = p.grid.nvox * p.grid.nframes;
     int64_t nb = (total + kThreads - 1) / kThreads;
     nb = nb > 4096 ? 4096 : nb;
     if (mm)
-        hipLaunchKernelGGL(k_sum_owners<true>, dim3((unsigned)nb), dim3(kThreads), 0, s, part, bs.splits, total,
+        hipLaunchKernelGGL(k_sum_owners<true>, dim3((unsigned)nb), dim3(kThreads), 0, s, sc.part, bs.splits, total,
                            p.grid.nvox, g->map_mask, cube, acc, done_flag);
     else
-        hipLaunchKernelGGL(k_sum_owners<false>, dim3((unsigned)nb), dim3(kThreads), 0, s, part, bs.splits, total,
+        hipLaunchKernelGGL(k_sum_owners<false>, dim3((unsigned)nb), dim3(kThreads), 0, s, sc.part, bs.splits, total,
                            p.grid.nvox, g->map_mask, cube, acc, done_flag);
     return hip_fail(hipGetLastError(), "owner sum kernel launch");
 }

@@ -135,6 +135,7 @@ struct Plan {
     int64_t ntiles = 0;          // 16x16 tiles over all views
     int64_t npix = 0;            // total pixels
     int32_t max_steps = 0;       // bound on segments per ray
+    int32_t max_nrow = 0;        // most image rows of any view
     unsigned *spill_d = nullptr; // device counter: binned writes that missed their LDS box
     int32_t *frame_views_d = nullptr;  // device [nviews]: view indices grouped by frame
     int32_t *frame_voff_d = nullptr;   // device [nframes + 1]: offsets into frame_views_d
@@ -155,13 +156,17 @@ struct Plan {
 
 using PlanRef = std::shared_ptr<const Plan>;
 
-// Returns the cached plan for g (building it on first use), or null with the
-// error recorded.  Thread-safe; a plan stays valid while referenced even if
-// the cache is released.
-PlanRef get_plan(const tomo_geometry *g, int *status);
+// Returns the cached plan for g (building it on first use unless build is
+// false), or null with the error recorded.  Thread-safe; a plan stays valid
+// while referenced even if the cache is released.
+PlanRef get_plan(const tomo_geometry *g, int *status, bool build = true);
 
 int set_error(int status, const char *fmt, ...);
 int hip_fail(hipError_t e, const char *what);
+// Stream-ordered scratch from the library's memory pool (freed memory stays
+// mapped for later calls, up to a bound).
+hipError_t scratch_alloc(void **p, size_t bytes, hipStream_t s);
+hipError_t scratch_free(void *p, hipStream_t s);
 int validate_cube(const tomo_cube *c);
 tomo_tuning current_tuning();
 uint64_t size_class_of(const tomo_geometry *g, int64_t npix);
@@ -172,6 +177,9 @@ tomo_tuning tuning_for(const Plan &p);
 // Launchers (siddon.hip)
 int launch_project(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
                    bool use_map_mask, hipStream_t s);
+// The same path with an explicit tuning (the autotuner's candidates).
+int launch_project_with(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
+                        bool use_map_mask, hipStream_t s, const tomo_tuning &tu);
 // scratch: blocked strategy only; when null the launcher takes stream-ordered
 // scratch from the pool for this launch.
 int launch_backproject(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
@@ -196,10 +204,20 @@ struct BlockedShape {
     int32_t b[3];    // block dimensions
     int32_t nb[3];   // blocks per axis
     int32_t splits;  // owners per block
+    int32_t nt;      // lanes per workgroup
     int64_t items;   // workgroups of one launch
 };
 BlockedShape blocked_shape(const Plan &p, const tomo_tuning &tu);
-size_t blocked_scratch_bytes(const Plan &p, const BlockedShape &bs);
+// Scratch of one blocked launch; data_mask: the geometry has a data mask.
+size_t blocked_scratch_bytes(const Plan &p, const BlockedShape &bs, bool data_mask);
+// Static LDS of the blocked kernel for nt lanes (with or without row
+// intervals), and the check that a shape's bins fit beside it (TOMO_EINVAL
+// if not; *dyn_out receives the dynamic LDS bytes).
+int blocked_static_lds(int nt, bool rows);
+int blocked_check_lds(const BlockedShape &bs, bool rows, size_t *dyn_out);
+// Kept-pixel rows of a data mask (one wavefront per image row).
+int kept_rows_launch(const Plan &p, const ViewDev *views, int32_t nviews, const uint8_t *data_mask, uint16_t *pre,
+                     uint16_t *cols, hipStream_t s, const int *done_flag);
 int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
                                bool accumulate, bool use_map_mask, hipStream_t s, const int *done_flag,
                                void *scratch, size_t scratch_bytes, const tomo_tuning &tu);

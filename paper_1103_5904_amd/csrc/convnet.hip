@@ -1,6 +1,8 @@
 // The learned preconditioner network N for flexible CG: three 3x3x3
 // convolutions (1 -> 16 -> 16 -> 1 channels, zero padding 1, ReLU between
-// layers), its MSE training gradient, and Adam.  The paper names
+// layers), its parameter gradients (for an MSE loss, or for any loss given
+// its output gradient: the energy-norm error the preconditioner is trained
+// on), and Adam.  The paper names
 // preconditioning as the untried remedy for slow CG convergence (Sec.
 // "Smooth Temporal Evolution"); the network approximates the inverse of the
 // normal operator on residuals.

@@ -143,6 +143,35 @@ __global__ __launch_bounds__(kThreads) void k_mask_copy(const float *__restrict_
     }
 }
 
+// The bricked copy of M x (every frame): one thread per voxel of a frame,
+// reading the x-fastest cube in order.
+__global__ __launch_bounds__(kThreads) void k_brick_copy(const float *__restrict__ x,
+                                                         const uint8_t *__restrict__ mask, GridDev g, BrickDev bk,
+                                                         float *__restrict__ out, const int *__restrict__ done_flag)
+{
+    if (done_flag && *done_flag) return;
+    const int32_t nx = g.n[0], ny = g.n[1];
+    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < g.nvox; v += (int64_t)gridDim.x * kThreads) {
+        const int32_t i0 = (int32_t)(v % nx), r = (int32_t)(v / nx);
+        const int32_t i1 = r % ny, i2 = r / ny;
+        const int64_t o = brick_offset(bk, i0, i1, i2);
+        const bool keep = !mask || mask[v] != 0;
+        for (int32_t f = 0; f < g.nframes; ++f)
+            out[(int64_t)f * bk.frame_stride + o] = keep ? x[(int64_t)f * g.nvox + v] : 0.0f;
+    }
+}
+
+template <bool kDataMask, bool kObstacle>
+__global__ __launch_bounds__(kThreads) void k_project_bricked(
+    GridDev g, const ViewDev *__restrict__ views, int32_t nviews, Bundle bun, int32_t maxit,
+    const float *__restrict__ bricked, BrickDev bk, const uint8_t *__restrict__ data_mask,
+    float *__restrict__ images, const int *__restrict__ done_flag)
+{
+    if (done_flag && *done_flag) return;
+    project_tile_bricked<kDataMask, kObstacle>(g, views, nviews, bun.log2_bw, block_tile(bun), maxit, bricked, bk,
+                                               data_mask, images);
+}
+
 // ------------------------------------------------------------ launchers
 
 static int64_t grid_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
@@ -182,30 +211,92 @@ int launch_project_tuned(const Plan &p, const tomo_geometry *g, const float *cub
 int launch_project(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
                    bool use_map_mask, hipStream_t s)
 {
+    return launch_project_with(p, g, cube, images, use_map_mask, s, tuning_for(p));
+}
+
+// The bricked layout of a plan's frames for brick side 2^k, or false when a
+// padded frame would not be addressable with 32-bit element offsets.
+static bool brick_layout(const Plan &p, int k, BrickDev &bk)
+{
+    const int B = 1 << k;
+    bk.k = k;
+    int64_t stride = (int64_t)B * B * B;
+    for (int a = 0; a < 3; ++a) {
+        bk.nb[a] = (p.grid.n[a] + B - 1) / B;
+        stride *= bk.nb[a];
+    }
+    bk.frame_stride = stride;
+    return stride < ((int64_t)1 << 32);
+}
+
+int launch_project_bricked(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
+                           bool use_map_mask, hipStream_t s, const int *done_flag, const tomo_tuning &tu)
+{
+    BrickDev bk;
+    float *br = nullptr;
+    if (!brick_layout(p, tu.p_layout, bk) ||
+        scratch_alloc((void **)&br, sizeof(float) * (size_t)(bk.frame_stride * p.grid.nframes), s) != hipSuccess) {
+        (void)hipGetLastError();  // no bricked copy: the x-fastest walk gives the same result
+        tomo_tuning lin = tu;
+        lin.p_layout = 0;
+        return launch_project_tuned(p, g, cube, images, use_map_mask, s, done_flag, lin);
+    }
+    const uint8_t *mm = use_map_mask ? g->map_mask : nullptr;
+    int64_t nb = grid_blocks(p.grid.nvox);
+    nb = nb > 8192 ? 8192 : nb;
+    hipLaunchKernelGGL(k_brick_copy, dim3((unsigned)nb), dim3(kThreads), 0, s, cube, mm, p.grid, bk, br, done_flag);
+    int rc = hip_fail(hipGetLastError(), "brick copy launch");
+    if (!rc) {
+        const Bundle b{tu.p_bundle, tu.p_xcd_remap};
+        const bool dm = g->data_mask != nullptr;
+        const dim3 grid((unsigned)p.ntiles), blk(kThreads);
+#define TOMO_LAUNCH_PB(D, O)                                                                                   \
+    hipLaunchKernelGGL((k_project_bricked<D, O>), grid, blk, 0, s, p.grid, p.views_d, p.nviews, b, p.max_steps, \
+                       br, bk, g->data_mask, images, done_flag)
+        if (dm) {
+            if (p.grid.has_sph) TOMO_LAUNCH_PB(true, true);
+            else TOMO_LAUNCH_PB(true, false);
+        } else {
+            if (p.grid.has_sph) TOMO_LAUNCH_PB(false, true);
+            else TOMO_LAUNCH_PB(false, false);
+        }
+#undef TOMO_LAUNCH_PB
+        rc = hip_fail(hipGetLastError(), "bricked projection kernel launch");
+    }
+    (void)scratch_free(br, s);
+    return rc;
+}
+
+int launch_project_with(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
+                        bool use_map_mask, hipStream_t s, const tomo_tuning &tu)
+{
+    if (tu.p_layout >= 2) return launch_project_bricked(p, g, cube, images, use_map_mask, s, nullptr, tu);
     if (use_map_mask && g->map_mask) {
         // P M x as the unmasked walk over a masked copy (stream-ordered
         // scratch); without the memory, the walk tests the mask itself
         float *tmp = nullptr;
         const int64_t total = p.grid.nvox * p.grid.nframes;
-        if (hipMallocAsync((void **)&tmp, sizeof(float) * (size_t)total, s) == hipSuccess) {
+        if (scratch_alloc((void **)&tmp, sizeof(float) * (size_t)total, s) == hipSuccess) {
             int64_t nb = grid_blocks(p.grid.nvox);
             nb = nb > 4096 ? 4096 : nb;
             hipLaunchKernelGGL(k_mask_copy, dim3((unsigned)nb), dim3(kThreads), 0, s, cube, g->map_mask,
                                p.grid.nvox, (int32_t)p.grid.nframes, tmp);
             int rc = hip_fail(hipGetLastError(), "mask copy launch");
-            if (!rc) rc = launch_project_tuned(p, g, tmp, images, false, s, nullptr, tuning_for(p));
-            (void)hipFreeAsync(tmp, s);
+            if (!rc) rc = launch_project_tuned(p, g, tmp, images, false, s, nullptr, tu);
+            (void)scratch_free(tmp, s);
             return rc;
         }
         (void)hipGetLastError();  // the failed allocation's error is not the caller's
     }
-    return launch_project_tuned(p, g, cube, images, use_map_mask, s, nullptr, tuning_for(p));
+    return launch_project_tuned(p, g, cube, images, use_map_mask, s, nullptr, tu);
 }
 
 int launch_project_flagged(const Plan &p, const tomo_geometry *g, const float *cube,
                            float *images, hipStream_t s, const int *done_flag)
 {
-    return launch_project_tuned(p, g, cube, images, false, s, done_flag, tuning_for(p));
+    const tomo_tuning tu = tuning_for(p);
+    if (tu.p_layout >= 2) return launch_project_bricked(p, g, cube, images, false, s, done_flag, tu);
+    return launch_project_tuned(p, g, cube, images, false, s, done_flag, tu);
 }
 
 int resolve_bp_strategy(const Plan &p, int strategy)
@@ -231,13 +322,13 @@ int launch_backproject_tuned(const Plan &p, const tomo_geometry *g, const float 
         if (scratch)
             return launch_backproject_blocked(p, g, images, cube, accumulate, use_map_mask, s, done_flag,
                                               scratch, scratch_bytes, tu);
-        const size_t need = blocked_scratch_bytes(p, blocked_shape(p, tu));
+        const size_t need = blocked_scratch_bytes(p, blocked_shape(p, tu), g->data_mask != nullptr);
         void *tmp = nullptr;
-        if (hipMallocAsync(&tmp, need, s) != hipSuccess)
+        if (scratch_alloc(&tmp, need, s) != hipSuccess)
             return set_error(TOMO_ENOMEM, "back-projection scratch of %zu bytes", need);
         const int rc = launch_backproject_blocked(p, g, images, cube, accumulate, use_map_mask, s,
                                                   done_flag, tmp, need, tu);
-        (void)hipFreeAsync(tmp, s);
+        (void)scratch_free(tmp, s);
         return rc;
     }
     // the atomic kernels address a frame through a buffer resource, whose
@@ -276,7 +367,7 @@ extern "C" int tomo_count_crossings(const tomo_geometry *g, int64_t *total_h, to
     if (!p) return st;
     hipStream_t s = (hipStream_t)stream;
     unsigned long long *d = nullptr;
-    if (hipMallocAsync((void **)&d, sizeof(*d), s) != hipSuccess)
+    if (scratch_alloc((void **)&d, sizeof(*d), s) != hipSuccess)
         return set_error(TOMO_ENOMEM, "tomo_count_crossings: device allocation failed");
     (void)hipMemsetAsync(d, 0, sizeof(*d), s);
     const tomo_tuning tu = tuning_for(*p);
@@ -291,7 +382,7 @@ extern "C" int tomo_count_crossings(const tomo_geometry *g, int64_t *total_h, to
     unsigned long long h = 0;
     if (!rc) rc = hip_fail(hipMemcpyAsync(&h, d, sizeof(h), hipMemcpyDeviceToHost, s), "copy count");
     if (!rc) rc = hip_fail(hipStreamSynchronize(s), "count synchronise");
-    (void)hipFreeAsync(d, s);
+    (void)scratch_free(d, s);
     if (!rc) *total_h = (int64_t)h;
     return rc;
 }

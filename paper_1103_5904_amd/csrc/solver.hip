@@ -637,13 +637,13 @@ struct SolveBuffers {
     void *alloc(size_t bytes)
     {
         void *p = nullptr;
-        if (hipMallocAsync(&p, bytes, s) != hipSuccess) return nullptr;
+        if (scratch_alloc(&p, bytes, s) != hipSuccess) return nullptr;
         ptrs.push_back(p);
         return p;
     }
     ~SolveBuffers()
     {
-        for (void *p : ptrs) (void)hipFreeAsync(p, s);
+        for (void *p : ptrs) (void)scratch_free(p, s);
     }
 };
 
@@ -768,7 +768,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     size_t bscr_bytes = 0;
     void *bscr = nullptr;
     if (bps == TOMO_BP_BLOCKED) {
-        bscr_bytes = blocked_scratch_bytes(*plan, blocked_shape(*plan, tuning_for(*plan)));
+        bscr_bytes = blocked_scratch_bytes(*plan, blocked_shape(*plan, tuning_for(*plan)), g->data_mask != nullptr);
         bscr = buf.alloc(bscr_bytes);
         if (!bscr) return set_error(TOMO_ENOMEM, "tomo_cg_solve: device allocation failed");
     }
@@ -942,7 +942,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         if (!rc) rc = hip_fail(hipStreamSynchronize(s), "cg synchronise");
         if (rc) return rc;
         true_rel = hst->bb > 0 ? sqrt(hst->aux / hst->bb) : 0.0;
-        const bool unconfirmed = prm->rtol > 0 && true_rel > 1.1 * prm->rtol;
+        const bool unconfirmed = prm->rtol > 0 && true_rel > prm->rtol;
         if (!unconfirmed || done_iters >= maxit || restarts >= 8) break;
         // restart from the true residual
         ++restarts;
@@ -968,7 +968,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     rep->rel_res = hst->bb > 0 ? sqrt(hst->res2 / hst->bb) : 0.0;
     rep->true_rel_res = true_rel;
     if (hst->nonfinite) rep->status = TOMO_ENONFINITE;
-    else if (prm->rtol > 0 && !(true_rel <= 1.1 * prm->rtol)) rep->status = TOMO_ENOCONV;
+    else if (prm->rtol > 0 && !(true_rel <= prm->rtol)) rep->status = TOMO_ENOCONV;
     else rep->status = TOMO_OK;
     rep->history_len = 0;
     if (rep->history && rep->history_cap > 0) {
@@ -1176,21 +1176,57 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
     rc = hip_fail(hipGetLastError(), "batched cg start");
     if (rc) return rc;
 
-    // one iteration of every system
-    auto enqueue_iteration = [&](hipStream_t st) -> int {
+    // Kernel timing: three events per iteration slot of a check interval
+    // (before the batched P, between it and the batched P^T, after it),
+    // read after every interval.  In a graph they are event-record nodes,
+    // recorded again at every replay.
+    bool timed = rep[0].time_kernels != 0;
+    EventPool evp;
+    std::vector<hipEvent_t> slot_ev;
+    if (timed) {
+        for (int i = 0; i < 3 * chunk; ++i) {
+            hipEvent_t e = evp.get();
+            if (!e) return set_error(TOMO_EHIP, "tomo_batch_cg_solve: event creation failed");
+            slot_ev.push_back(e);
+        }
+    }
+    double ms_p = 0.0, ms_b = 0.0;
+    int slots_used = 0;  // slots recorded since the last read
+    auto read_slots = [&]() -> int {  // after a synchronisation
+        for (int i = 0; i < slots_used; ++i) {
+            float a = 0.f, b2 = 0.f;
+            int e = hip_fail(hipEventElapsedTime(&a, slot_ev[(size_t)(3 * i)], slot_ev[(size_t)(3 * i + 1)]),
+                             "timing event read");
+            if (!e)
+                e = hip_fail(hipEventElapsedTime(&b2, slot_ev[(size_t)(3 * i + 1)], slot_ev[(size_t)(3 * i + 2)]),
+                             "timing event read");
+            if (e) return e;
+            ms_p += a;
+            ms_b += b2;
+        }
+        slots_used = 0;
+        return TOMO_OK;
+    };
+
+    // the three parts of one iteration of every system
+    auto part_p = [&](hipStream_t st) -> int {
         Operands o = ops_of(true);
         for (int k = 0; k < ns; ++k) {
             o.src[k] = sy[(size_t)k].p;
             o.dst[k] = sy[(size_t)k].img;
         }
-        int e = batch_project_ops(bt, o, st);
+        return batch_project_ops(bt, o, st);
+    };
+    auto part_bp = [&](hipStream_t st) -> int {
+        Operands o = ops_of(true);
         for (int k = 0; k < ns; ++k) {
             o.src[k] = sy[(size_t)k].img;
             o.dst[k] = sy[(size_t)k].q;
         }
         o.acc = 1;
-        if (!e) e = batch_backproject_ops(bt, o, st);
-        if (e) return e;
+        return batch_backproject_ops(bt, o, st);
+    };
+    auto part_vec = [&](hipStream_t st) -> int {
         for (int k = 0; k < ns; ++k) {
             Sys &c = sy[(size_t)k];
             if (c.skip) continue;
@@ -1201,30 +1237,95 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
         }
         return hip_fail(hipGetLastError(), "batched cg iteration launch");
     };
+    auto enqueue_iteration = [&](hipStream_t st, int slot) -> int {  // direct launches
+        auto mark = [&](int j) {
+            return timed ? hip_fail(hipEventRecord(slot_ev[(size_t)(3 * slot + j)], st), "timing event record")
+                         : TOMO_OK;
+        };
+        int e = mark(0);
+        if (!e) e = part_p(st);
+        if (!e) e = mark(1);
+        if (!e) e = part_bp(st);
+        if (!e) e = mark(2);
+        if (!e) e = part_vec(st);
+        return e;
+    };
 
-    // the check interval as a graph
+    // The check interval as a graph, built node by node: each part is
+    // captured on a private stream (the caller's may be the null stream) as
+    // a child graph, chained behind the previous node, with the timing
+    // events as event-record nodes between the parts.  Replayed on the
+    // caller's stream.
     struct GraphGuard {
         hipStream_t cs = nullptr;
+        hipGraph_t graph = nullptr;
+        std::vector<hipGraph_t> children;
         hipGraphExec_t exec = nullptr;
-        ~GraphGuard()
+        void clear()
         {
             if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            for (hipGraph_t c : children) (void)hipGraphDestroy(c);
+            exec = nullptr;
+            graph = nullptr;
+            children.clear();
+        }
+        ~GraphGuard()
+        {
+            clear();
             if (cs) (void)hipStreamDestroy(cs);
         }
     } gg;
+    auto build_graph = [&](bool with_events) -> int {
+        gg.clear();
+        int e = hip_fail(hipGraphCreate(&gg.graph, 0), "graph create");
+        hipGraphNode_t prev = nullptr;
+        auto add_part = [&](auto &&part) -> int {
+            hipGraph_t child = nullptr;
+            int r = hip_fail(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal), "begin capture");
+            if (r) return r;
+            const int cap = part(gg.cs);
+            r = hip_fail(hipStreamEndCapture(gg.cs, &child), "end capture");
+            if (child) gg.children.push_back(child);
+            if (!r && cap) r = cap;
+            hipGraphNode_t node = nullptr;
+            if (!r)
+                r = hip_fail(hipGraphAddChildGraphNode(&node, gg.graph, prev ? &prev : nullptr, prev ? 1 : 0, child),
+                             "child graph node");
+            if (!r) prev = node;
+            return r;
+        };
+        auto add_event = [&](int slot, int j) -> int {
+            if (!with_events) return TOMO_OK;
+            hipGraphNode_t node = nullptr;
+            const int r = hip_fail(hipGraphAddEventRecordNode(&node, gg.graph, prev ? &prev : nullptr, prev ? 1 : 0,
+                                                              slot_ev[(size_t)(3 * slot + j)]),
+                                   "event record node");
+            if (!r) prev = node;
+            return r;
+        };
+        for (int i = 0; i < chunk && !e; ++i) {
+            e = add_event(i, 0);
+            if (!e) e = add_part(part_p);
+            if (!e) e = add_event(i, 1);
+            if (!e) e = add_part(part_bp);
+            if (!e) e = add_event(i, 2);
+            if (!e) e = add_part(part_vec);
+        }
+        if (!e) e = hip_fail(hipGraphInstantiate(&gg.exec, gg.graph, nullptr, nullptr, 0), "graph instantiate");
+        return e;
+    };
+    bool timing_lost = false;  // the graph could not hold the timing events
     if (use_graph) {
-        // capture on a private stream (the caller's may be the null stream),
-        // replay on the caller's
         rc = hip_fail(hipStreamCreateWithFlags(&gg.cs, hipStreamNonBlocking), "capture stream");
-        if (!rc) rc = hip_fail(hipStreamBeginCapture(gg.cs, hipStreamCaptureModeThreadLocal), "begin capture");
         if (rc) return rc;
-        int cap_rc = TOMO_OK;
-        for (int i = 0; i < chunk && !cap_rc; ++i) cap_rc = enqueue_iteration(gg.cs);
-        hipGraph_t graph = nullptr;
-        rc = hip_fail(hipStreamEndCapture(gg.cs, &graph), "end capture");
-        if (!rc && cap_rc) rc = cap_rc;
-        if (!rc) rc = hip_fail(hipGraphInstantiate(&gg.exec, graph, nullptr, nullptr, 0), "graph instantiate");
-        if (graph) (void)hipGraphDestroy(graph);
+        rc = build_graph(timed);
+        if (rc && timed) {  // without the events, the iterations are still timed as a whole by the caller
+            (void)hipGetLastError();
+            timed = false;
+            timing_lost = true;
+            rc = build_graph(false);
+        }
         if (rc) return rc;
     }
 
@@ -1233,9 +1334,11 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
             if (gg.exec) {
                 rc = hip_fail(hipGraphLaunch(gg.exec, s), "graph launch");
             } else {
-                for (int i = 0; i < chunk && !rc; ++i) rc = enqueue_iteration(s);
+                for (int i = 0; i < chunk && !rc; ++i) rc = enqueue_iteration(s, i);
             }
+            if (timed) slots_used = chunk;
             if (!rc) rc = pull_states();
+            if (!rc && timed) rc = read_slots();
             if (rc) return rc;
             bool all = true;
             for (int k = 0; k < ns; ++k) all = all && (sy[(size_t)k].skip || hst[k].done);
@@ -1256,7 +1359,7 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
             Sys &c = sy[(size_t)k];
             if (c.skip || hst[k].nonfinite) continue;
             c.true_rel = hst[k].bb > 0 ? sqrt(hst[k].aux / hst[k].bb) : 0.0;
-            const bool unconfirmed = c.rtol > 0 && c.true_rel > 1.1 * c.rtol;
+            const bool unconfirmed = c.rtol > 0 && c.true_rel > c.rtol;
             if (unconfirmed && hst[k].iter < c.maxit && c.restarts < 8) {
                 ++c.restarts;
                 restarted = true;
@@ -1291,7 +1394,7 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
         r.rel_res = h.bb > 0 ? sqrt(h.res2 / h.bb) : 0.0;
         r.true_rel_res = c.true_rel;
         if (h.nonfinite) r.status = TOMO_ENONFINITE;
-        else if (c.rtol > 0 && !(c.true_rel <= 1.1 * c.rtol)) r.status = TOMO_ENOCONV;
+        else if (c.rtol > 0 && !(c.true_rel <= c.rtol)) r.status = TOMO_ENOCONV;
         else r.status = TOMO_OK;
         r.history_len = 0;
         if (hist_h && cap > 0) {
@@ -1300,7 +1403,9 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
             if (rc) return rc;
             r.history_len = nh;
         }
-        r.ms_project = r.ms_backproject = 0.0;
+        r.ms_project = timing_lost ? NAN : ms_p;
+        r.ms_backproject = timing_lost ? NAN : ms_b;
+        r.time_kernels = rep[0].time_kernels;
     }
     return TOMO_OK;
 }

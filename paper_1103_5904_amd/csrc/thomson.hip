@@ -178,13 +178,13 @@ struct Scratch {
     void *take(size_t bytes)
     {
         void *q = nullptr;
-        if (hipMallocAsync(&q, bytes, s) != hipSuccess) return nullptr;
+        if (scratch_alloc(&q, bytes, s) != hipSuccess) return nullptr;
         p.push_back(q);
         return q;
     }
     ~Scratch()
     {
-        for (void *q : p) (void)hipFreeAsync(q, s);
+        for (void *q : p) (void)scratch_free(q, s);
     }
 };
 

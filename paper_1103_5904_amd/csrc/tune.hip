@@ -1,24 +1,32 @@
 // Launch autotuner.
 //
 // The best launch shape depends on the geometry: pixels per voxel decide
-// how many rays share a voxel block, the cube side how long the walks are,
-// the view count how much work one owner of a block gets.  The autotuner
-// times every candidate on the caller's geometry with synthetic data (all
-// ones: the walks are what costs, and zero pixels would be skipped), keeps
-// the fastest P shape and the fastest P^T strategy and shape, and files them
-// under the geometry's size class: the cube side, the pixels per view and
-// the view count, each rounded up to a power of two, and whether the cube has
-// frames.  Every later launch on a geometry of the same class uses that
-// entry (tuning_for); other classes keep the process-wide tuning.
+// how many rays share a voxel block, the cube side how long the walks are
+// and how far they stray from the caches, the view count how much work one
+// owner of a block gets.  The autotuner times the candidates on the caller's
+// geometry and data (or, without data, on a cube of ones and its own
+// projection, whose zero pattern is the real one: masked pixels and rays
+// that miss the box are 0), through the same launch paths the library's
+// calls take (scratch from the library's pool included), and files the
+// winners under the geometry's size class: the cube side, the pixels per view
+// and the view count, each rounded up to a power of two, and whether the
+// cube has frames.  Every later launch on a geometry of the same class uses
+// that entry (tuning_for); other classes keep the process-wide tuning.
 //
-// Candidates: P - the four wavefront bundles x XCD remap on/off; P^T - the
-// owner-computes strategy over seven block shapes (flat to cubic), two owner
-// counts and the XCD remap on/off, the LDS-binned strategy over three
-// bundles, and the atomic one.
-// The workgroup size is not searched (every kernel is built for 256 lanes,
-// four wavefronts), nor is the cube layout (x fastest is the ABI's).
+// Candidates: P - the four wavefront bundles x XCD remap on/off x the cube
+// layouts (x-fastest, bricks of 4, 8 and 16 voxels a side); P^T - the
+// owner-computes strategy over block shapes for workgroups of 256, 512 and
+// 1024 lanes (larger workgroups own larger blocks, so a ray is set up for
+// fewer of them), two owner counts and the XCD remap on/off, the LDS-binned
+// strategy over three bundles, and the atomic one.
+//
+// Each candidate is screened over `reps` launches; the fastest P and P^T
+// candidates are then timed against the process-wide tuning in alternation
+// (five rounds, medians), and a candidate is kept only if it beats that
+// tuning there by 1%: the tuner never files a pick slower than the default.
 #include <math.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -53,6 +61,19 @@ struct Timer {
     }
 };
 
+// Block shapes per workgroup size: flat ones suit lines of sight near one
+// plane (solar observers near the ecliptic), cubic ones views from all
+// directions.  The bins take 8 bytes per voxel of the LDS a workgroup has.
+struct Shape {
+    int nt, b[3];
+};
+const Shape kShapes[] = {
+    {256, {64, 32, 2}},  {256, {64, 64, 1}},  {256, {64, 16, 4}},  {256, {32, 32, 4}},  {256, {32, 16, 8}},
+    {256, {16, 32, 8}},  {256, {16, 16, 16}}, {512, {64, 64, 2}},  {512, {128, 32, 2}}, {512, {64, 32, 4}},
+    {512, {32, 32, 8}},  {512, {16, 16, 32}}, {1024, {128, 64, 2}}, {1024, {64, 64, 4}}, {1024, {128, 128, 1}},
+    {1024, {32, 32, 16}},
+};
+
 }  // namespace
 
 uint64_t size_class_of(const tomo_geometry *g, int64_t npix)
@@ -75,49 +96,48 @@ tomo_tuning tuning_for(const Plan &p)
     return current_tuning();
 }
 
-}  // namespace tomo
-
-using namespace tomo;
-
-extern "C" {
-
-int tomo_autotune(const tomo_geometry *g, int32_t reps, tomo_tuning *out, tomo_stream stream)
+static int autotune_impl(const tomo_geometry *g, const float *cube_in, const float *img_in, int32_t reps,
+                         tomo_tuning *out, hipStream_t s)
 {
     if (reps < 1 || reps > 100) return set_error(TOMO_EINVAL, "tomo_autotune: reps must be in [1, 100]");
     int st = TOMO_OK;
     PlanRef plan = get_plan(g, &st);
     if (!plan) return st;
     const Plan &p = *plan;
-    hipStream_t s = (hipStream_t)stream;
     const int64_t nvox = p.grid.nvox * p.grid.nframes;
+    const bool wide = p.grid.nvox >= ((int64_t)1 << 30);  // the atomic strategies refuse such frames
 
     // candidates
     const tomo_tuning base = current_tuning();
     std::vector<tomo_tuning> pc, bc;
-    for (int bun : {0, 2, 3, 4})
-        for (int xr : {0, 1}) {
-            tomo_tuning t = base;
-            t.p_bundle = bun;
-            t.p_xcd_remap = xr;
-            pc.push_back(t);
-        }
-    // flat blocks suit lines of sight near one plane (solar observers near the
-    // ecliptic); cubic ones suit views from all directions
-    const int blocks[7][3] = {{64, 32, 2}, {64, 64, 1}, {64, 16, 4}, {32, 32, 4},
-                              {32, 16, 8}, {16, 32, 8}, {16, 16, 16}};
-    for (const auto &b : blocks)
+    for (int lay : {0, 2, 3, 4})
+        for (int bun : {0, 2, 3, 4})
+            for (int xr : {0, 1}) {
+                tomo_tuning t = base;
+                t.p_bundle = bun;
+                t.p_xcd_remap = xr;
+                t.p_layout = lay;
+                pc.push_back(t);
+            }
+    for (const Shape &sh : kShapes)
         for (int sp : {0, 8})
             for (int xr : {0, 1}) {  // (the blocked kernel takes no bundle shape)
                 tomo_tuning t = base;
                 t.bp_default = TOMO_BP_BLOCKED;
-                t.bp_block[0] = b[0];
-                t.bp_block[1] = b[1];
-                t.bp_block[2] = b[2];
+                t.bp_threads = sh.nt;
+                t.bp_block[0] = sh.b[0];
+                t.bp_block[1] = sh.b[1];
+                t.bp_block[2] = sh.b[2];
                 t.bp_splits = sp;
                 t.bp_xcd_remap = xr;
+                const BlockedShape bs = blocked_shape(p, t);
+                if (blocked_check_lds(bs, p.bp_rows, nullptr) != TOMO_OK) {
+                    (void)set_error(TOMO_OK, "");  // a shape this device cannot hold: not a candidate
+                    continue;
+                }
                 bc.push_back(t);
             }
-    if (p.grid.nvox < ((int64_t)1 << 30)) {  // the atomic strategies' frame limit
+    if (!wide) {
         for (int bun : {2, 3, 4}) {
             tomo_tuning t = base;
             t.bp_default = TOMO_BP_BINNED;
@@ -128,109 +148,156 @@ int tomo_autotune(const tomo_geometry *g, int32_t reps, tomo_tuning *out, tomo_s
         t.bp_default = TOMO_BP_ATOMIC;
         bc.push_back(t);
     }
+    // the process-wide tuning's P^T strategy may refuse this frame: then
+    // the first blocked candidate stands in for it
+    const tomo_tuning base_b = base.bp_default != TOMO_BP_BLOCKED && wide ? bc.front() : base;
 
-    // synthetic operands and the largest scratch any candidate (or the
-    // current tuning) needs
-    size_t scratch_bytes = blocked_scratch_bytes(p, blocked_shape(p, base));
-    for (const auto &t : bc) {
-        const size_t b = blocked_scratch_bytes(p, blocked_shape(p, t));
-        scratch_bytes = b > scratch_bytes ? b : scratch_bytes;
-    }
+    // operands: the caller's, or a cube of ones and its projection
     float *cube = nullptr, *img = nullptr;
-    void *scratch = nullptr;
-    if (hipMallocAsync((void **)&cube, sizeof(float) * (size_t)nvox, s) != hipSuccess ||
-        hipMallocAsync((void **)&img, sizeof(float) * (size_t)p.npix, s) != hipSuccess ||
-        hipMallocAsync(&scratch, scratch_bytes, s) != hipSuccess) {
-        if (cube) (void)hipFreeAsync(cube, s);
-        if (img) (void)hipFreeAsync(img, s);
-        return set_error(TOMO_ENOMEM, "tomo_autotune: device allocation failed");
+    if (!cube_in || !img_in) {
+        if (scratch_alloc((void **)&cube, sizeof(float) * (size_t)nvox, s) != hipSuccess ||
+            scratch_alloc((void **)&img, sizeof(float) * (size_t)p.npix, s) != hipSuccess) {
+            (void)scratch_free(cube, s);
+            return set_error(TOMO_ENOMEM, "tomo_autotune: device allocation failed");
+        }
     }
     struct Release {
         hipStream_t s;
-        void *a, *b, *c;
+        void *a, *b;
         ~Release()
         {
-            (void)hipFreeAsync(a, s);
-            (void)hipFreeAsync(b, s);
-            (void)hipFreeAsync(c, s);
+            (void)scratch_free(a, s);
+            (void)scratch_free(b, s);
         }
-    } release{s, cube, img, scratch};
-    int rc = launch_fill(cube, nvox, 1.0f, s);
-    if (!rc) rc = launch_fill(img, p.npix, 1.0f, s);
-    if (rc) return rc;
+    } release{s, cube, img};
+    const float *xc = cube_in ? cube_in : cube;
+    const float *yc = img_in ? img_in : img;
+    // the work buffers the candidates write into: the image and the cube of
+    // the synthetic operands are refilled after the candidates have run
+    float *img_w = nullptr, *cube_w = nullptr;
+    if (scratch_alloc((void **)&img_w, sizeof(float) * (size_t)p.npix, s) != hipSuccess ||
+        scratch_alloc((void **)&cube_w, sizeof(float) * (size_t)nvox, s) != hipSuccess) {
+        (void)scratch_free(img_w, s);
+        return set_error(TOMO_ENOMEM, "tomo_autotune: device allocation failed");
+    }
+    Release release_w{s, img_w, cube_w};
+    int rc = TOMO_OK;
+    if (!cube_in || !img_in) {
+        rc = launch_fill(cube, nvox, 1.0f, s);
+        if (!rc) rc = launch_project_with(p, g, cube, img, true, s, base);
+        if (rc) return rc;
+    }
 
     Timer tm;
     if (!tm.a || !tm.b) return set_error(TOMO_EHIP, "tomo_autotune: event creation failed");
-    auto time_it = [&](auto &&launch, float &ms) -> int {
-        int e = launch();  // warm-up
-        for (int k = 0; k < reps && !e; ++k) {
-            if (k == 0) e = hip_fail(hipEventRecord(tm.a, s), "event record");
-            if (!e) e = launch();
-        }
+    // ms per launch over n launches after one untimed one
+    auto time_it = [&](auto &&launch, int n, float &ms) -> int {
+        int e = launch();
+        if (!e) e = hip_fail(hipEventRecord(tm.a, s), "event record");
+        for (int k = 0; k < n && !e; ++k) e = launch();
         if (!e) e = hip_fail(hipEventRecord(tm.b, s), "event record");
         if (!e) e = hip_fail(hipEventSynchronize(tm.b), "event synchronise");
         if (!e) e = hip_fail(hipEventElapsedTime(&ms, tm.a, tm.b), "event time");
+        ms /= (float)n;
         return e;
     };
-    // bring the clocks up before anything is timed: the current tuning's P
-    // (and P^T, unless this geometry refuses its strategy) repeated for at
-    // least 30 ms; then the current tuning is the one to beat, by at least 2%
-    // (differences below that are within the timing noise)
-    const tomo_tuning base_b = base.bp_default != TOMO_BP_BLOCKED && p.grid.nvox >= ((int64_t)1 << 30)
-                                   ? bc.front()  // a blocked candidate: the atomic strategies refuse this frame
-                                   : base;
-    float best_p = INFINITY, best_b = INFINITY;
-    tomo_tuning win = base;
+    auto run_p = [&](const tomo_tuning &t) { return launch_project_with(p, g, xc, img_w, true, s, t); };
+    auto run_b = [&](const tomo_tuning &t) {
+        return launch_backproject_tuned(p, g, yc, cube_w, false, true, t.bp_default, s, nullptr, nullptr, 0, t);
+    };
+    // bring the clocks up before anything is timed: the process-wide
+    // tuning's P and P^T repeated for at least 30 ms
     {
         float warm = 0.f, a = 0.f, b = 0.f;
         for (int k = 0; k < 64 && warm < 30.f; ++k) {
-            rc = time_it([&] { return launch_project_tuned(p, g, cube, img, true, s, nullptr, base); }, a);
-            if (!rc)
-                rc = time_it([&] {
-                    return launch_backproject_tuned(p, g, img, cube, false, true, base_b.bp_default, s, nullptr,
-                                                    scratch, scratch_bytes, base_b);
-                }, b);
+            rc = time_it([&] { return run_p(base); }, 1, a);
+            if (!rc) rc = time_it([&] { return run_b(base_b); }, 1, b);
             if (rc) return rc;
             warm += a + b;
         }
-        best_p = 0.98f * a;
-        if (base_b.bp_default == base.bp_default) best_b = 0.98f * b;  // else a candidate must set it
     }
-    for (const auto &t : pc) {
-        float ms = 0.f;
-        rc = time_it([&] { return launch_project_tuned(p, g, cube, img, true, s, nullptr, t); }, ms);
-        if (rc) return rc;
-        if (ms < best_p) {
-            best_p = ms;
-            win.p_bundle = t.p_bundle;
-            win.p_xcd_remap = t.p_xcd_remap;
+    // screening
+    auto best_of = [&](const std::vector<tomo_tuning> &cands, auto &&run, tomo_tuning &win) -> int {
+        float best = INFINITY;
+        for (const auto &t : cands) {
+            float ms = 0.f;
+            const int e = time_it([&] { return run(t); }, reps, ms);
+            if (e) return e;
+            if (ms < best) {
+                best = ms;
+                win = t;
+            }
         }
-    }
-    for (const auto &t : bc) {
-        float ms = 0.f;
-        rc = time_it([&] {
-            return launch_backproject_tuned(p, g, img, cube, false, true, t.bp_default, s, nullptr, scratch,
-                                            scratch_bytes, t);
-        }, ms);
-        if (rc) return rc;
-        if (ms < best_b) {
-            best_b = ms;
-            win.bp_default = t.bp_default;
-            win.bp_bundle = t.bp_bundle;
-            win.bp_xcd_remap = t.bp_xcd_remap;
-            win.bp_block[0] = t.bp_block[0];
-            win.bp_block[1] = t.bp_block[1];
-            win.bp_block[2] = t.bp_block[2];
-            win.bp_splits = t.bp_splits;
-            win.bp_lds_bins = t.bp_lds_bins;
+        return TOMO_OK;
+    };
+    tomo_tuning win_p = base, win_b = base_b;
+    rc = best_of(pc, run_p, win_p);
+    if (!rc) rc = best_of(bc, run_b, win_b);
+    if (rc) return rc;
+    // confirmation against the process-wide tuning, in alternation: medians
+    // of five rounds each; a winner must beat it by 1%
+    auto confirm = [&](auto &&run, const tomo_tuning &cand, const tomo_tuning &ref, bool &keep) -> int {
+        std::vector<float> tc, tr;
+        for (int round = 0; round < 5; ++round) {
+            float a = 0.f, b = 0.f;
+            int e = time_it([&] { return run(ref); }, reps, a);
+            if (!e) e = time_it([&] { return run(cand); }, reps, b);
+            if (e) return e;
+            tr.push_back(a);
+            tc.push_back(b);
         }
+        std::sort(tc.begin(), tc.end());
+        std::sort(tr.begin(), tr.end());
+        keep = tc[2] < 0.99f * tr[2];
+        return TOMO_OK;
+    };
+    bool keep_p = false, keep_b = false;
+    rc = confirm(run_p, win_p, base, keep_p);
+    if (!rc) {
+        if (base_b.bp_default == base.bp_default) rc = confirm(run_b, win_b, base_b, keep_b);
+        else keep_b = true;  // the process-wide strategy cannot run here
     }
+    if (rc) return rc;
+    tomo_tuning win = base;
+    if (keep_p) {
+        win.p_bundle = win_p.p_bundle;
+        win.p_xcd_remap = win_p.p_xcd_remap;
+        win.p_layout = win_p.p_layout;
+    }
+    const tomo_tuning &bsrc = keep_b ? win_b : base_b;
+    win.bp_default = bsrc.bp_default;
+    win.bp_bundle = bsrc.bp_bundle;
+    win.bp_xcd_remap = bsrc.bp_xcd_remap;
+    win.bp_block[0] = bsrc.bp_block[0];
+    win.bp_block[1] = bsrc.bp_block[1];
+    win.bp_block[2] = bsrc.bp_block[2];
+    win.bp_splits = bsrc.bp_splits;
+    win.bp_lds_bins = bsrc.bp_lds_bins;
+    win.bp_threads = bsrc.bp_threads;
     {
         std::lock_guard<std::mutex> lock(g_class_mu);
         g_class_tuning[p.size_class] = win;
     }
     if (out) *out = win;
-    return TOMO_OK;
+    return hip_fail(hipStreamSynchronize(s), "tomo_autotune: synchronise");
+}
+
+}  // namespace tomo
+
+using namespace tomo;
+
+extern "C" {
+
+int tomo_autotune(const tomo_geometry *g, int32_t reps, tomo_tuning *out, tomo_stream stream)
+{
+    return autotune_impl(g, nullptr, nullptr, reps, out, (hipStream_t)stream);
+}
+
+int tomo_autotune_data(const tomo_geometry *g, const float *cube_d, const float *images_d, int32_t reps,
+                       tomo_tuning *out, tomo_stream stream)
+{
+    if (!cube_d || !images_d) return set_error(TOMO_EINVAL, "tomo_autotune_data: NULL array");
+    return autotune_impl(g, cube_d, images_d, reps, out, (hipStream_t)stream);
 }
 
 int tomo_get_class_tuning(const tomo_geometry *g, tomo_tuning *out, int32_t *tuned)

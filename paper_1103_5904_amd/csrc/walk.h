@@ -58,9 +58,10 @@ struct RayAxes {
 };
 
 // kObstacle = false leaves out the obstacle's code (only for grids without
-// one); true cuts the ray at the obstacle when the grid has one.
-template <bool kObstacle = true>
-__device__ inline bool ray_setup(const GridDev &g, const ViewDev &v, int col, int row,
+// one); true cuts the ray at the obstacle when the grid has one.  V is any
+// view record with the pointing fields of ViewDev (o, w, u, v, cd, cp).
+template <bool kObstacle = true, class V>
+__device__ inline bool ray_setup(const GridDev &g, const V &v, int col, int row,
                                  RayState &r, RayAxes *ax = nullptr)
 {
     const double x = ((double)col - v.cp[0]) * v.cd[0];
@@ -335,6 +336,78 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
                 x_prev = buf_load_f32(rc, (uint32_t)off * 4u);
                 dl_prev = dl;
             });
+        }
+        acc = fma(dl_prev, (double)x_prev, acc);
+        out = (float)(acc * (r.dn * v.gain));
+    }
+    images[pix] = out;
+}
+
+// A bricked copy of the cube: bricks of B = 2^k voxels a side in x-fastest
+// order, x fastest inside each brick, every frame padded to whole bricks.
+struct BrickDev {
+    int32_t k;            // log2 of the brick side
+    int32_t nb[3];        // bricks per axis
+    int64_t frame_stride; // floats per padded frame
+};
+
+// Offset of voxel (i0, i1, i2) in its frame of the bricked copy.
+__device__ inline uint32_t brick_offset(const BrickDev &bk, int i0, int i1, int i2)
+{
+    const uint32_t m = (1u << bk.k) - 1u;
+    const uint32_t brick = ((uint32_t)(i2 >> bk.k) * (uint32_t)bk.nb[1] + (uint32_t)(i1 >> bk.k)) * (uint32_t)bk.nb[0] +
+                           (uint32_t)(i0 >> bk.k);
+    return (brick << (3 * bk.k)) | (((uint32_t)i2 & m) << (2 * bk.k)) | (((uint32_t)i1 & m) << bk.k) |
+           ((uint32_t)i0 & m);
+}
+
+// P for one 16x16 tile from a bricked copy of M x (the map mask applied by
+// the copy): the same walk as project_tile, the voxel indices carried per
+// axis and the offset formed from them; the same segments summed in the
+// same order, so the same bits.
+template <bool kDataMask, bool kObstacle>
+__device__ inline void project_tile_bricked(const GridDev &g, const ViewDev *__restrict__ views, int32_t nviews,
+                                            int log2_bw, int64_t tile, int32_t maxit, const float *__restrict__ bricked,
+                                            const BrickDev &bk, const uint8_t *__restrict__ data_mask,
+                                            float *__restrict__ images)
+{
+    const LanePixel lp = lane_pixel(views, nviews, tile, log2_bw);
+    const ViewDev &v = views[lp.view];
+    if (lp.col >= v.ncol || lp.row >= v.nrow) return;
+    const int64_t pix = v.pix_off + (int64_t)lp.row * v.ncol + lp.col;
+    float out = 0.0f;
+    RayState r;
+    RayAxes ax;
+    if ((!kDataMask || data_mask[pix]) && ray_setup<kObstacle>(g, v, lp.col, lp.row, r, &ax)) {
+        const float *__restrict__ base = bricked + (int64_t)v.frame * bk.frame_stride;
+        const bool wide = bk.frame_stride >= ((int64_t)1 << 30);
+        const uint32_t last = (uint32_t)(bk.frame_stride - 1);
+        const auto rc = make_rsrc(base, wide ? 0u : (uint32_t)(bk.frame_stride * 4));
+        int i[3] = {ax.idx[0], ax.idx[1], ax.idx[2]};
+        int dir[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) dir[a] = r.st[a] > 0 ? 1 : (r.st[a] < 0 ? -1 : 0);
+        // pipelined by one segment as in project_tile
+        double acc = 0.0, dl_prev = 0.0, scur = 0.0;
+        float x_prev = 0.0f;
+        auto step = [&]() {
+            const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
+            const uint32_t off = brick_offset(bk, i[0], i[1], i[2]);
+            const double dl = m - scur;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                const bool t = (r.s[a] == m);
+                r.s[a] = fma(r.ds[a], tie_factor(t), r.s[a]);
+                i[a] += t ? dir[a] : 0;
+            }
+            scur = m;
+            acc = fma(dl_prev, (double)x_prev, acc);
+            x_prev = wide ? base[min(off, last)] : buf_load_f32(rc, off * 4u);
+            dl_prev = dl;
+            return m >= r.send;
+        };
+        for (int it = 0; it < maxit; it += 4) {
+            if (step() || step() || step() || step()) break;
         }
         acc = fma(dl_prev, (double)x_prev, acc);
         out = (float)(acc * (r.dn * v.gain));

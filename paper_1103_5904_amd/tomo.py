@@ -68,7 +68,8 @@ THOMSON_KINDS = {"pB": 0, "B": 1}
 class Tuning(ctypes.Structure):
     _fields_ = [("p_bundle", c_int32), ("p_xcd_remap", c_int32), ("bp_bundle", c_int32),
                 ("bp_xcd_remap", c_int32), ("bp_lds_bins", c_int32), ("bp_default", c_int32),
-                ("bp_block", c_int32 * 3), ("bp_splits", c_int32)]
+                ("bp_block", c_int32 * 3), ("bp_splits", c_int32), ("bp_threads", c_int32),
+                ("p_layout", c_int32)]
 
 
 class CgParams(ctypes.Structure):
@@ -99,7 +100,7 @@ EXPORTS = [
     "tomo_convnet_loss_grad", "tomo_convnet_backward", "tomo_adam_step", "tomo_autotune",
     "tomo_get_class_tuning", "tomo_autotune_clear", "tomo_batch_create", "tomo_batch_destroy",
     "tomo_batch_project", "tomo_batch_backproject", "tomo_batch_binning_spills", "tomo_batch_items",
-    "tomo_batch_cg_solve",
+    "tomo_batch_cg_solve", "tomo_autotune_data",
 ]
 NPARAMS = 7809
 
@@ -148,6 +149,8 @@ def lib():
                                      c_double, c_double, c_double, c_double, c_void_p]
         L.tomo_set_tuning.argtypes = [POINTER(Tuning)]
         L.tomo_autotune.argtypes = [POINTER(TomoGeometry), c_int32, POINTER(Tuning), c_void_p]
+        L.tomo_autotune_data.argtypes = [POINTER(TomoGeometry), c_void_p, c_void_p, c_int32, POINTER(Tuning),
+                                         c_void_p]
         L.tomo_get_class_tuning.argtypes = [POINTER(TomoGeometry), POINTER(Tuning), POINTER(c_int32)]
         L.tomo_autotune_clear.argtypes = []
         L.tomo_autotune_clear.restype = None
@@ -314,11 +317,19 @@ def _tuning_dict(t: Tuning) -> dict:
     return out
 
 
-def autotune(geom: DeviceGeometry, reps: int = 3) -> dict:
-    """Time the launch candidates on this geometry and keep the fastest for
-    its size class (tomo_autotune); returns the chosen tuning."""
+def autotune(geom: DeviceGeometry, reps: int = 3, cube: torch.Tensor | None = None,
+             images: torch.Tensor | None = None) -> dict:
+    """Time the launch candidates on this geometry (on the given cube and
+    images, else on a cube of ones and its projection) and keep the fastest
+    for its size class if it beats the process-wide tuning
+    (tomo_autotune / tomo_autotune_data); returns the chosen tuning."""
     t = Tuning()
-    _check(lib().tomo_autotune(geom.ref, int(reps), ctypes.byref(t), _stream()))
+    if cube is not None and images is not None:
+        _check(lib().tomo_autotune_data(geom.ref, _dev_f32(cube, geom.nvox * geom.nframes, "cube"),
+                                        _dev_f32(images, geom.npix, "images"), int(reps), ctypes.byref(t),
+                                        _stream()))
+    else:
+        _check(lib().tomo_autotune(geom.ref, int(reps), ctypes.byref(t), _stream()))
     return _tuning_dict(t)
 
 
@@ -416,10 +427,13 @@ class Batch:
         return outs
 
     def cg_solve(self, ys, x0s=None, *, lam_r=1e-2, lam_t=0.0, max_iter=50, rtol=0.0, check_every=10,
-                 use_graph=False, outs=None, heights=None):
+                 use_graph=False, outs=None, heights=None, time_kernels=False):
         """CG on every system at once; lam_r, lam_t, max_iter, rtol may be
         per-system lists, heights a per-system list of (cx, cy, cz, offset)
-        or None (height-weighted spatial prior).  Returns (xs, reports)."""
+        or None (height-weighted spatial prior).  With time_kernels, every
+        report's ms_project / ms_backproject hold the total time of the
+        batched P / P^T launches of the iterations (shared by all systems).
+        Returns (xs, reports)."""
         n = len(self.geoms)
         per = lambda v: list(v) if isinstance(v, (list, tuple)) else [v] * n  # noqa: E731
         lr, lt, mi, rt = per(lam_r), per(lam_t), per(max_iter), per(rtol)
@@ -438,6 +452,7 @@ class Batch:
         for k in range(n):
             reps[k].history = hists[k]
             reps[k].history_cap = int(mi[k]) + 1
+            reps[k].time_kernels = int(bool(time_kernels))
         src = _ptrs(ys, [g.npix for g in self.geoms], "y")
         dst = _ptrs(outs, [g.nvox * g.nframes for g in self.geoms], "x")
         _check(lib().tomo_batch_cg_solve(self.h, src, dst, params, reps, _stream()))

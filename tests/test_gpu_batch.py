@@ -119,6 +119,33 @@ def test_batched_cg_equals_per_system_cg(tomo, use_graph):
     assert reps[1]["status"] == 0 and reps[1]["iters"] < 30  # converged on its own tolerance
 
 
+def test_batched_cg_kernel_timing(tomo):
+    """time_kernels in a batched solve, replayed from a graph (the events
+    are graph nodes) and enqueued directly: the same iterates either way,
+    positive P and P^T totals shared by every report, and per launch within
+    a factor 3 of each other (the two runs time the same launches)."""
+    import torch
+
+    geoms = _systems()[:3]
+    dgs = [tomo.DeviceGeometry(g) for g in geoms]
+    ys = _data(tomo, dgs, geoms, 12)
+    b = tomo.Batch(dgs)
+    out = {}
+    for use_graph in (True, False):
+        xs, reps = b.cg_solve(ys, lam_r=1e-2, max_iter=8, check_every=4, use_graph=use_graph, time_kernels=True)
+        out[use_graph] = ([x.clone() for x in xs], reps)
+        for r in reps:
+            assert r["ms_project"] == reps[0]["ms_project"] > 0.0
+            assert r["ms_backproject"] == reps[0]["ms_backproject"] > 0.0
+    for a, c in zip(out[True][0], out[False][0]):
+        assert torch.equal(a, c)
+    for key in ("ms_project", "ms_backproject"):
+        ratio = out[True][1][0][key] / out[False][1][0][key]
+        assert 1 / 3 < ratio < 3, (key, ratio)
+    _, reps = b.cg_solve(ys, lam_r=1e-2, max_iter=8, check_every=4, use_graph=True)
+    assert reps[0]["ms_project"] == 0.0 and reps[0]["ms_backproject"] == 0.0
+
+
 def test_single_solver_graph_mode(tomo):
     import torch
 

@@ -292,3 +292,90 @@ def test_blocked_is_deterministic(tomo):
     b = tomo.backproject(dg, y, strategy=tomo.BP_BLOCKED)
     torch.cuda.synchronize()
     assert torch.equal(a, b)
+
+
+def _mixed_geometry(rng, n=64, with_masks=False):
+    """Views from the ecliptic, the poles, close up and at random, over an
+    n^3 cube; optionally random data and map masks."""
+    rows, pix = [], []
+    specs = [(ts.observer(lon), (0.0, 0.0, 0.0), (128, 128), 3.2) for lon in (10.0, 45.0, 100.0)]
+    specs += [(ts.observer(20.0, 0.0, 3.0), (0.0, 0.0, 0.0), (97, 61), 3.0)]
+    specs += [(ts.observer(rng.uniform(0, 360), lat), (0.0, 0.0, 0.0), (120, 100), 3.2) for lat in (30.0, 89.0)]
+    for _ in range(2):
+        d = rng.normal(size=3)
+        specs.append((d / np.linalg.norm(d) * rng.uniform(2.5, 40.0), tuple(rng.uniform(-0.3, 0.3, 3)),
+                      (int(rng.integers(40, 160)), int(rng.integers(40, 160))), rng.uniform(1.0, 5.0)))
+    for obs, target, npix, fov in specs:
+        r, p = ts.pinhole_view(np.asarray(obs, dtype=np.float64), target=target, npix=npix, fov=fov)
+        rows.append(r)
+        pix.append(p)
+    g = ts.Geometry((n, n, n), np.full(3, -1.5), np.full(3, 1.5), np.array(rows), np.array(pix, np.int32))
+    if with_masks:
+        g.data_mask = (rng.uniform(size=g.nrays) > 0.35).astype(np.uint8)
+        g.map_mask = (rng.uniform(size=g.cube_shape()) > 0.1).astype(np.uint8)
+    return g
+
+
+@pytest.mark.parametrize("masks", [False, True])
+def test_blocked_workgroup_sizes(tuning, ora, masks):
+    """The blocked P^T for workgroups of 256, 512 and 1024 lanes, with the
+    larger blocks those own (up to 16384 voxels of LDS bins), one owner per
+    block: every output bit equal whatever the shape (the fixed-point sums
+    are exact), and the whole operator against the oracle.  With a data mask
+    the passes take the kept pixels of each footprint row only."""
+    import torch
+
+    tomo = tuning
+    rng = np.random.default_rng(51 + int(masks))
+    g = _mixed_geometry(rng, with_masks=masks)
+    dg = tomo.DeviceGeometry(g)
+    y = rng.normal(size=g.nrays).astype(np.float32).astype(np.float64)
+    yd = to_dev(y)
+    outs = {}
+    for nt, block in ((256, (64, 32, 2)), (256, (16, 16, 16)), (512, (64, 64, 2)), (512, (32, 32, 8)),
+                      (1024, (128, 64, 2)), (1024, (32, 32, 16)), (1024, (64, 64, 4))):
+        tomo.set_tuning(bp_threads=nt, bp_block=block, bp_splits=1)
+        outs[(nt, block)] = tomo.backproject(dg, yd, strategy=tomo.BP_BLOCKED).clone()
+        assert tomo.binning_spills(dg) == 0
+    ref = outs[(256, (64, 32, 2))]
+    for key, out in outs.items():
+        assert torch.equal(out, ref), key
+    res = length_resolution(g)
+    assert_p_close(to_host(ref), ora.backproject(g, y), ora.backproject(g, np.abs(y)), rtol=1e-4,
+                   what="P^T", atol=res * np.abs(y).max())
+
+
+@pytest.mark.parametrize("layout", [2, 3, 4])
+def test_bricked_projection_equals_linear(tuning, ora, layout):
+    """P from a bricked copy of the cube (bricks of 4, 8 and 16 voxels a
+    side) walks the same segments in the same order as from the x-fastest
+    cube: the same bits, on ragged boxes whose sides are not multiples of
+    the brick, with masks, frames and the obstacle."""
+    import torch
+
+    tomo = tuning
+    rng = np.random.default_rng(60 + layout)
+    g1 = _mixed_geometry(rng, n=37, with_masks=True)
+    wl = ts.tiny()
+    g0 = wl.geom
+    vf = (np.arange(g0.nviews) % 3).astype(np.int32)
+    g2 = ts.Geometry(g0.n, g0.lo, g0.hi, g0.views, g0.npix, vf, 3,
+                     map_mask=(rng.uniform(size=g0.cube_shape()) > 0.2).astype(np.uint8))
+    g3 = ts.Geometry((23, 41, 19), np.array([-1.3, -1.5, -0.9]), np.array([1.4, 1.2, 1.1]), g0.views, g0.npix,
+                     obstacle=np.array([0.1, 0.0, -0.1, 0.7]))
+    for g in (g1, g2, g3):
+        dg = tomo.DeviceGeometry(g)
+        x = to_dev(rng.uniform(size=g.cube_shape()))
+        tomo.set_tuning(p_layout=0)
+        ref = tomo.project(dg, x).clone()
+        tomo.set_tuning(p_layout=layout)
+        got = tomo.project(dg, x)
+        torch.cuda.synchronize()
+        assert torch.equal(got, ref)
+        assert float(ref.abs().max()) > 0
+    # and the bricked P agrees with the oracle on the masked geometry
+    dg = tomo.DeviceGeometry(g1)
+    x = rng.uniform(size=g1.cube_shape())
+    res = length_resolution(g1)
+    img = to_host(tomo.project(dg, to_dev(x)))
+    assert_p_close(img, ora.project(g1, x), ora.project(g1, np.abs(x * g1.map_mask)), atol=res * np.abs(x).max())

@@ -125,3 +125,44 @@ def test_cube_1024(tomo, ora):
     for strat in ("binned", "atomic"):
         with pytest.raises(tomo.TomoError):
             tomo.backproject(dg, y, strategy=CODES[strat])
+
+
+def test_autotune_is_never_slower(tomo):
+    """The tuner keeps a candidate only if it beats the process-wide tuning
+    in alternation through the same launch paths, so on a sweep point where
+    an earlier tuner picked a slower back-projection (128^3 under 128^2)
+    the tuned launches are at most 2% slower than the default ones, timed
+    here in alternation (medians of five rounds of 20 launches)."""
+    g, parts, dg, x = _case(tomo, 128, 128)
+    y = tomo.project(dg, x)
+    out = torch.empty_like(x)
+
+    def per_launch(f, n=20):
+        f()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(n):
+            f()
+        e1.record()
+        e1.synchronize()
+        return e0.elapsed_time(e1) / n
+
+    default = tomo.get_tuning()
+    tomo.autotune_clear()
+    tomo.autotune(dg, reps=5)
+    tuned, is_tuned = tomo.class_tuning(dg)
+    assert is_tuned
+    tomo.autotune_clear()
+    times = {"P": ([], []), "P^T": ([], [])}
+    try:
+        for _ in range(5):
+            for key, f in (("P", lambda: tomo.project(dg, x, out=y)), ("P^T", lambda: tomo.backproject(dg, y, out=out))):
+                tomo.set_tuning(**tuned)
+                times[key][0].append(per_launch(f))
+                tomo.set_tuning(**default)
+                times[key][1].append(per_launch(f))
+    finally:
+        tomo.set_tuning(**default)
+    for key, (tt, td) in times.items():
+        print(f"{key}: tuned {np.median(tt):.4f} ms, default {np.median(td):.4f} ms", flush=True)
+        assert np.median(tt) <= 1.02 * np.median(td), key
