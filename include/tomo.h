@@ -193,8 +193,11 @@ int tomo_trace_ray(const tomo_geometry *g, int32_t view, int32_t col,
  *     (p_bundle: P; bp_bundle: the binned and atomic back-projections; the
  *     blocked one walks each footprint 256 pixels at a time in row-major
  *     order and takes no bundle shape).
- *   p_xcd_remap, bp_xcd_remap: 1 = give each XCD a contiguous run of tiles
- *     (of voxel-block items for the blocked back-projection).
+ *   p_xcd_remap, bp_xcd_remap: order of the tiles (of the voxel-block items
+ *     for the blocked back-projection) over the 8 XCDs: 0 = launch order,
+ *     1 = one contiguous run per XCD, 2 = runs of 64 per XCD with all XCDs
+ *     advancing through the list together (a multi-frame cube then keeps one
+ *     frame in the caches at a time).
  *   bp_lds_bins: 64-bit LDS bins per workgroup of the binned
  *     back-projection (512..8192, i.e. 4..64 KiB; larger boxes mean fewer
  *     flushes but fewer resident workgroups).

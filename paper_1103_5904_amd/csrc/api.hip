@@ -20,15 +20,16 @@ static thread_local std::string g_last_error;
 
 // Process-wide launch tuning (see tomo_set_tuning).
 static std::mutex g_tuning_mu;
-// Defaults measured on MI355X (EUVI-like 128^3, 28 views of 512^2): P with
-// 4x16 bundles and the XCD remap (18% faster than without); P^T
-// owner-computes on 64x32x2 blocks, no remap and the automatic owner count.
-// Solar observers sit near the ecliptic, so lines of sight run nearly in
-// the x-y plane and cross few z planes: blocks flat in z are crossed by
-// fewer rays per deposit (1.47 ms per launch against 1.71 for 32x16x8).
-// The binned strategy, which alone takes the bundle field, prefers 8x8
-// bundles and 4096 bins.
-static tomo_tuning g_tuning = {2, 1, 3, 0, 4096, TOMO_BP_BLOCKED, {64, 32, 2}, 0, 256, 0};
+// Defaults measured on MI355X: P with 4x16 bundles and the XCD remap (18%
+// faster than without on the EUVI-like 128^3 / 28 x 512^2 problem); P^T
+// owner-computes with 512-lane workgroups on 128x32x2 blocks, no remap and
+// the automatic owner count.  Solar observers sit near the ecliptic, so
+// lines of sight run nearly in the x-y plane and cross few z planes: blocks
+// flat in z and long in x are crossed by fewer rays per deposit (per launch:
+// 1.27 ms against 1.46 ms for 64x32x2 with 256 lanes on the EUVI-like
+// problem, 5.50 against 6.65 ms on a COR1-like frame).  The binned strategy,
+// which alone takes the bundle field, prefers 8x8 bundles and 4096 bins.
+static tomo_tuning g_tuning = {2, 1, 3, 0, 4096, TOMO_BP_BLOCKED, {128, 32, 2}, 0, 512, 0};
 
 tomo_tuning current_tuning()
 {
@@ -346,8 +347,8 @@ int tomo_set_tuning(const tomo_tuning *in)
     auto bundle_ok = [](int b) { return b == 0 || b == 2 || b == 3 || b == 4; };
     if (!bundle_ok(in->p_bundle) || !bundle_ok(in->bp_bundle))
         return set_error(TOMO_EINVAL, "tomo_set_tuning: bundle must be 0, 2, 3 or 4");
-    if ((in->p_xcd_remap != 0 && in->p_xcd_remap != 1) || (in->bp_xcd_remap != 0 && in->bp_xcd_remap != 1))
-        return set_error(TOMO_EINVAL, "tomo_set_tuning: xcd_remap must be 0 or 1");
+    if (in->p_xcd_remap < 0 || in->p_xcd_remap > 2 || in->bp_xcd_remap < 0 || in->bp_xcd_remap > 2)
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: xcd_remap must be 0, 1 or 2");
     if (in->bp_lds_bins < 512 || in->bp_lds_bins > 8192)
         return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_lds_bins must be in [512, 8192]");
     if (in->bp_default != TOMO_BP_BINNED && in->bp_default != TOMO_BP_ATOMIC &&

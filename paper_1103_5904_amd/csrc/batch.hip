@@ -7,10 +7,14 @@
 //   (system, frame, voxel block, owner) for the owner-computes P^T - from
 //   device work queues until they are empty, so systems of very different
 //   sizes share the machine without one launch per system and without tail
-//   effects between them.  The item list is cut into eight contiguous
-//   queues, one per XCD: a workgroup drains the queue of its own XCD first
-//   (neighbouring tiles share cube lines in that XCD's L2) and then takes
-//   from the others.  The last workgroup to leave resets the queues, so a
+//   effects between them.  The item list is dealt to eight queues, one per
+//   XCD, in runs of neighbouring items (64 tiles, 4 blocks): a workgroup
+//   drains the queue of its own XCD first (neighbouring tiles share cube
+//   lines in that XCD's L2) and then takes from the others.  Dealt in runs
+//   rather than cut into eight contiguous parts, the queues advance through
+//   the list together, so the XCDs work on one frame of a multi-frame cube
+//   at a time and its lines stay in the Infinity Cache (eight 64 MiB
+//   frames at once do not fit).  The last workgroup to leave resets the queues, so a
 //   launch needs no host-side clearing and can be captured in a graph.
 // * Each item runs the same device code as the single-geometry launches
 //   (project_tile, blocked_item) with the system's own tuned shape, so a
@@ -32,14 +36,18 @@
 namespace tomo {
 
 // Next item for this workgroup (thread 0), or -1 when every queue is empty.
-__device__ inline int64_t next_item(unsigned long long *q, int64_t total, int &visited)
+// The items are dealt to the queues in runs of `chunk`: queue x holds runs
+// x, x + 8, x + 16, ...  All XCDs then advance through the item list
+// together (the systems and frames one at a time, so that what they read
+// stays in the caches), while each drains runs of neighbouring items.
+__device__ inline int64_t next_item(unsigned long long *q, int64_t total, int64_t chunk, int &visited)
 {
     const int home = (int)(blockIdx.x % kQueues);
     while (visited < kQueues) {
         const int qx = (home + visited) % kQueues;
-        const int64_t lo = total * qx / kQueues, hi = total * (qx + 1) / kQueues;
-        const unsigned long long k = atomicAdd(&q[qx], 1ull);
-        if ((int64_t)k < hi - lo) return lo + (int64_t)k;
+        const int64_t k = (int64_t)atomicAdd(&q[qx], 1ull);
+        const int64_t i = ((k / chunk) * kQueues + qx) * chunk + k % chunk;
+        if (i < total) return i;
         ++visited;
     }
     return -1;
@@ -78,7 +86,7 @@ __global__ __launch_bounds__(kThreads) void k_batch_project(const SysDev *__rest
     __shared__ int64_t s_item;
     int visited = 0;
     for (;;) {
-        if (threadIdx.x == 0) s_item = next_item(q, ntiles, visited);
+        if (threadIdx.x == 0) s_item = next_item(q, ntiles, 64, visited);
         __syncthreads();
         const int64_t t = s_item;
         __syncthreads();
@@ -135,7 +143,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ int64_t s_item;
     int visited = 0;
     for (;;) {
-        if (threadIdx.x == 0) s_item = next_item(q, nitems, visited);
+        if (threadIdx.x == 0) s_item = next_item(q, nitems, 4, visited);
         __syncthreads();
         const int64_t t = s_item;
         __syncthreads();

@@ -102,7 +102,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     __shared__ BlockedShared<NT, kRows> sh;
     if (done_flag && *done_flag) return;
     const int64_t nitems = (int64_t)bd.nb[0] * bd.nb[1] * bd.nb[2] * g.nframes * bd.splits;
-    const int64_t item = bun.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t item = xcd_order(bun.xcd_remap, blockIdx.x, gridDim.x);
     if (item >= nitems) return;
     blocked_item<NT, kMapMask, kDataMask, kObstacle, kRows>(g, views, frame_views, frame_voff, bd, item, images,
                                                             map_mask, data_mask, kept, ymax_parts, out, accumulate,

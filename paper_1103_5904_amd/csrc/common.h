@@ -50,7 +50,7 @@ struct GridDev {
 // pixel of the tile in both directions, offset by its index.
 struct Bundle {
     int32_t log2_bw;    // 3 -> 8x8, 4 -> 16x4, 2 -> 4x16, 0 -> interleaved
-    int32_t xcd_remap;  // 1: give each XCD a contiguous range of tiles
+    int32_t xcd_remap;  // tile order (xcd_order): 0 launch order, 1 a run per XCD, 2 runs per XCD in step
 };
 
 // Owner-computes P^T launch shape (device copy).
@@ -97,6 +97,29 @@ __device__ inline int64_t xcd_remap(int64_t b, int64_t nb)
     const int64_t q = nb >> 3, r = nb & 7;
     const int64_t x = b & 7, i = b >> 3;
     return x * q + (x < r ? x : r) + i;
+}
+
+// The same with runs of kXcdChunk: each group of 8 kXcdChunk consecutive
+// workgroup ids covers 8 kXcdChunk consecutive tiles, kXcdChunk of them
+// (contiguous) per XCD.  All XCDs then advance through the tile list
+// together, so the data they touch at one time stays a window of it (one
+// frame of a multi-frame cube, not eight), while each XCD's L2 still sees
+// neighbouring tiles.  The ragged last group keeps the identity.  Bijective
+// on [0, nb).
+constexpr int64_t kXcdChunk = 64;
+__device__ inline int64_t xcd_remap_chunked(int64_t b, int64_t nb)
+{
+    const int64_t g = b / (8 * kXcdChunk);
+    if ((g + 1) * 8 * kXcdChunk > nb) return b;
+    const int64_t w = b - g * 8 * kXcdChunk;
+    return g * 8 * kXcdChunk + (w & 7) * kXcdChunk + (w >> 3);
+}
+
+// Tile order of a launch: 0 = launch order, 1 = one contiguous run per
+// XCD, 2 = runs of kXcdChunk per XCD advancing together.
+__device__ inline int64_t xcd_order(int32_t mode, int64_t b, int64_t nb)
+{
+    return mode == 1 ? xcd_remap(b, nb) : (mode == 2 ? xcd_remap_chunked(b, nb) : b);
 }
 
 // Sum of one double per thread over a 256-thread block; the result is valid

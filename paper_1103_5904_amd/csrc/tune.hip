@@ -112,7 +112,7 @@ static int autotune_impl(const tomo_geometry *g, const float *cube_in, const flo
     std::vector<tomo_tuning> pc, bc;
     for (int lay : {0, 2, 3, 4})
         for (int bun : {0, 2, 3, 4})
-            for (int xr : {0, 1}) {
+            for (int xr : {0, 1, 2}) {
                 tomo_tuning t = base;
                 t.p_bundle = bun;
                 t.p_xcd_remap = xr;
@@ -121,7 +121,7 @@ static int autotune_impl(const tomo_geometry *g, const float *cube_in, const flo
             }
     for (const Shape &sh : kShapes)
         for (int sp : {0, 8})
-            for (int xr : {0, 1}) {  // (the blocked kernel takes no bundle shape)
+            for (int xr : {0, 1, 2}) {  // (the blocked kernel takes no bundle shape)
                 tomo_tuning t = base;
                 t.bp_default = TOMO_BP_BLOCKED;
                 t.bp_threads = sh.nt;

@@ -269,7 +269,7 @@ __device__ inline LanePixel lane_pixel(const ViewDev *__restrict__ views, int nv
 
 __device__ inline int64_t block_tile(const Bundle &b)
 {
-    return b.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    return xcd_order(b.xcd_remap, blockIdx.x, gridDim.x);
 }
 
 // P for one 16x16 tile (all threads of the workgroup): each lane's pixel =

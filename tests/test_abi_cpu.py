@@ -116,7 +116,7 @@ def test_tuning_round_trip_and_range_checks(tomo):
         tomo.set_tuning(p_bundle=4, bp_lds_bins=2048)
         t = tomo.get_tuning()
         assert t["p_bundle"] == 4 and t["bp_lds_bins"] == 2048
-        for bad in ({"p_bundle": 5}, {"bp_lds_bins": 100}, {"bp_default": 7}, {"p_xcd_remap": 2}):
+        for bad in ({"p_bundle": 5}, {"bp_lds_bins": 100}, {"bp_default": 7}, {"p_xcd_remap": 3}):
             with pytest.raises(tomo.TomoError):
                 tomo.set_tuning(**bad)
         assert tomo.get_tuning() == t  # unchanged by rejected calls
