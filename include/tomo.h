@@ -163,6 +163,31 @@ int tomo_backproject_ex(const tomo_geometry *g, const float *images_d,
                         tomo_stream stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP stream
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * transpose as tomo_backproject_ex(..., TOMO_BP_BLOCKED, ...), bit for bit,
+ * with no allocation of any kind.  Its scratch (4 * nviews * 64 bytes of
+ * per-view maxima; owners * 4 * nframes * nvox bytes of partial sums when
+ * blocks have several owners; 4 bytes per image pixel of kept-pixel row
+ * tables when a data mask is given and footprints are cut to row
+ * intervals) lives in one static device array of
+ * TOMO_NOALLOC_SCRATCH_BYTES per GPU, held until the process ends.
+ *   - The geometry's device tables must already exist: make any other call
+ *     with the same geometry first (tomo_count_crossings, tomo_backproject,
+ *     ...), as before a stream capture; otherwise TOMO_EINVAL.
+ *   - TOMO_EINVAL if the scratch this geometry needs under its tuning
+ *     exceeds TOMO_NOALLOC_SCRATCH_BYTES; nothing is launched then.
+ *   - Every call on one GPU shares that GPU's array, and each call writes
+ *     all the scratch it reads, so nothing carries over between calls; but
+ *     calls that overlap in time on one GPU (other streams or threads) race
+ *     on it and must be serialised by the caller.
+ */
+#define TOMO_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int tomo_backproject_noalloc(const tomo_geometry *g, const float *images_d,
+                             float *cube_d, int accumulate,
+                             tomo_stream stream);
+
+/*
  * Number of positive-length ray/voxel segments walked by one projection
  * (masked pixels excluded): the "voxel crossings" P and P^T each process.
  * Synchronises the stream; *total_h is host memory.

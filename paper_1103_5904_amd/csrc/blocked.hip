@@ -341,3 +341,71 @@ int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const floa
 }
 
 }  // namespace tomo
+
+// ---------------------------------------------------------------------------
+// The allocation-free transpose.  Its scratch (the per-view maxima, the
+// owners' partial sums when blocks have several owners, the kept-pixel row
+// tables under a data mask) lives in a static device array instead of
+// stream-ordered memory; every byte of it that a launch reads, the same
+// launch writes first, so nothing needs clearing between calls.  In host code the array's
+// name stands for a host-side shadow, not for device memory: the array's
+// device address is taken once per GPU with hipGetSymbolAddress and only
+// that address is handed to kernels.
+
+#include <mutex>
+
+namespace tomo {
+
+constexpr size_t kNoAllocScratch = TOMO_NOALLOC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+
+__device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+// Device address of this GPU's copy of `scratch` (looked up on the first
+// call on each device, with that device current).
+static int noalloc_scratch(void **out)
+{
+    int dev = 0;
+    int rc = hip_fail(hipGetDevice(&dev), "tomo_backproject_noalloc: current device");
+    if (rc) return rc;
+    if (dev < 0 || dev >= kMaxDevices)
+        return set_error(TOMO_EUNSUPPORTED, "tomo_backproject_noalloc: device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        rc = hip_fail(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "tomo_backproject_noalloc: scratch address");
+        if (rc) return rc;
+        if (!p) return set_error(TOMO_EHIP, "tomo_backproject_noalloc: scratch address is NULL");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return TOMO_OK;
+}
+
+}  // namespace tomo
+
+extern "C" int tomo_backproject_noalloc(const tomo_geometry *g, const float *images_d, float *cube_d,
+                                        int accumulate, tomo_stream stream)
+{
+    using namespace tomo;
+    if (!cube_d || !images_d) return set_error(TOMO_EINVAL, "tomo_backproject_noalloc: NULL array");
+    int st = TOMO_OK;
+    PlanRef p = get_plan(g, &st, false);
+    if (!p) return st;
+    const tomo_tuning tu = tuning_for(*p);
+    const BlockedShape bs = blocked_shape(*p, tu);
+    const size_t need = blocked_scratch_bytes(*p, bs, g->data_mask != nullptr);
+    if (need > kNoAllocScratch)
+        return set_error(TOMO_EINVAL,
+                         "tomo_backproject_noalloc: %zu bytes of scratch needed (%d owners per block over %lld "
+                         "voxels), above the %zu-byte static array",
+                         need, bs.splits, (long long)(p->grid.nvox * p->grid.nframes), kNoAllocScratch);
+    void *sp = nullptr;
+    const int rc = noalloc_scratch(&sp);
+    if (rc) return rc;
+    return launch_backproject_blocked(*p, g, images_d, cube_d, accumulate != 0, true, (hipStream_t)stream,
+                                      nullptr, sp, kNoAllocScratch, tu);
+}

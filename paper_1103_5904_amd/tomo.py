@@ -100,7 +100,7 @@ EXPORTS = [
     "tomo_convnet_loss_grad", "tomo_convnet_backward", "tomo_adam_step", "tomo_autotune",
     "tomo_get_class_tuning", "tomo_autotune_clear", "tomo_batch_create", "tomo_batch_destroy",
     "tomo_batch_project", "tomo_batch_backproject", "tomo_batch_binning_spills", "tomo_batch_items",
-    "tomo_batch_cg_solve", "tomo_autotune_data",
+    "tomo_batch_cg_solve", "tomo_backproject_noalloc", "tomo_autotune_data",
 ]
 NPARAMS = 7809
 
@@ -122,6 +122,8 @@ def lib():
                                        c_void_p]
         L.tomo_backproject_ex.argtypes = [POINTER(TomoGeometry), c_void_p, c_void_p, ctypes.c_int,
                                           ctypes.c_int, c_void_p]
+        L.tomo_backproject_noalloc.argtypes = [POINTER(TomoGeometry), c_void_p, c_void_p, ctypes.c_int,
+                                               c_void_p]
         L.tomo_count_crossings.argtypes = [POINTER(TomoGeometry), POINTER(c_int64), c_void_p]
         L.tomo_trace_ray.argtypes = [POINTER(TomoGeometry), c_int32, c_int32, c_int32,
                                      POINTER(c_int32), POINTER(c_double), POINTER(c_double),
@@ -284,6 +286,17 @@ def backproject(geom: DeviceGeometry, images: torch.Tensor, out: torch.Tensor | 
     y = _dev_f32(images, geom.npix, "images")
     o = _dev_f32(out, geom.nvox * geom.nframes, "out")
     _check(lib().tomo_backproject_ex(geom.ref, y, o, int(bool(accumulate)), int(strategy), _stream()))
+    return out
+
+
+def backproject_noalloc(geom: DeviceGeometry, images: torch.Tensor, out: torch.Tensor,
+                        accumulate: bool = False):
+    """Cube = M P^T images (or += with accumulate) through the allocation-free
+    entry point: the blocked transpose with the library's static scratch
+    array.  `out` must be given (nothing is allocated)."""
+    y = _dev_f32(images, geom.npix, "images")
+    o = _dev_f32(out, geom.nvox * geom.nframes, "out")
+    _check(lib().tomo_backproject_noalloc(geom.ref, y, o, int(bool(accumulate)), _stream()))
     return out
 
 
