@@ -53,6 +53,11 @@ HBM_PEAK_GBS = 8000.0
 # the full rate on gfx950), at 2.4 GHz.  In flops this is the FP64 vector
 # peak, 78.6 TFLOP/s, with an FMA counted as two.
 VALU_PEAK_LANE_INSTR = 256 * 64 * 2.4e9
+# VALU instructions of one voxel crossing in the walk loop of each batched
+# kernel (its four-crossing loop body in the gfx950 ISA of batch.hip, divided
+# by four): the P gather-FMA walk over the linear cube, and the P^T walk with
+# its fixed-point LDS deposit.
+WALK_VALU_PER_CROSSING = {"k_batch_project": 101 / 4, "k_batch_backproject": 92 / 4}
 
 # Per-launch counters of the batched kernels on the headline step, from
 # rocprofv3 --pmc passes of `bench.py --headline-only` (profiles/
@@ -211,26 +216,35 @@ def headline(tomo, ts, args):
 
 
 def roofline(h):
-    """The dominant batched kernel against the VALU issue ceiling, with its
-    algorithmic and measured HBM bytes."""
+    """The dominant batched kernel against the VALU issue ceiling.
+
+    achieved = (walk-loop VALU lane-instructions per voxel crossing, counted
+    in the kernel's gfx950 ISA) x (crossings of one launch) / (the launch's
+    live duration): the walk's own arithmetic, the algorithmic unit of this
+    bound.  issued_frac counts every VALU instruction the launch issued
+    (ray set-ups, footprints, idle lanes of diverged wavefronts included),
+    from the profiled SQ_INSTS_VALU; traffic is the profiled HBM bytes of one
+    launch.  Both are null when the sources changed since they were taken."""
     if h["ms_b"] >= h["ms_p"]:
-        kern, ms, alg = "k_batch_backproject", h["ms_b"], 8.0 * h["cross_b"] + 4.0 * h["rays"]
+        kern, ms, cross = "k_batch_backproject", h["ms_b"], h["cross_b"]
+        alg = 8.0 * cross + 4.0 * h["rays"]
     else:
-        kern, ms, alg = "k_batch_project", h["ms_p"], 4.0 * h["cross_p"] + 4.0 * h["rays"]
-    prof = profiled(kern)
+        kern, ms, cross = "k_batch_project", h["ms_p"], h["cross_p"]
+        alg = 4.0 * cross + 4.0 * h["rays"]
     sec = ms * 1e-3
-    out = {"kernel": kern, "bound": "alu", "unit": "Tinstr/s", "peak": VALU_PEAK_LANE_INSTR / 1e12,
-           "launch_ms": ms, "algorithmic_gbs": alg / sec / 1e9, "algorithmic_frac_hbm": alg / sec / 1e9 / HBM_PEAK_GBS}
+    per = WALK_VALU_PER_CROSSING[kern]
+    peak = VALU_PEAK_LANE_INSTR / 1e12
+    achieved = per * cross / sec / 1e12
+    out = {"kernel": kern, "bound": "alu", "achieved": achieved, "peak": peak, "unit": "Tinstr/s",
+           "frac": achieved / peak, "traffic": None, "launch_ms": ms, "valu_per_crossing": per,
+           "algorithmic_bytes": alg, "algorithmic_frac_hbm": alg / sec / 1e9 / HBM_PEAK_GBS}
+    prof = profiled(kern)
     if prof is not None:
-        achieved = prof["valu_insts"] * 64.0 / sec / 1e12
-        out.update({"achieved": achieved, "frac": achieved / out["peak"],
-                    "traffic": prof["hbm_bytes"], "traffic_gbs": prof["hbm_bytes"] / sec / 1e9,
-                    "valu_lane_instr_per_crossing": prof["valu_insts"] * 64.0 / (h["cross_b"] if
-                                                                                 kern.endswith("backproject")
-                                                                                 else h["cross_p"])})
+        issued = prof["valu_insts"] * 64.0 / sec / 1e12
+        out.update({"issued_frac": issued / peak, "traffic": prof["hbm_bytes"],
+                    "traffic_over_algorithmic": prof["hbm_bytes"] / alg})
     else:
-        out.update({"achieved": None, "frac": None, "traffic": None,
-                    "note": "kernel sources changed since the counters were profiled"})
+        out.update({"issued_frac": None, "note": "kernel sources changed since the counters were profiled"})
     return out
 
 

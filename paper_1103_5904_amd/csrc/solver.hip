@@ -121,13 +121,14 @@ __device__ inline float height_of(float dx, float dy, float dz, float off)
 // lambda_r (D^T D x)_v + lambda_t (D_t^T D_t x)_v, or with kHeight
 // lambda_r (R D^T D R x)_v + lambda_t (D_t^T D_t x)_v: forward differences
 // between in-range neighbours only (free ends).
+// c = x[idx]; xm, xp: x one frame before and after (read only where those
+// frames exist and lambda_t != 0).
 template <bool kHeight = false>
-__device__ inline float prior_at(const float *__restrict__ x, const Dims &d, int64_t idx, const VoxIdx &c_,
-                                 float lr, float lt, const HeightDev &hd = HeightDev{})
+__device__ inline float prior_core(const float *__restrict__ x, const Dims &d, int64_t idx, const VoxIdx &c_,
+                                   float lr, float lt, const HeightDev &hd, float c, float xm, float xp)
 {
     const int32_t i = c_.i, j = c_.j, k = c_.k;
     const int64_t f = c_.f;
-    const float c = x[idx];
     const int64_t pl = (int64_t)d.nx * d.ny;
     float s = 0.0f, w = 1.0f;
     if constexpr (!kHeight) {
@@ -154,11 +155,21 @@ __device__ inline float prior_at(const float *__restrict__ x, const Dims &d, int
     float out = lr * (w * s);
     if (lt != 0.0f) {
         float t = 0.0f;
-        if (f > 0) t += c - x[idx - d.nvox];
-        if (f < d.nf - 1) t += c - x[idx + d.nvox];
+        if (f > 0) t += c - xm;
+        if (f < d.nf - 1) t += c - xp;
         out += lt * t;
     }
     return out;
+}
+
+template <bool kHeight = false>
+__device__ inline float prior_at(const float *__restrict__ x, const Dims &d, int64_t idx, const VoxIdx &c,
+                                 float lr, float lt, const HeightDev &hd = HeightDev{})
+{
+    const bool tm = lt != 0.0f;
+    const float xm = tm && c.f > 0 ? x[idx - d.nvox] : 0.0f;
+    const float xp = tm && c.f < d.nf - 1 ? x[idx + d.nvox] : 0.0f;
+    return prior_core<kHeight>(x, d, idx, c, lr, lt, hd, x[idx], xm, xp);
 }
 
 template <bool kHeight>
@@ -332,7 +343,10 @@ __global__ __launch_bounds__(kThreads) void k_cg_start(const float *__restrict__
     }
 }
 
-// q = M (q + prior(p)); per-workgroup partials of p.q.
+// q = M (q + prior(p)); per-workgroup partials of p.q.  A thread takes one
+// spatial voxel through all frames, so that the temporal neighbours p[f -+ 1]
+// come from registers (each p read once from memory, the map mask once per
+// voxel) and the voxel's coordinates are found once.
 template <bool kHeight>
 __global__ __launch_bounds__(kThreads) void k_cg_q(const float *__restrict__ p,
                                                    float *__restrict__ q,
@@ -341,22 +355,33 @@ __global__ __launch_bounds__(kThreads) void k_cg_q(const float *__restrict__ p,
 {
     if (ws.st->done) return;
     double pq = 0.0;
-    for (int64_t i = (int64_t)blockIdx.x * kThreads + threadIdx.x; i < d.total;
-         i += (int64_t)gridDim.x * kThreads) {
-        const VoxIdx c = vox_index(d, i);
-        float v = q[i] + prior_at<kHeight>(p, d, i, c, lr, lt, hd);
-        if (map_mask && !map_mask[c.rem]) v = 0.0f;
-        q[i] = v;
-        pq += (double)p[i] * v;
+    for (int64_t sp = (int64_t)blockIdx.x * kThreads + threadIdx.x; sp < d.nvox;
+         sp += (int64_t)gridDim.x * kThreads) {
+        VoxIdx c = vox_index(d, sp);
+        const bool keep = !map_mask || map_mask[sp];
+        float pm = 0.0f, pc = p[sp];
+        for (int32_t f = 0; f < d.nf; ++f) {
+            const int64_t i = (int64_t)f * d.nvox + sp;
+            const float pn = f < d.nf - 1 ? p[i + d.nvox] : 0.0f;
+            c.f = f;
+            float v = q[i] + prior_core<kHeight>(p, d, i, c, lr, lt, hd, pc, pm, pn);
+            if (!keep) v = 0.0f;
+            q[i] = v;
+            pq += (double)pc * v;
+            pm = pc;
+            pc = pn;
+        }
     }
     put_partial(pq, ws.cpart);
 }
 
-// alpha = rr / p.q; x += alpha p; r -= alpha q; q = 0; per-workgroup
+// alpha = rr / p.q; x += alpha p; r -= alpha q; q = 0 when the next P^T
+// adds into q (zero_q; the blocked P^T writes q outright); per-workgroup
 // partials of the new r.r.
 __global__ __launch_bounds__(kThreads) void k_cg_xr(float *__restrict__ x, float *__restrict__ r,
                                                     const float *__restrict__ p,
-                                                    float *__restrict__ q, int64_t n, Workspace ws)
+                                                    float *__restrict__ q, int64_t n, Workspace ws,
+                                                    int32_t zero_q)
 {
     if (stopped(ws.st)) return;
     double alpha;
@@ -368,7 +393,7 @@ __global__ __launch_bounds__(kThreads) void k_cg_xr(float *__restrict__ x, float
         x[i] = (float)((double)x[i] + alpha * pv);
         const float rv = (float)((double)r[i] - alpha * q[i]);
         r[i] = rv;
-        q[i] = 0.0f;
+        if (zero_q) q[i] = 0.0f;
         rr += (double)rv * rv;
     }
     put_partial(rr, ws.cpart + kIterBlocks);
@@ -417,7 +442,8 @@ __global__ void k_fcg_init(Workspace ws, int32_t window, double min_drop)
     s.net_off = s.done || s.fellback;
 }
 
-// x += alpha p; r -= alpha q (q is kept for beta); res2 = r.r; stall test.
+// x += alpha p; r -= alpha q (q is kept for beta); per-workgroup partials
+// of the new r.r, which k_fcg_commit sums.
 __global__ __launch_bounds__(kThreads) void k_fcg_xr(float *__restrict__ x, float *__restrict__ r,
                                                      const float *__restrict__ p,
                                                      const float *__restrict__ q, int64_t n,
@@ -434,32 +460,43 @@ __global__ __launch_bounds__(kThreads) void k_fcg_xr(float *__restrict__ x, floa
         r[i] = rv;
         rr += (double)rv * rv;
     }
-    double trr, unused;
-    if (grid_reduce2(rr, 0.0, ws, trr, unused) && threadIdx.x == 0) {
-        CgState &s = *ws.st;
-        s.res_prev = s.res2;
-        s.res2 = trr;
-        s.iter += 1;
-        ws.hist[s.iter] = sqrt(trr / s.bb);
-        if (bad(trr)) s.nonfinite = 1;
-        s.stall = trr > s.drop2 * s.res_prev ? s.stall + 1 : 0;
-        if (!s.fellback && s.stall >= s.window) {
-            s.fellback = 1;
-            s.fb_iter = s.iter;
-            s.restart = 1;
-            s.stall = 0;
-        }
-        s.done = s.nonfinite || trr <= s.thresh2 || s.iter >= s.max_iter;
-        s.net_off = s.done || s.fellback;
-    }
+    put_partial(rr, ws.cpart + kIterBlocks);
 }
 
-// z.r, z.q, r.r, r.q per workgroup (for k_fcg_p); q = 0.  Workgroup 0
-// snapshots the fall-back state that k_fcg_p reads while it rewrites it.
+// One workgroup: res2 = r.r from k_fcg_xr's `nparts` partials, then the
+// iteration's commit (history, stall test, fall-back, stop test) before the
+// network reads ||r|| and its skip flag.  A single small workgroup after the
+// vector pass costs less than a last-workgroup reduction inside it (one
+// device-scope fence per workgroup).
+__global__ __launch_bounds__(kThreads) void k_fcg_commit(Workspace ws, int32_t nparts)
+{
+    if (stopped(ws.st)) return;
+    const double trr = sum_partials(ws.cpart + kIterBlocks, nparts);
+    if (threadIdx.x != 0) return;
+    CgState &s = *ws.st;
+    s.res_prev = s.res2;
+    s.res2 = trr;
+    s.iter += 1;
+    ws.hist[s.iter] = sqrt(trr / s.bb);
+    if (bad(trr)) s.nonfinite = 1;
+    s.stall = trr > s.drop2 * s.res_prev ? s.stall + 1 : 0;
+    if (!s.fellback && s.stall >= s.window) {
+        s.fellback = 1;
+        s.fb_iter = s.iter;
+        s.restart = 1;
+        s.stall = 0;
+    }
+    s.done = s.nonfinite || trr <= s.thresh2 || s.iter >= s.max_iter;
+    s.net_off = s.done || s.fellback;
+}
+
+// z.r, z.q, r.r, r.q per workgroup (for k_fcg_p); q = 0 when the next P^T
+// adds into q (zero_q).  Workgroup 0 snapshots the fall-back state that
+// k_fcg_p reads while it rewrites it.
 __global__ __launch_bounds__(kThreads) void k_fcg_dots(const float *__restrict__ z,
                                                        const float *__restrict__ r,
                                                        float *__restrict__ q, int64_t n,
-                                                       Workspace ws)
+                                                       Workspace ws, int32_t zero_q)
 {
     if (stopped(ws.st)) return;
     const bool usez = !ws.st->fellback;
@@ -472,7 +509,7 @@ __global__ __launch_bounds__(kThreads) void k_fcg_dots(const float *__restrict__
         a[1] += zv * qv;
         a[2] += rv * rv;
         a[3] += rv * qv;
-        q[i] = 0.0f;
+        if (zero_q) q[i] = 0.0f;
     }
 #pragma unroll
     for (int k = 0; k < 4; ++k) put_partial(a[k], ws.cpart + k * kIterBlocks);
@@ -765,6 +802,9 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)maxit + 1));
     // back-projection strategy and its scratch, fixed for the whole solve
     const int bps = resolve_bp_strategy(*plan, prm->bp_strategy);
+    // the blocked P^T writes every voxel of q; the atomic ones add into a
+    // q that the x/r update has cleared
+    const int bp_acc = bps == TOMO_BP_BLOCKED ? 0 : 1;
     size_t bscr_bytes = 0;
     void *bscr = nullptr;
     if (bps == TOMO_BP_BLOCKED) {
@@ -849,7 +889,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
                                     !frags_ready, &ws.st->net_off);
         frags_ready = true;
         if (e) return e;
-        hipLaunchKernelGGL(k_fcg_dots, dim3(eb), dim3(kThreads), 0, s, z, r, q, n, ws);
+        hipLaunchKernelGGL(k_fcg_dots, dim3(eb), dim3(kThreads), 0, s, z, r, q, n, ws, bp_acc);
         hipLaunchKernelGGL(k_fcg_p, dim3(eb), dim3(kThreads), 0, s, z, r, p, n, ws);
         return hip_fail(hipGetLastError(), "fcg start");
     };
@@ -882,7 +922,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         }
         int e = launch_project_flagged(*plan, g, p, img, s, &ws.st->done);
         if (timed) (void)hipEventRecord(e1, s);
-        if (!e) e = launch_backproject(*plan, g, img, q, true, false, bps, s, &ws.st->done, bscr, bscr_bytes);
+        if (!e) e = launch_backproject(*plan, g, img, q, bp_acc != 0, false, bps, s, &ws.st->done, bscr, bscr_bytes);
         if (timed) {
             (void)hipEventRecord(e2, s);
             evP.push_back(e0);
@@ -893,14 +933,15 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         if (e) return e;
         launch_cg_q(hw, (unsigned)ws.nq, s, p, q, g->map_mask, d, lr, lt, ws, hd);
         if (!fcg) {
-            hipLaunchKernelGGL(k_cg_xr, dim3(ws.nq), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
+            hipLaunchKernelGGL(k_cg_xr, dim3(ws.nq), dim3(kThreads), 0, s, x_d, r, p, q, n, ws, bp_acc);
             hipLaunchKernelGGL(k_cg_p, dim3(ws.nq), dim3(kThreads), 0, s, r, p, n, ws);
         } else {
-            hipLaunchKernelGGL(k_fcg_xr, dim3(eb), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
+            hipLaunchKernelGGL(k_fcg_xr, dim3(ws.nq), dim3(kThreads), 0, s, x_d, r, p, q, n, ws);
+            hipLaunchKernelGGL(k_fcg_commit, dim3(1), dim3(kThreads), 0, s, ws, ws.nq);
             e = convnet_forward_dev(g->cube, prm->precond, r, z, &ws.st->res2, g->map_mask, netws, s,
                                     false, &ws.st->net_off);
             if (e) return e;
-            hipLaunchKernelGGL(k_fcg_dots, dim3(eb), dim3(kThreads), 0, s, z, r, q, n, ws);
+            hipLaunchKernelGGL(k_fcg_dots, dim3(eb), dim3(kThreads), 0, s, z, r, q, n, ws, bp_acc);
             hipLaunchKernelGGL(k_fcg_p, dim3(eb), dim3(kThreads), 0, s, z, r, p, n, ws);
         }
         return hip_fail(hipGetLastError(), "cg iteration launch");
@@ -1223,7 +1264,7 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
             o.src[k] = sy[(size_t)k].img;
             o.dst[k] = sy[(size_t)k].q;
         }
-        o.acc = 1;
+        o.acc = 0;  // every voxel of q written: the x/r update need not clear it
         return batch_backproject_ops(bt, o, st);
     };
     auto part_vec = [&](hipStream_t st) -> int {
@@ -1232,7 +1273,7 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
             if (c.skip) continue;
             const unsigned eb = (unsigned)c.ws.nq;
             launch_cg_q(c.hw, eb, st, c.p, c.q, c.mm, c.d, c.lr, c.lt, c.ws, c.hd);
-            hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, st, x_d[k], c.r, c.p, c.q, c.n, c.ws);
+            hipLaunchKernelGGL(k_cg_xr, dim3(eb), dim3(kThreads), 0, st, x_d[k], c.r, c.p, c.q, c.n, c.ws, 0);
             hipLaunchKernelGGL(k_cg_p, dim3(eb), dim3(kThreads), 0, st, c.r, c.p, c.n, c.ws);
         }
         return hip_fail(hipGetLastError(), "batched cg iteration launch");
