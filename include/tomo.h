@@ -509,13 +509,13 @@ void tomo_autotune_clear(void);
  * cubes of one time-dependent reconstruction, whose projector is
  * block-diagonal over the frames (Eq. srt_t, coupled only through the
  * temporal prior of Eq. stsrt), plus independent reconstructions of other
- * sizes.  One persistent P kernel and one
- * persistent P^T kernel (owner-computes, as TOMO_BP_BLOCKED) drain device
- * work queues of (system, view, pixel tile) and (system, frame, voxel
- * block, owner) items covering every system; each system uses the launch
- * shape of its size class (tomo_autotune) as it was when the batch was
- * created, and its results equal the per-system calls with that tuning
- * (tomo_project; tomo_backproject_ex with TOMO_BP_BLOCKED) bit for bit.
+ * sizes.  One persistent P^T kernel (owner-computes, as TOMO_BP_BLOCKED)
+ * drains device work queues of (system, frame, voxel block, owner) items
+ * covering every system; P runs each system's own launch (the projection
+ * needs no queue).  Each system uses the launch shape of its size class
+ * (tomo_autotune) as it was when the batch was created, and its results
+ * equal the per-system calls with that tuning (tomo_project;
+ * tomo_backproject_ex with TOMO_BP_BLOCKED) bit for bit.
  *   systems: HOST array of nsystems geometries (1..32); their masks (DEVICE)
  *   must stay valid while the batch exists, their view arrays need not.
  * The batch owns its device work queues and scratch: use it from one stream
@@ -536,21 +536,23 @@ int tomo_batch_backproject(tomo_batch b, const float *const *images_d,
 /* Writes outside a voxel block's LDS box since the last call (must be 0);
  * synchronises the device and resets the counter. */
 int tomo_batch_binning_spills(tomo_batch b, int64_t *count_h);
-/* Launch sizes: which 0 = P items, 1 = P^T items, 2 = P workgroups,
- * 3 = P^T workgroups (resident, persistent); -1 for a NULL batch. */
+/* Launch sizes: which 0 = P tiles, 1 = P^T items, 2 = P workgroups (one
+ * per tile, over the systems' launches), 3 = P^T workgroups (resident,
+ * persistent); -1 for a NULL batch. */
 int64_t tomo_batch_items(tomo_batch b, int32_t which);
 /*
  * CG on every system at once (plain CG as tomo_cg_solve; each system has
  * its own parameters, state, convergence test, true-residual confirmation
- * and report).  One iteration is one batched P, one batched P^T and three
- * vector kernels per system; converged systems are skipped on the device.
+ * and report).  One iteration is the systems' P launches, one batched P^T
+ * and three vector kernels per system; converged systems are skipped on
+ * the device.
  * check_every and use_graph come from params[0]: with use_graph = 1 the
  * check_every iterations between host checks are captured once as a HIP
  * graph and replayed.  precond and record_* must be unset
  * (TOMO_EUNSUPPORTED); bp_strategy is ignored (always blocked).
  * With reports[0].time_kernels = 1, every report's ms_project and
- * ms_backproject receive the total time of the batched P and P^T launches
- * of the iterations (one launch each per iteration, shared by all systems;
+ * ms_backproject receive the total time of the P launches and of the
+ * batched P^T launches of the iterations (shared by all systems;
  * HIP events on the launch stream, recorded as event-record nodes of the
  * graph under use_graph; NaN if the graph could not hold them).
  *   y_d, x_d: HOST arrays of DEVICE pointers.  params, reports: HOST arrays

@@ -22,6 +22,8 @@ struct SysDev {
     float *part;          // owner partials [splits][ntot] (splits > 1)
     uint16_t *kept_pre;   // kept-pixel rows of the data mask (row intervals only), or null
     uint16_t *kept_cols;
+    float *bricked;       // P's bricked copy of M x (the system's tuning asks for bricks), or null
+    BrickDev bk;
     BlockDev bd;
     int32_t nviews;
     int32_t p_log2_bw;
@@ -50,19 +52,21 @@ struct tomo_batch_s {
     int device = 0;
     int32_t nsys = 0;
     std::vector<tomo::PlanRef> plans;
+    std::vector<tomo_tuning> tunings;  // each system's tuning at creation (its P launch shape and layout)
     std::vector<tomo_geometry> geoms;  // headers (views and obstacle unused after planning)
     std::vector<tomo::SysDev> sys_h;
     tomo::SysDev *sys_d = nullptr;
     int64_t ntiles = 0, nitems = 0;
     int32_t nviews = 0;
-    unsigned long long *q = nullptr;   // [2][kQueues + 1]: P queues, then P^T queues
+    unsigned long long *q = nullptr;   // [kQueues + 1]: P^T work queues, then the leave counter
     uint32_t *ymax = nullptr;
     float *part = nullptr;
     unsigned *spill = nullptr;
     size_t lds_bytes = 0;
     unsigned grid_p = 0, grid_b = 0;
     bool rows = false;  // P^T walks footprint row intervals (most systems' plans ask for them)
-    int32_t nt = 256;   // lanes per workgroup of the persistent P^T (the largest any system's tuning asks for)
+    int32_t nt = 256;   // lanes per workgroup of the persistent P^T (the dominant system's tuning)
     uint16_t *kept = nullptr;  // kept-pixel rows of the systems' data masks
+    float *bricks = nullptr;   // bricked copies of the cubes of the systems that walk bricks in P
     ~tomo_batch_s();
 };

@@ -1,27 +1,30 @@
 // Batched persistent launches over several independent systems (time-frame
 // cubes and independent reconstructions of uneven sizes).
 //
-// * One persistent P kernel and one persistent P^T kernel cover every
-//   system.  Their grids hold as many workgroups as the chip keeps resident;
-//   each workgroup pulls work items - (system, view, 16x16 pixel tile) for P,
-//   (system, frame, voxel block, owner) for the owner-computes P^T - from
-//   device work queues until they are empty, so systems of very different
-//   sizes share the machine without one launch per system and without tail
-//   effects between them.  The item list is dealt to eight queues, one per
-//   XCD, in runs of neighbouring items (64 tiles, 4 blocks): a workgroup
-//   drains the queue of its own XCD first (neighbouring tiles share cube
-//   lines in that XCD's L2) and then takes from the others.  Dealt in runs
-//   rather than cut into eight contiguous parts, the queues advance through
-//   the list together, so the XCDs work on one frame of a multi-frame cube
-//   at a time and its lines stay in the Infinity Cache (eight 64 MiB
-//   frames at once do not fit).  The last workgroup to leave resets the queues, so a
-//   launch needs no host-side clearing and can be captured in a graph.
-// * Each item runs the same device code as the single-geometry launches
-//   (project_tile, blocked_item) with the system's own tuned shape, so a
-//   batched result equals the per-system one bit for bit.
+// * One persistent P^T launch covers every system, so that systems of very
+//   different sizes share the machine without one launch per system and
+//   without tail effects between them.  P, whose tiles need no owner and
+//   no queue, runs each system's own tuned single-geometry launch (tile
+//   shape, XCD order, cube layout; the bricked copies live in the batch);
+//   a persistent P over all systems measured slower per tile than those
+//   launches, whatever its register budget.  The P^T grid holds
+//   as many workgroups as the chip keeps resident; each pulls (system,
+//   frame, voxel block, owner) items from eight device work queues, one per
+//   XCD, draining its own XCD's queue first.  The blocks are dealt to the
+//   queues in runs of 4, so that the queues advance through the list
+//   together and the XCDs work on one frame of a multi-frame cube at a
+//   time: the images and voxels of that frame stay in the Infinity Cache
+//   (eight 64 MiB frames at once do not fit).  The last workgroup to leave
+//   resets the queues, so a launch needs no host-side clearing and can be
+//   captured in a graph.
+// * A P^T item runs the same device code as the single-geometry launch
+//   (blocked_item) with the system's own owners per block; the workgroup
+//   size and the largest block follow the dominant system (most rays),
+//   which changes no bit of the result.  A batched result equals the
+//   per-system one bit for bit.
 // * The batched CG keeps one state (scalars, done flag) per system on the
-//   device.  An iteration is one batched P, one batched P^T and three vector
-//   kernels per system; a system that has converged is skipped by every
+//   device.  An iteration is the systems' P launches, one batched P^T and
+//   three vector kernels per system; a system that has converged is skipped by every
 //   kernel through its done flag.  With use_graph, the iterations of one
 //   check interval are captured once as a HIP graph and replayed.
 #include <math.h>
@@ -53,6 +56,17 @@ __device__ inline int64_t next_item(unsigned long long *q, int64_t total, int64_
     return -1;
 }
 
+// A value the whole workgroup holds alike (read from LDS after a barrier),
+// declared uniform so that what is indexed by it - the system's table
+// entry, its pointers and shapes - lives in scalar registers.
+__device__ inline int64_t uniform(int64_t v)
+{
+    const uint64_t u = (uint64_t)v;
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)u);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(u >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
 // The last workgroup out clears the queues for the next launch.
 __device__ inline void leave_queues(unsigned long long *q)
 {
@@ -77,45 +91,6 @@ __device__ inline int find_system(int nsys, int64_t t, F begin)
         else hi = mid - 1;
     }
     return lo;
-}
-
-__global__ __launch_bounds__(kThreads) void k_batch_project(const SysDev *__restrict__ sys, int32_t nsys,
-                                                            Operands ops, int64_t ntiles,
-                                                            unsigned long long *q)
-{
-    __shared__ int64_t s_item;
-    int visited = 0;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = next_item(q, ntiles, 64, visited);
-        __syncthreads();
-        const int64_t t = s_item;
-        __syncthreads();
-        if (t < 0) break;
-        const int k = find_system(nsys, t, [&](int i) { return sys[i].tile_begin; });
-        if (ops.done[k] && *ops.done[k]) continue;
-        const SysDev &sd = sys[k];
-        const int64_t lt = t - sd.tile_begin;
-        const bool mm = ops.map && sd.map_mask, dm = sd.data_mask != nullptr;
-#define TOMO_TILE(M, D, O)                                                                                   \
-    project_tile<M, D, O>(sd.grid, sd.views, sd.nviews, sd.p_log2_bw, lt, sd.maxit, ops.src[k], sd.map_mask, \
-                          sd.data_mask, ops.dst[k])
-        if (sd.grid.has_sph) {  // the obstacle's variant: one code path for every mask combination
-            if (mm && dm) TOMO_TILE(true, true, true);
-            else if (mm) TOMO_TILE(true, false, true);
-            else if (dm) TOMO_TILE(false, true, true);
-            else TOMO_TILE(false, false, true);
-        } else if (mm && dm) {
-            TOMO_TILE(true, true, false);
-        } else if (mm) {
-            TOMO_TILE(true, false, false);
-        } else if (dm) {
-            TOMO_TILE(false, true, false);
-        } else {
-            TOMO_TILE(false, false, false);
-        }
-#undef TOMO_TILE
-    }
-    leave_queues(q);
 }
 
 // max |y| per view share for every view of every system.
@@ -145,7 +120,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     for (;;) {
         if (threadIdx.x == 0) s_item = next_item(q, nitems, 4, visited);
         __syncthreads();
-        const int64_t t = s_item;
+        const int64_t t = uniform(s_item);
         __syncthreads();
         if (t < 0) break;
         const int k = find_system(nsys, t, [&](int i) { return sys[i].item_begin; });
@@ -214,17 +189,32 @@ tomo_batch_s::~tomo_batch_s()
     if (ymax) (void)hipFree(ymax);
     if (part) (void)hipFree(part);
     if (kept) (void)hipFree(kept);
+    if (bricks) (void)hipFree(bricks);
     if (spill) (void)hipFree(spill);
     (void)hipSetDevice(cur);
 }
 
 namespace tomo {
 
-int batch_project_ops(tomo_batch b, const Operands &ops, hipStream_t s)
+int batch_project_ops(tomo_batch b, const Operands &h, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_batch_project, dim3(b->grid_p), dim3(kThreads), 0, s, b->sys_d, b->nsys, ops,
-                       b->ntiles, b->q);
-    return hip_fail(hipGetLastError(), "batched projection launch");
+    // each system's own tuned P (tile shape, XCD order, cube layout), the
+    // bricked copies in the batch's buffers
+    for (int k = 0; k < b->nsys; ++k) {
+        const SysDev &sd = b->sys_h[(size_t)k];
+        const Plan &p = *b->plans[(size_t)k];
+        const tomo_geometry *g = &b->geoms[(size_t)k];
+        const tomo_tuning &tu = b->tunings[(size_t)k];
+        int rc;
+        if (sd.bricked) {
+            rc = brick_copy_launch(p, h.src[k], h.map ? sd.map_mask : nullptr, sd.bk, sd.bricked, s, h.done[k]);
+            if (!rc) rc = launch_project_from_bricks(p, g, sd.bricked, sd.bk, h.dst[k], s, h.done[k], tu);
+        } else {
+            rc = launch_project_tuned(p, g, h.src[k], h.dst[k], h.map != 0, s, h.done[k], tu);
+        }
+        if (rc) return rc;
+    }
+    return TOMO_OK;
 }
 
 // The persistent P^T kernel for a batch's workgroup size and row mode.
@@ -256,7 +246,7 @@ int batch_backproject_ops(tomo_batch b, const Operands &ops, hipStream_t s)
     }
 #define TOMO_BATCH_BP(NT, R)                                                                                     \
     hipLaunchKernelGGL((k_batch_backproject<NT, R>), dim3(b->grid_b), dim3(NT), b->lds_bytes, s, b->sys_d, b->nsys, \
-                       ops, b->nitems, b->ymax, b->q + (kQueues + 1), b->spill)
+                       ops, b->nitems, b->ymax, b->q, b->spill)
     if (b->nt == 512) {
         if (b->rows) TOMO_BATCH_BP(512, true);
         else TOMO_BATCH_BP(512, false);
@@ -294,8 +284,10 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
     if (!b) return set_error(TOMO_ENOMEM, "tomo_batch_create: host allocation failed");
     (void)hipGetDevice(&b->device);
     b->nsys = nsystems;
-    int64_t part_floats = 0, kept_pix = 0;
+    int64_t part_floats = 0, kept_pix = 0, brick_floats = 0;
     int nrows = 0;  // systems whose plans ask for footprint row intervals
+    std::vector<PlanRef> plans;
+    std::vector<tomo_tuning> tunings;
     for (int k = 0; k < nsystems; ++k) {
         int st = TOMO_OK;
         PlanRef p = get_plan(&systems[k], &st);
@@ -303,7 +295,28 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
             delete b;
             return st;
         }
-        const tomo_tuning tu = tuning_for(*p);
+        plans.push_back(p);
+        tunings.push_back(tuning_for(*p));
+    }
+    // One workgroup size and LDS size serve every item of the persistent
+    // P^T: the dominant system's (most rays).  The others keep their tuned
+    // blocks when those fit its LDS, else take its block shape, and keep
+    // their tuned number of owners per block: with the same owners (the same
+    // views summed in each owner's exact bins) the result does not depend
+    // on the block shape or the workgroup size, bit for bit.
+    int dom = 0;
+    for (int k = 1; k < nsystems; ++k)
+        if (plans[(size_t)k]->npix > plans[(size_t)dom]->npix) dom = k;
+    const BlockedShape dom_bs = blocked_shape(*plans[(size_t)dom], tunings[(size_t)dom]);
+    const int64_t dom_bins = (int64_t)dom_bs.b[0] * dom_bs.b[1] * dom_bs.b[2];
+    std::vector<bool> bricked(nsystems, false);
+    for (int k = 0; k < nsystems; ++k) {
+        const PlanRef &p = plans[(size_t)k];
+        tomo_tuning tu = tunings[(size_t)k];
+        tu.bp_splits = blocked_shape(*p, tu).splits;
+        tu.bp_threads = dom_bs.nt;
+        if ((int64_t)tu.bp_block[0] * tu.bp_block[1] * tu.bp_block[2] > dom_bins)
+            for (int a = 0; a < 3; ++a) tu.bp_block[a] = dom_bs.b[a];
         const BlockedShape bs = blocked_shape(*p, tu);
         SysDev sd;
         memset(&sd, 0, sizeof(sd));
@@ -321,6 +334,10 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
         sd.bd.maxit = bs.b[0] + bs.b[1] + bs.b[2] + 3;
         sd.nviews = p->nviews;
         sd.p_log2_bw = tu.p_bundle;
+        if (tu.p_layout >= 2 && brick_layout(*p, tu.p_layout, sd.bk)) {
+            bricked[(size_t)k] = true;
+            brick_floats += sd.bk.frame_stride * p->grid.nframes;
+        }
         sd.maxit = p->max_steps;
         sd.view_begin = b->nviews;
         sd.tile_begin = b->ntiles;
@@ -332,21 +349,22 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
         if (bs.splits > 1) part_floats += (int64_t)bs.splits * sd.ntot;
         const size_t lds = sizeof(unsigned long long) * ((size_t)bs.b[0] * bs.b[1] * bs.b[2] + 1);  // + dummy bin
         b->lds_bytes = lds > b->lds_bytes ? lds : b->lds_bytes;
-        b->nt = bs.nt > b->nt ? bs.nt : b->nt;
+        b->nt = bs.nt;
         nrows += p->bp_rows ? 1 : 0;
         if (systems[k].data_mask) kept_pix += p->npix;
         b->plans.push_back(p);
+        b->tunings.push_back(tunings[(size_t)k]);
         b->geoms.push_back(systems[k]);
         b->geoms.back().obstacle = nullptr;  // captured in the plan's grid
         b->geoms.back().gains = nullptr;     // captured in the plan's view table
         b->sys_h.push_back(sd);
     }
-    if (b->ntiles >= ((int64_t)1 << 40) || b->nitems >= ((int64_t)1 << 40)) {
+    if (b->ntiles >= ((int64_t)1 << 31) || b->nitems >= ((int64_t)1 << 40)) {
         delete b;
         return set_error(TOMO_EINVAL, "tomo_batch_create: too much work for one batch");
     }
-    hipError_t e = hipMalloc((void **)&b->q, sizeof(unsigned long long) * 2 * (kQueues + 1));
-    if (e == hipSuccess) e = hipMemset(b->q, 0, sizeof(unsigned long long) * 2 * (kQueues + 1));
+    hipError_t e = hipMalloc((void **)&b->q, sizeof(unsigned long long) * (kQueues + 1));
+    if (e == hipSuccess) e = hipMemset(b->q, 0, sizeof(unsigned long long) * (kQueues + 1));
     if (e == hipSuccess) e = hipMalloc((void **)&b->ymax, sizeof(uint32_t) * (size_t)b->nviews * kYmaxParts);
     if (e == hipSuccess) e = hipMalloc((void **)&b->spill, sizeof(unsigned));
     if (e == hipSuccess) e = hipMemset(b->spill, 0, sizeof(unsigned));
@@ -354,13 +372,18 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
     b->rows = 2 * nrows > (int)b->sys_h.size();
     if (e == hipSuccess && b->rows && kept_pix > 0)
         e = hipMalloc((void **)&b->kept, 2 * sizeof(uint16_t) * (size_t)kept_pix);
+    if (e == hipSuccess && brick_floats > 0) e = hipMalloc((void **)&b->bricks, sizeof(float) * (size_t)brick_floats);
     if (e != hipSuccess) {
         delete b;
         return set_error(TOMO_ENOMEM, "tomo_batch_create: device allocation failed (%s)", hipGetErrorString(e));
     }
-    int64_t off = 0, koff = 0;
+    int64_t off = 0, koff = 0, boff = 0;
     for (size_t k = 0; k < b->sys_h.size(); ++k) {
         SysDev &sd = b->sys_h[k];
+        if (bricked[k]) {
+            sd.bricked = b->bricks + boff;
+            boff += sd.bk.frame_stride * sd.grid.nframes;
+        }
         if (sd.bd.splits > 1) {
             sd.part = b->part + off;
             off += (int64_t)sd.bd.splits * sd.ntot;
@@ -379,9 +402,8 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
         return set_error(TOMO_ENOMEM, "tomo_batch_create: system table upload failed (%s)", hipGetErrorString(e));
     }
     // persistent grids: as many workgroups as stay resident, at most one per item
-    int cus = 0, per_p = 0, per_b = 0;
+    int cus = 0, per_b = 0;
     (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device);
-    (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_p, k_batch_project, kThreads, 0);
     {
         BlockedShape probe;
         probe.b[0] = 1;
@@ -402,10 +424,9 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
         (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_b, kern, b->nt, b->lds_bytes);
     }
     cus = cus > 0 ? cus : 256;
-    per_p = per_p > 0 ? per_p : 1;
     per_b = per_b > 0 ? per_b : 1;
-    const int64_t gp = (int64_t)cus * per_p, gb = (int64_t)cus * per_b;
-    b->grid_p = (unsigned)(gp < b->ntiles ? gp : (b->ntiles > 0 ? b->ntiles : 1));
+    const int64_t gb = (int64_t)cus * per_b;
+    b->grid_p = (unsigned)(b->ntiles > 0 ? b->ntiles : 1);  // one workgroup per tile
     b->grid_b = (unsigned)(gb < b->nitems ? gb : (b->nitems > 0 ? b->nitems : 1));
     *out = b;
     return TOMO_OK;

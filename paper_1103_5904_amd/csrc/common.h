@@ -201,6 +201,22 @@ tomo_tuning tuning_for(const Plan &p);
 int launch_project(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
                    bool use_map_mask, hipStream_t s);
 // The same path with an explicit tuning (the autotuner's candidates).
+// A bricked copy of the cube: bricks of B = 2^k voxels a side in x-fastest
+// order, x fastest inside each brick, every frame padded to whole bricks.
+struct BrickDev {
+    int32_t k;            // log2 of the brick side
+    int32_t nb[3];        // bricks per axis
+    int64_t frame_stride; // floats per padded frame
+};
+// The bricked layout of a plan's cube with bricks of 2^k (false: a frame
+// would pass 2^32 floats), and the copy of M x into it (map_mask may be
+// null; frames past the done flag's raise are skipped like any launch).
+bool brick_layout(const Plan &p, int k, BrickDev &bk);
+int brick_copy_launch(const Plan &p, const float *cube, const uint8_t *map_mask, const BrickDev &bk, float *out,
+                      hipStream_t s, const int *done_flag);
+// P from a bricked copy made by brick_copy_launch (the map mask is in it).
+int launch_project_from_bricks(const Plan &p, const tomo_geometry *g, const float *br, const BrickDev &bk,
+                               float *images, hipStream_t s, const int *done_flag, const tomo_tuning &tu);
 int launch_project_with(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
                         bool use_map_mask, hipStream_t s, const tomo_tuning &tu);
 // scratch: blocked strategy only; when null the launcher takes stream-ordered

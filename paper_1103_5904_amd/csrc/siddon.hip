@@ -216,7 +216,7 @@ int launch_project(const Plan &p, const tomo_geometry *g, const float *cube, flo
 
 // The bricked layout of a plan's frames for brick side 2^k, or false when a
 // padded frame would not be addressable with 32-bit element offsets.
-static bool brick_layout(const Plan &p, int k, BrickDev &bk)
+bool brick_layout(const Plan &p, int k, BrickDev &bk)
 {
     const int B = 1 << k;
     bk.k = k;
@@ -227,6 +227,36 @@ static bool brick_layout(const Plan &p, int k, BrickDev &bk)
     }
     bk.frame_stride = stride;
     return stride < ((int64_t)1 << 32);
+}
+
+int brick_copy_launch(const Plan &p, const float *cube, const uint8_t *map_mask, const BrickDev &bk, float *out,
+                      hipStream_t s, const int *done_flag)
+{
+    int64_t nb = grid_blocks(p.grid.nvox);
+    nb = nb > 8192 ? 8192 : nb;
+    hipLaunchKernelGGL(k_brick_copy, dim3((unsigned)nb), dim3(kThreads), 0, s, cube, map_mask, p.grid, bk, out,
+                       done_flag);
+    return hip_fail(hipGetLastError(), "brick copy launch");
+}
+
+int launch_project_from_bricks(const Plan &p, const tomo_geometry *g, const float *br, const BrickDev &bk,
+                               float *images, hipStream_t s, const int *done_flag, const tomo_tuning &tu)
+{
+    const Bundle b{tu.p_bundle, tu.p_xcd_remap};
+    const bool dm = g->data_mask != nullptr;
+    const dim3 grid((unsigned)p.ntiles), blk(kThreads);
+#define TOMO_LAUNCH_PB(D, O)                                                                                   \
+    hipLaunchKernelGGL((k_project_bricked<D, O>), grid, blk, 0, s, p.grid, p.views_d, p.nviews, b, p.max_steps, \
+                       br, bk, g->data_mask, images, done_flag)
+    if (dm) {
+        if (p.grid.has_sph) TOMO_LAUNCH_PB(true, true);
+        else TOMO_LAUNCH_PB(true, false);
+    } else {
+        if (p.grid.has_sph) TOMO_LAUNCH_PB(false, true);
+        else TOMO_LAUNCH_PB(false, false);
+    }
+#undef TOMO_LAUNCH_PB
+    return hip_fail(hipGetLastError(), "bricked projection kernel launch");
 }
 
 int launch_project_bricked(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
@@ -241,28 +271,8 @@ int launch_project_bricked(const Plan &p, const tomo_geometry *g, const float *c
         lin.p_layout = 0;
         return launch_project_tuned(p, g, cube, images, use_map_mask, s, done_flag, lin);
     }
-    const uint8_t *mm = use_map_mask ? g->map_mask : nullptr;
-    int64_t nb = grid_blocks(p.grid.nvox);
-    nb = nb > 8192 ? 8192 : nb;
-    hipLaunchKernelGGL(k_brick_copy, dim3((unsigned)nb), dim3(kThreads), 0, s, cube, mm, p.grid, bk, br, done_flag);
-    int rc = hip_fail(hipGetLastError(), "brick copy launch");
-    if (!rc) {
-        const Bundle b{tu.p_bundle, tu.p_xcd_remap};
-        const bool dm = g->data_mask != nullptr;
-        const dim3 grid((unsigned)p.ntiles), blk(kThreads);
-#define TOMO_LAUNCH_PB(D, O)                                                                                   \
-    hipLaunchKernelGGL((k_project_bricked<D, O>), grid, blk, 0, s, p.grid, p.views_d, p.nviews, b, p.max_steps, \
-                       br, bk, g->data_mask, images, done_flag)
-        if (dm) {
-            if (p.grid.has_sph) TOMO_LAUNCH_PB(true, true);
-            else TOMO_LAUNCH_PB(true, false);
-        } else {
-            if (p.grid.has_sph) TOMO_LAUNCH_PB(false, true);
-            else TOMO_LAUNCH_PB(false, false);
-        }
-#undef TOMO_LAUNCH_PB
-        rc = hip_fail(hipGetLastError(), "bricked projection kernel launch");
-    }
+    int rc = brick_copy_launch(p, cube, use_map_mask ? g->map_mask : nullptr, bk, br, s, done_flag);
+    if (!rc) rc = launch_project_from_bricks(p, g, br, bk, images, s, done_flag, tu);
     (void)scratch_free(br, s);
     return rc;
 }

@@ -343,10 +343,13 @@ __global__ __launch_bounds__(kThreads) void k_cg_start(const float *__restrict__
     }
 }
 
-// q = M (q + prior(p)); per-workgroup partials of p.q.  A thread takes one
-// spatial voxel through all frames, so that the temporal neighbours p[f -+ 1]
-// come from registers (each p read once from memory, the map mask once per
-// voxel) and the voxel's coordinates are found once.
+// q = M (q + prior(p)); per-workgroup partials of p.q.  Each workgroup
+// takes one contiguous span of the vector, and the spans of one XCD are
+// adjacent (MI355X deals consecutive workgroups to its 8 XCDs in turn), so
+// the stencil's neighbours a row and a plane away were read into the same
+// XCD's L2 by its own workgroups; with one frame per XCD, the temporal
+// neighbours are the lines that the neighbouring XCDs are reading at the
+// same time.
 template <bool kHeight>
 __global__ __launch_bounds__(kThreads) void k_cg_q(const float *__restrict__ p,
                                                    float *__restrict__ q,
@@ -354,23 +357,16 @@ __global__ __launch_bounds__(kThreads) void k_cg_q(const float *__restrict__ p,
                                                    float lr, float lt, Workspace ws, HeightDev hd)
 {
     if (ws.st->done) return;
+    const int64_t span = ((d.total + gridDim.x - 1) / gridDim.x + kThreads - 1) / kThreads * kThreads;
+    const int64_t beg = xcd_remap(blockIdx.x, gridDim.x) * span;
+    const int64_t end = beg + span < d.total ? beg + span : d.total;
     double pq = 0.0;
-    for (int64_t sp = (int64_t)blockIdx.x * kThreads + threadIdx.x; sp < d.nvox;
-         sp += (int64_t)gridDim.x * kThreads) {
-        VoxIdx c = vox_index(d, sp);
-        const bool keep = !map_mask || map_mask[sp];
-        float pm = 0.0f, pc = p[sp];
-        for (int32_t f = 0; f < d.nf; ++f) {
-            const int64_t i = (int64_t)f * d.nvox + sp;
-            const float pn = f < d.nf - 1 ? p[i + d.nvox] : 0.0f;
-            c.f = f;
-            float v = q[i] + prior_core<kHeight>(p, d, i, c, lr, lt, hd, pc, pm, pn);
-            if (!keep) v = 0.0f;
-            q[i] = v;
-            pq += (double)pc * v;
-            pm = pc;
-            pc = pn;
-        }
+    for (int64_t i = beg + threadIdx.x; i < end; i += kThreads) {
+        const VoxIdx c = vox_index(d, i);
+        float v = q[i] + prior_at<kHeight>(p, d, i, c, lr, lt, hd);
+        if (map_mask && !map_mask[c.rem]) v = 0.0f;
+        q[i] = v;
+        pq += (double)p[i] * v;
     }
     put_partial(pq, ws.cpart);
 }
@@ -1151,29 +1147,31 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
             o.done[k] = (all_flags || sy[(size_t)k].skip) ? &states[k].done : nullptr;
         return o;
     };
-    // b = M P^T y
-    {
-        Operands o = ops_of(true);
-        for (int k = 0; k < ns; ++k) {
-            o.src[k] = y_d[k];
-            o.dst[k] = sy[(size_t)k].b;
-        }
-        o.map = 1;
-        rc = batch_backproject_ops(bt, o, s);
-        if (rc) return rc;
+    // The operand sets of the solve: the right-hand side, the true
+    // residual's P and P^T, an iteration's P and P^T.
+    enum { kRhs, kAxP, kAxPT, kItP, kItPT, kSets };
+    Operands oset[kSets];
+    for (int i = 0; i < kSets; ++i) oset[i] = ops_of(i != kAxP && i != kAxPT);
+    for (int k = 0; k < ns; ++k) {
+        const Sys &c = sy[(size_t)k];
+        oset[kRhs].src[k] = y_d[k];
+        oset[kRhs].dst[k] = c.b;
+        oset[kAxP].src[k] = x_d[k];
+        oset[kAxP].dst[k] = c.img;
+        oset[kAxPT].src[k] = c.img;
+        oset[kAxPT].dst[k] = c.q;
+        oset[kItP].src[k] = c.p;
+        oset[kItP].dst[k] = c.img;
+        oset[kItPT].src[k] = c.img;
+        oset[kItPT].dst[k] = c.q;  // every voxel of q written: the x/r update need not clear it
     }
+    oset[kRhs].map = 1;
+    // b = M P^T y
+    rc = batch_backproject_ops(bt, oset[kRhs], s);
+    if (rc) return rc;
     auto apply_A_x = [&]() -> int {  // q = (P^T P) x for every active system (prior added by k_true_res)
-        Operands o = ops_of(false);
-        for (int k = 0; k < ns; ++k) {
-            o.src[k] = x_d[k];
-            o.dst[k] = sy[(size_t)k].img;
-        }
-        int e = batch_project_ops(bt, o, s);
-        for (int k = 0; k < ns; ++k) {
-            o.src[k] = sy[(size_t)k].img;
-            o.dst[k] = sy[(size_t)k].q;
-        }
-        if (!e) e = batch_backproject_ops(bt, o, s);
+        int e = batch_project_ops(bt, oset[kAxP], s);
+        if (!e) e = batch_backproject_ops(bt, oset[kAxPT], s);
         for (auto &c : sy)
             if (!c.skip) {
                 c.n_proj++;
@@ -1250,23 +1248,8 @@ int tomo_batch_cg_solve(tomo_batch bt, const float *const *y_d, float *const *x_
     };
 
     // the three parts of one iteration of every system
-    auto part_p = [&](hipStream_t st) -> int {
-        Operands o = ops_of(true);
-        for (int k = 0; k < ns; ++k) {
-            o.src[k] = sy[(size_t)k].p;
-            o.dst[k] = sy[(size_t)k].img;
-        }
-        return batch_project_ops(bt, o, st);
-    };
-    auto part_bp = [&](hipStream_t st) -> int {
-        Operands o = ops_of(true);
-        for (int k = 0; k < ns; ++k) {
-            o.src[k] = sy[(size_t)k].img;
-            o.dst[k] = sy[(size_t)k].q;
-        }
-        o.acc = 0;  // every voxel of q written: the x/r update need not clear it
-        return batch_backproject_ops(bt, o, st);
-    };
+    auto part_p = [&](hipStream_t st) -> int { return batch_project_ops(bt, oset[kItP], st); };
+    auto part_bp = [&](hipStream_t st) -> int { return batch_backproject_ops(bt, oset[kItPT], st); };
     auto part_vec = [&](hipStream_t st) -> int {
         for (int k = 0; k < ns; ++k) {
             Sys &c = sy[(size_t)k];

@@ -343,14 +343,6 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
     images[pix] = out;
 }
 
-// A bricked copy of the cube: bricks of B = 2^k voxels a side in x-fastest
-// order, x fastest inside each brick, every frame padded to whole bricks.
-struct BrickDev {
-    int32_t k;            // log2 of the brick side
-    int32_t nb[3];        // bricks per axis
-    int64_t frame_stride; // floats per padded frame
-};
-
 // Offset of voxel (i0, i1, i2) in its frame of the bricked copy.
 __device__ inline uint32_t brick_offset(const BrickDev &bk, int i0, int i1, int i2)
 {
