@@ -337,79 +337,6 @@ __global__ __launch_bounds__(kThreads) void k_conv16(const uint16_t *__restrict_
     conv16_tile(region, frag, bias, d, x0, y0, z0, relu, mask, out);
 }
 
-// Layers 1 and 2 in one pass (inference): the layer-1 activations of the
-// tile's one-voxel halo region are computed straight into the LDS region
-// from the input's two-voxel halo region, instead of being written out and
-// staged back (64 MB each way at 128^3).  Each activation is computed
-// exactly as k_conv1 computes it (the same three MFMA instructions on the
-// same split operands, bias, ReLU and rounding), and region voxels outside
-// the volume are the zero padding of layer 2, so a2 equals the two-kernel
-// result bit for bit.
-constexpr int kXX = kRX + 2, kXY = kRY + 2, kXZ = kRZ + 2, kXRegion = kXX * kXY * kXZ;
-constexpr int kRegionGroups = (kRegion + 15) / 16;
-
-__global__ __launch_bounds__(kThreads) void k_conv12(const bf16x8 *__restrict__ frag,
-                                                     const float *__restrict__ P,
-                                                     const float *__restrict__ x, Vol d,
-                                                     const double *__restrict__ norm2,
-                                                     uint16_t *__restrict__ a2,
-                                                     const int *__restrict__ skip)
-{
-    __shared__ float xs[kXRegion];
-    __shared__ uint4 region[kRegion * 2];
-    if (skip && *skip) return;
-    const float s = read_scale(norm2);
-    const float inv = s > 0.0f ? 1.0f / s : 0.0f;
-    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
-    for (int e = threadIdx.x; e < kXRegion; e += kThreads) {
-        const int ex = e % kXX, ey = (e / kXX) % kXY, ez = e / (kXX * kXY);
-        const int gx = x0 + ex - 2, gy = y0 + ey - 2, gz = z0 + ez - 2;
-        float v = 0.0f;
-        if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
-            v = x[((int64_t)gz * d.ny + gy) * d.nx + gx] * inv;
-        xs[e] = v;
-    }
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int vl = lane % 16, g = lane / 16, cg = 4 * g;
-    {
-        const bf16x8 wh = frag[kFrag1 + lane], wl = frag[kFrag1 + 64 + lane];
-        float b1[4];
-#pragma unroll
-        for (int r = 0; r < 4; ++r) b1[r] = P[OB1 + cg + r];
-        __syncthreads();
-        // region voxel rv of group grp: lane column vl; this lane's taps 8g..8g+7
-        for (int grp = wave; grp < kRegionGroups; grp += kThreads / 64) {
-            const int rv = grp * 16 + vl;
-            const int rc = rv < kRegion ? rv : kRegion - 1;
-            const int ex = rc % kRX, ey = (rc / kRX) % kRY, ez = rc / (kRX * kRY);
-            bf16x8 xh, xl;
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-                const int t = min(8 * g + e, kTaps - 1);
-                const float v = xs[((ez + t / 9) * kXY + (ey + (t / 3) % 3)) * kXX + ex + t % 3];
-                const uint16_t h = f2bf(v);
-                xh[e] = (short)h;
-                xl[e] = (short)f2bf(v - bf2f(h));
-            }
-            f32x4 acc = f32x4{0.f, 0.f, 0.f, 0.f};
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xh, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wh, xl, acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wl, xh, acc, 0, 0, 0);
-            if (rv < kRegion) {
-                const int gx = x0 + ex - 1, gy = y0 + ey - 1, gz = z0 + ez - 1;
-                const bool inside = gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz;
-                bf16x4 o;
-#pragma unroll
-                for (int r = 0; r < 4; ++r) o[r] = inside ? (short)f2bf(fmaxf(acc[r] + b1[r], 0.0f)) : (short)0;
-                // channels 4g..4g+3: plane g / 2, second half of the entry for odd g
-                *reinterpret_cast<bf16x4 *>(reinterpret_cast<char *>(region) + ((g >> 1) * kRegion + rv) * 16 +
-                                            (g & 1) * 8) = o;
-            }
-        }
-    }
-    conv16_tile(region, frag, P + OB2, d, x0, y0, z0, 1, nullptr, a2);
-}
-
 // layer 3: out[v] = s * (b3 + sum_{c,t} w3[c][t] a2[v + t - 1][c]), zero
 // where the map mask is 0.  On MFMA like the 16 -> 16 layer with the 1 x 16
 // weight row as rows 0 (BF16 value) and 1 (BF16 remainder) of a 16 x 16
@@ -700,8 +627,9 @@ int convnet_forward_dev(const tomo_cube &c, const float *P, const float *x, floa
     bf16x8 *frag = (bf16x8 *)(base + 2 * align256(sizeof(uint16_t) * kC * d.n));
     if (prep_frags)
         hipLaunchKernelGGL(k_conv_frags, dim3((kFragFwd + 255) / 256), dim3(256), 0, s, P, 0, frag);
-    (void)a1;
-    hipLaunchKernelGGL(k_conv12, tile_grid(d), dim3(kThreads), 0, s, frag, P, x, d, norm2, a2, skip);
+    hipLaunchKernelGGL(k_conv1, tile_grid(d), dim3(kThreads), 0, s, frag + kFrag1, P, x, d, norm2, a1, skip);
+    hipLaunchKernelGGL(k_conv16, tile_grid(d), dim3(kThreads), 0, s, a1, frag, P + OB2, d, 1,
+                       (const uint16_t *)nullptr, a2, skip);
     hipLaunchKernelGGL(k_conv3, tile_grid(d), dim3(kThreads), 0, s, frag + kFrag3, P, a2, d, norm2, map_mask,
                        out, skip);
     return hip_fail(hipGetLastError(), "convnet forward launch");

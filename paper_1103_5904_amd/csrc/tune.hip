@@ -70,8 +70,8 @@ struct Shape {
 const Shape kShapes[] = {
     {256, {64, 32, 2}},  {256, {64, 64, 1}},  {256, {64, 16, 4}},  {256, {32, 32, 4}},  {256, {32, 16, 8}},
     {256, {16, 32, 8}},  {256, {16, 16, 16}}, {512, {64, 64, 2}},  {512, {128, 32, 2}}, {512, {64, 32, 4}},
-    {512, {32, 32, 8}},  {512, {16, 16, 32}}, {1024, {128, 64, 2}}, {1024, {64, 64, 4}}, {1024, {128, 128, 1}},
-    {1024, {32, 32, 16}},
+    {512, {32, 32, 8}},  {512, {16, 16, 32}}, {512, {128, 64, 1}}, {1024, {128, 64, 2}}, {1024, {64, 64, 4}},
+    {1024, {128, 128, 1}}, {1024, {32, 32, 16}},
 };
 
 }  // namespace

@@ -102,7 +102,9 @@ def fit_linear_filter(A, residuals: torch.Tensor) -> np.ndarray:
     G_ij = sum_k (S_i r_k)^T A (S_j r_k) and c_i = sum_k (S_i r_k)^T r_k, S_t the
     tap-t copy.  A(v, out) writes A v into out (a NormalOperator, or any
     symmetric positive definite operator on the residuals' device); costs 27
-    applications of A per residual."""
+    applications of A per residual.  An offline step of training (run once
+    by train_precond before the Adam steps), not part of any solve: its Gram
+    products are plain torch GEMMs on the device, outside the library."""
     shape = residuals.shape[1:]
     S = torch.empty((27,) + tuple(shape), dtype=residuals.dtype, device=residuals.device)
     AS = torch.empty_like(S)

@@ -34,7 +34,7 @@ def test_weights_were_trained_on_other_seeds():
     assert 1000 + meta["train_seeds"] <= 2003
 
 
-@pytest.mark.parametrize("seed", [2003, 2004])
+@pytest.mark.parametrize("seed", [2003, 2004, 2006])
 def test_learned_fcg_beats_plain_cg(setup, seed):
     import torch
 
