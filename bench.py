@@ -53,11 +53,13 @@ HBM_PEAK_GBS = 8000.0
 # the full rate on gfx950), at 2.4 GHz.  In flops this is the FP64 vector
 # peak, 78.6 TFLOP/s, with an FMA counted as two.
 VALU_PEAK_LANE_INSTR = 256 * 64 * 2.4e9
-# VALU instructions of one voxel crossing in the walk loop of each batched
-# kernel (its four-crossing loop body in the gfx950 ISA of batch.hip, divided
-# by four): the P gather-FMA walk over the linear cube, and the P^T walk with
-# its fixed-point LDS deposit.
-WALK_VALU_PER_CROSSING = {"k_batch_project": 101 / 4, "k_batch_backproject": 92 / 4}
+# VALU instructions of one voxel crossing in the walk loop of each kernel of
+# an iteration (its four-crossing loop body in the gfx950 ISA, divided by
+# four): the P^T walk with its fixed-point LDS deposit (batch.hip), and the
+# P gather-FMA walk over the 16^3-bricked cube of the dominant system
+# (siddon.hip; its loop body holds both the buffer and the clamped global
+# load, of which a launch runs one).
+WALK_VALU_PER_CROSSING = {"k_project_bricked": 158 / 4, "k_batch_backproject": 92 / 4}
 
 # Per-launch counters of the batched kernels on the headline step, from
 # rocprofv3 --pmc passes of `bench.py --headline-only` (profiles/
@@ -231,7 +233,7 @@ def roofline(h):
         kern, ms, cross = "k_batch_backproject", h["ms_b"], h["cross_b"]
         alg = 8.0 * cross + 4.0 * h["rays"]
     else:
-        kern, ms, cross = "k_batch_project", h["ms_p"], h["cross_p"]
+        kern, ms, cross = "k_project_bricked", h["ms_p"], h["cross_p"]
         alg = 4.0 * cross + 4.0 * h["rays"]
     sec = ms * 1e-3
     per = WALK_VALU_PER_CROSSING[kern]
@@ -591,7 +593,7 @@ def main():
                    "rays": h["rays"], "arithmetic": "f32 storage and vectors, f64 ray walk and dot products, "
                                                     "64-bit fixed-point P^T bins",
                    "autotuned": not args.no_autotune},
-        "kernels": {"k_batch_project_ms": h["ms_p"], "k_batch_backproject_ms": h["ms_b"],
+        "kernels": {"p_launches_ms": h["ms_p"], "k_batch_backproject_ms": h["ms_b"],
                     "project_crossings_per_s": h["cross_p"] / (h["ms_p"] * 1e-3),
                     "backproject_crossings_per_s": h["cross_b"] / (h["ms_b"] * 1e-3)},
         "roofline": roofline(h),
