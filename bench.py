@@ -5,8 +5,8 @@ configuration that fits one GPU: 8 time-frame cubes of 256^3 on [-4, 4]^3
 R_sun (60 views of 512x512, detector annulus 1.4-4 R_sun kept, unit sphere
 masked, temporal prior lambda_t 10) plus four independent reconstructions of
 64^3, 96^3, 128^3 and 192^3 (16 views of 256x256 each), solved together by
-the batched CG: one persistent P launch and one persistent P^T launch per
-iteration over all five systems, each check interval replayed from a HIP
+the batched CG: per iteration each system's own P launch and one persistent
+P^T launch over all five systems, each check interval replayed from a HIP
 graph, launch shapes chosen by the autotuner per size class.  A step is one
 such solve of --iters iterations (one P^T for the right-hand side, per
 iteration one P and one P^T, one P and P^T for the final true residual).

@@ -229,7 +229,8 @@ int tomo_trace_ray(const tomo_geometry *g, int32_t view, int32_t col,
  *   bp_default: strategy used for TOMO_BP_AUTO (TOMO_BP_BLOCKED,
  *     TOMO_BP_BINNED or TOMO_BP_ATOMIC).
  *   bp_block: voxel block (x, y, z) a workgroup of the blocked
- *     back-projection owns (each 1..64, product <= 8192 64-bit LDS bins).
+ *     back-projection owns (each 1..256, at most 16384 voxels, one 64-bit
+ *     LDS bin each; see bp_threads for what the launch checks).
  *   bp_splits: owners per block in the blocked back-projection, the block's
  *     views dealt round-robin (1..64; 0 = chosen from the block count so
  *     that the launch has about 2048 x 256 / bp_threads workgroups, at most
