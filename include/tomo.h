@@ -408,7 +408,10 @@ typedef struct tomo_cg_params {
     int32_t max_iter;      /* iteration limit (>= 0)                             */
     int32_t x0_given;      /* 1: x_d holds the starting point; 0: start at 0     */
     double rtol;           /* stop when ||b - A x|| <= rtol ||b|| (0: never)      */
-    int32_t check_every;   /* host convergence check period (iterations, >= 1)   */
+    int32_t check_every;   /* host convergence check period (iterations, >= 1);
+                              with rtol > 0, tomo_cg_solve shortens an interval
+                              to the iterations the residual's decay over the
+                              last interval predicts are left                 */
     int32_t use_graph;     /* 1: replay each check interval from a HIP graph     */
     const float *precond;  /* DEVICE convnet parameters, or NULL for plain CG    */
     int32_t fallback_window; /* FCG: restart as plain CG after this many

@@ -12,9 +12,13 @@
 //   so one voxel's 16 channels are one contiguous 32-byte run.
 // * Every layer is a contraction over (tap, input channel) and runs on MFMA
 //   over row tiles of 16 voxels: D[cout][voxel] += A[cout][k] B[k][voxel],
-//   with v_mfma_f32_16x16x32_bf16 taking two taps per instruction (fourteen
-//   instructions for the 27 taps of a 16-channel input), the weights held in
-//   registers and the inputs read from an LDS copy of the tile's region.
+//   with the weights held in registers and the inputs read from an LDS copy
+//   of the tile's region.  For a 16-channel input the taps (dz, dy, dx) go
+//   in nine x-triples: v_mfma_f32_16x16x32_bf16 takes dx = 0 and 1 (two
+//   taps of 16 channels), v_mfma_f32_16x16x16_bf16 takes dx = 2.  The B
+//   operand of an x-triple depends only on the input row (y + dy, z + dz),
+//   so each input row read from LDS feeds the up to three output rows that
+//   use it (dy = 0, 1, 2): half the LDS reads of pairing the taps in order.
 //   D lands as out[voxel l % 16][4 (l / 16) .. +3]: one 8-byte store.  The
 //   same kernel computes the 16 -> 16 data gradient with flipped, transposed
 //   weights.
@@ -104,23 +108,25 @@ __device__ inline void stage_channels(const uint16_t *__restrict__ src, const Vo
 // A(16x32) B(32x16) with lane l holding A[l % 16][8 (l / 16) + e] and
 // B[8 (l / 16) + e][l % 16] (e = 0..7) and D[4 (l / 16) + r][l % 16] (r =
 // 0..3); v_mfma_f32_16x16x16_bf16 has the same D with A[l % 16][4 (l / 16) +
-// e], e = 0..3.  A 16 -> C layer contracts over (tap, input channel): one
-// K = 32 instruction takes the tap pair (2p, 2p + 1), k = 16 j + c for tap
-// 2p + j and channel c, so that lane group g = l / 16 reads tap 2p + g / 2
-// from LDS plane g % 2; thirteen pairs, then tap 26 as a K = 16 instruction
-// (k = channel).  Fragment f of a set is the 64 bf16x8 entries [64 f, 64 f +
-// 64); the K = 16 fragment uses elements 0..3.
+// e], e = 0..3.  A 16 -> C layer contracts over (tap, input channel), the
+// taps t = 9 dz + 3 dy + dx taken in x-triples q = 3 dz + dy (t = 3 q + dx):
+// the K = 32 instruction of triple q has k = 16 dx + c for dx = 0, 1 (lane
+// group g = l / 16 reads dx = g / 2 from LDS plane g % 2), the K = 16
+// instruction has k = c for dx = 2 (lane group g reads channels 4g..4g+3).
+// Fragment f of a set is the 64 bf16x8 entries [64 f, 64 f + 64): f = q
+// for the K = 32 fragment of triple q, f = 9 + q for its K = 16 fragment
+// (elements 0..3).
 //   forward set, kFragFwd entries:
-//   * fragments 0-13: the 16 -> 16 layer, A[cout][k] = W2[cout][c][tap];
-//   * fragments 14-27: the 16 -> 1 layer, row 0 = bf16(W3[0][c][tap]), row 1 =
+//   * fragments 0-17: the 16 -> 16 layer, A[cout][k] = W2[cout][c][tap];
+//   * fragments 18-35: the 16 -> 1 layer, row 0 = bf16(W3[0][c][tap]), row 1 =
 //     its remainder W3 - bf16(W3), rows 2-15 zero: output row 0 + row 1 is
 //     the layer with ~16 significant bits of weight at no extra instruction;
-//   * fragments 28-29: the 1 -> 16 layer with the 27 taps as k (27-31 zero),
+//   * fragments 36-37: the 1 -> 16 layer with the 27 taps as k (27-31 zero),
 //     A[cout][k] = bf16(W1[cout][k]) and its remainder.
 //   transposed set (transpose = 1), kFragConv entries: the 16 -> 16 data
 //   gradient, A[cin][k] = W2[c][cin][26 - tap] (taps flipped).
-constexpr int kPairs = 13;
-constexpr int kConvFrags = kPairs + 1;
+constexpr int kTriples = 9;
+constexpr int kConvFrags = 2 * kTriples;
 constexpr int kFragConv = kConvFrags * 64;
 constexpr int kFrag3 = kFragConv, kFrag1 = 2 * kFragConv;
 constexpr int kFragFwd = 2 * kFragConv + 2 * 64;
@@ -136,11 +142,12 @@ __global__ void k_conv_frags(const float *__restrict__ P, int transpose, bf16x8 
     for (int e = 0; e < 8; ++e) {
         float w = 0.0f;
         if (transpose || f < 2 * kConvFrags) {
-            const int p = f % kConvFrags;
-            const bool tail = p == kPairs;
-            const int tap = tail ? kTaps - 1 : 2 * p + (g >> 1);
-            const int c = tail ? 4 * g + e : 8 * (g & 1) + e;
-            if (tail && e >= 4) {
+            const int ff = f % kConvFrags;
+            const bool k16 = ff >= kTriples;
+            const int q = k16 ? ff - kTriples : ff;
+            const int tap = 3 * q + (k16 ? 2 : (g >> 1));
+            const int c = k16 ? 4 * g + e : 8 * (g & 1) + e;
+            if (k16 && e >= 4) {
                 w = 0.0f;
             } else if (transpose) {
                 w = P[OW2 + (c * kC + row) * kTaps + (kTaps - 1 - tap)];
@@ -162,50 +169,70 @@ __global__ void k_conv_frags(const float *__restrict__ P, int transpose, bf16x8 
     frag[idx] = out;
 }
 
-// Per-lane LDS byte offsets of the B operands of the thirteen tap pairs and
-// the tail tap, for output voxel (vl, 0, lz) of the tile; row y adds y * kRX
-// entries (a compile-time immediate).
+// Per-lane LDS byte offsets of the B operands for output voxel (vl, 0, lz)
+// of the tile and input row (y, z) = (0, lz) of the region: k32 for the
+// dx = 0, 1 pair, k16 for dx = 2.  Input row (dy', dz') further adds
+// (dz' kRY + dy') kRX entries (a compile-time immediate).
 struct ConvOffsets {
-    uint32_t pair[kPairs];
-    uint32_t tail;
+    uint32_t k32;
+    uint32_t k16;
 };
 
 __device__ inline ConvOffsets conv_offsets(int vl, int lz, int g)
 {
     ConvOffsets o;
-#pragma unroll
-    for (int p = 0; p < kPairs; ++p)
-        o.pair[p] = (uint32_t)(((g & 1) * kRegion + region_index(vl, 0, lz, 2 * p + (g >> 1))) * 16);
-    o.tail = (uint32_t)(((g >> 1) * kRegion + region_index(vl, 0, lz, kTaps - 1)) * 16 + (g & 1) * 8);
+    o.k32 = (uint32_t)(((g & 1) * kRegion + region_index(vl, 0, lz, g >> 1)) * 16);
+    o.k16 = (uint32_t)(((g >> 1) * kRegion + region_index(vl, 0, lz, 2)) * 16 + (g & 1) * 8);
     return o;
 }
 
-// acc[y] += sum over taps and channels of A x region, for the four rows of
-// the wavefront; w: the fourteen fragments of a 16 -> C layer in registers.
-__device__ inline void conv_rows(const char *rbytes, const ConvOffsets &o, const bf16x8 (&w)[kPairs],
-                                 const bf16x4 &wt, f32x4 (&acc)[kTY])
+// acc[y] += sum over taps and channels of A x region, for the four output
+// rows y of the wavefront; w, wt: the K = 32 and K = 16 fragments of the
+// nine x-triples of a 16 -> C layer, in registers.  Per input plane dz the
+// six input rows (region rows lz + dz, yi) are read once; output row y takes
+// row y + dy through triple 3 dz + dy.  The four rows are interleaved, so
+// three independent MFMA instructions separate two that update the same
+// accumulator: an instruction then never reads as its accumulator input the
+// result of one still in flight.
+__device__ inline void conv_rows(const char *rbytes, const ConvOffsets &o, const bf16x8 (&w)[kTriples],
+                                 const bf16x4 (&wt)[kTriples], f32x4 (&acc)[kTY])
 {
 #pragma unroll
-    for (int p = 0; p < kPairs; ++p)
+    for (int dz = 0; dz < 3; ++dz) {
+        bf16x8 b32[kRY];
+        bf16x4 b16[kRY];
 #pragma unroll
-        for (int y = 0; y < kTY; ++y) {
-            const bf16x8 bv = *reinterpret_cast<const bf16x8 *>(rbytes + o.pair[p] + y * kRX * 16);
-            acc[y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[p], bv, acc[y], 0, 0, 0);
+        for (int yi = 0; yi < kRY; ++yi) {
+            const uint32_t row = (uint32_t)((dz * kRY + yi) * kRX * 16);
+            b32[yi] = *reinterpret_cast<const bf16x8 *>(rbytes + o.k32 + row);
+            b16[yi] = *reinterpret_cast<const bf16x4 *>(rbytes + o.k16 + row);
         }
 #pragma unroll
-    for (int y = 0; y < kTY; ++y) {
-        const bf16x4 bv = *reinterpret_cast<const bf16x4 *>(rbytes + o.tail + y * kRX * 16);
-        acc[y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt, bv, acc[y], 0, 0, 0);
+        for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+            for (int y = 0; y < kTY; ++y)
+                acc[y] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w[3 * dz + dy], b32[y + dy], acc[y], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);  // keep the four-row interleave as written
+        }
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy) {
+#pragma unroll
+            for (int y = 0; y < kTY; ++y)
+                acc[y] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(wt[3 * dz + dy], b16[y + dy], acc[y], 0, 0, 0);
+            __builtin_amdgcn_sched_barrier(0);
+        }
     }
 }
 
-__device__ inline void load_conv_frags(const bf16x8 *__restrict__ frag, int lane, bf16x8 (&w)[kPairs],
-                                       bf16x4 &wt)
+__device__ inline void load_conv_frags(const bf16x8 *__restrict__ frag, int lane, bf16x8 (&w)[kTriples],
+                                       bf16x4 (&wt)[kTriples])
 {
 #pragma unroll
-    for (int p = 0; p < kPairs; ++p) w[p] = frag[p * 64 + lane];
-    const bf16x8 t = frag[kPairs * 64 + lane];
-    wt = __builtin_shufflevector(t, t, 0, 1, 2, 3);
+    for (int q = 0; q < kTriples; ++q) {
+        w[q] = frag[q * 64 + lane];
+        const bf16x8 t = frag[(kTriples + q) * 64 + lane];
+        wt[q] = __builtin_shufflevector(t, t, 0, 1, 2, 3);
+    }
 }
 
 // layer 1: a1[v][c] = relu(b1[c] + sum_t w1[c][t] x[v + t - 1] / s), on
@@ -286,8 +313,8 @@ __device__ inline void conv16_tile(const uint4 *region, const bf16x8 *__restrict
                                    int relu, const uint16_t *__restrict__ mask, uint16_t *__restrict__ out)
 {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    bf16x8 w[kPairs];
-    bf16x4 wt;
+    bf16x8 w[kTriples];
+    bf16x4 wt[kTriples];
     load_conv_frags(frag, lane, w, wt);
     const int vl = lane % 16, g = lane / 16, cg = 4 * g;
     const ConvOffsets o = conv_offsets(vl, wave, g);
@@ -355,8 +382,8 @@ __global__ __launch_bounds__(kThreads) void k_conv3(const bf16x8 *__restrict__ f
     const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * kTY, z0 = blockIdx.z * kTZ;
     stage_channels(a2, d, x0, y0, z0, region);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    bf16x8 w[kPairs];
-    bf16x4 wt;
+    bf16x8 w[kTriples];
+    bf16x4 wt[kTriples];
     load_conv_frags(frag3, lane, w, wt);
     const int vl = lane % 16, g = lane / 16;
     const ConvOffsets o = conv_offsets(vl, wave, g);

@@ -947,10 +947,15 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     double true_rel = -1.0;
     int restarts = 0;
     for (;;) {
-        // run chunks until the device says stop
+        // run chunks until the device says stop.  Iterations enqueued past
+        // convergence return at once but still cost their launches, so once
+        // the residual's decay rate over the last chunk predicts the target
+        // within check_every iterations, the next chunk stops there.
         int enq = 0;
+        int chunk = prm->rtol > 0 ? prm->check_every : maxit;
+        double ref_res2 = -1.0;
+        int ref_iter = 0;
         while (done_iters + enq < maxit) {
-            const int chunk = prm->rtol > 0 ? prm->check_every : maxit;
             const int todo = chunk < maxit - done_iters - enq ? chunk : maxit - done_iters - enq;
             for (int k = 0; k < todo; ++k) {
                 rc = enqueue_iteration();
@@ -962,6 +967,18 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
             if (!rc) rc = hip_fail(hipStreamSynchronize(s), "cg synchronise");
             if (rc) return rc;
             if (hst->done) break;
+            if (prm->rtol > 0) {
+                chunk = prm->check_every;
+                if (ref_res2 > 0.0 && hst->res2 > 0.0 && hst->thresh2 > 0.0 && hst->iter > ref_iter) {
+                    const double rate = log(hst->res2 / ref_res2) / (double)(hst->iter - ref_iter);
+                    if (rate < 0.0) {
+                        const double need = log(hst->thresh2 / hst->res2) / rate;
+                        if (need < (double)chunk) chunk = need < 1.0 ? 1 : (int)ceil(need);
+                    }
+                }
+                ref_res2 = hst->res2;
+                ref_iter = hst->iter;
+            }
         }
         rc = hip_fail(hipMemcpyAsync(hst, ws.st, sizeof(CgState), hipMemcpyDeviceToHost, s), "state copy");
         if (!rc) rc = hip_fail(hipStreamSynchronize(s), "cg synchronise");
