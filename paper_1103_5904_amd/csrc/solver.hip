@@ -371,6 +371,79 @@ __global__ __launch_bounds__(kThreads) void k_cg_q(const float *__restrict__ p,
     put_partial(pq, ws.cpart);
 }
 
+// k_cg_q for the plain prior on rows of a multiple of four voxels (and a
+// map mask, if any, on a 4-byte boundary): each thread takes four
+// consecutive voxels of one row, so the centre values, the row and plane
+// neighbours, the temporal neighbours, q and the mask are 16-byte (4-byte)
+// loads, and the voxel coordinates are derived once per four.  Per voxel
+// the sum runs in prior_core's order, so q is the same, bit for bit; the
+// p.q partial sums the same products in another order.
+__device__ inline float4 ld4(const float *__restrict__ a, int64_t i)
+{
+    return *reinterpret_cast<const float4 *>(a + i);
+}
+
+__global__ __launch_bounds__(kThreads) void k_cg_q4(const float *__restrict__ p, float *__restrict__ q,
+                                                    const uint8_t *__restrict__ map_mask, Dims d, float lr,
+                                                    float lt, Workspace ws)
+{
+    if (ws.st->done) return;
+    const int64_t n4 = d.total >> 2;
+    const int64_t span = ((n4 + gridDim.x - 1) / gridDim.x + kThreads - 1) / kThreads * kThreads;
+    const int64_t beg = xcd_remap(blockIdx.x, gridDim.x) * span;
+    const int64_t end = beg + span < n4 ? beg + span : n4;
+    const int64_t pl = (int64_t)d.nx * d.ny;
+    const float4 zero4 = make_float4(0.f, 0.f, 0.f, 0.f);
+    double pq = 0.0;
+    for (int64_t g = beg + threadIdx.x; g < end; g += kThreads) {
+        const int64_t idx = g << 2;
+        const VoxIdx c = vox_index(d, idx);
+        const float4 c4 = ld4(p, idx);
+        const float xl = c.i > 0 ? p[idx - 1] : 0.0f;
+        const float xr = c.i + 4 < d.nx ? p[idx + 4] : 0.0f;
+        const float4 ym = c.j > 0 ? ld4(p, idx - d.nx) : zero4;
+        const float4 yp = c.j < d.ny - 1 ? ld4(p, idx + d.nx) : zero4;
+        const float4 zm = c.k > 0 ? ld4(p, idx - pl) : zero4;
+        const float4 zp = c.k < d.nz - 1 ? ld4(p, idx + pl) : zero4;
+        const bool tm = lt != 0.0f && c.f > 0, tp = lt != 0.0f && c.f < d.nf - 1;
+        const float4 fm = tm ? ld4(p, idx - d.nvox) : zero4;
+        const float4 fp = tp ? ld4(p, idx + d.nvox) : zero4;
+        float4 q4 = ld4(q, idx);
+        uint32_t m4 = 0xffffffffu;
+        if (map_mask) m4 = *reinterpret_cast<const uint32_t *>(map_mask + c.rem);
+        const float cv[4] = {c4.x, c4.y, c4.z, c4.w};
+        const float ymv[4] = {ym.x, ym.y, ym.z, ym.w}, ypv[4] = {yp.x, yp.y, yp.z, yp.w};
+        const float zmv[4] = {zm.x, zm.y, zm.z, zm.w}, zpv[4] = {zp.x, zp.y, zp.z, zp.w};
+        const float fmv[4] = {fm.x, fm.y, fm.z, fm.w}, fpv[4] = {fp.x, fp.y, fp.z, fp.w};
+        float qv[4] = {q4.x, q4.y, q4.z, q4.w};
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const float cc = cv[e];
+            const float left = e > 0 ? cv[e - 1] : xl, right = e < 3 ? cv[e + 1] : xr;
+            float sum = 0.0f;
+            if (c.i + e > 0) sum += cc - left;
+            if (c.i + e < d.nx - 1) sum += cc - right;
+            if (c.j > 0) sum += cc - ymv[e];
+            if (c.j < d.ny - 1) sum += cc - ypv[e];
+            if (c.k > 0) sum += cc - zmv[e];
+            if (c.k < d.nz - 1) sum += cc - zpv[e];
+            float out = lr * sum;
+            if (lt != 0.0f) {
+                float t = 0.0f;
+                if (c.f > 0) t += cc - fmv[e];
+                if (c.f < d.nf - 1) t += cc - fpv[e];
+                out += lt * t;
+            }
+            float v = qv[e] + out;
+            if (!((m4 >> (8 * e)) & 0xffu)) v = 0.0f;
+            qv[e] = v;
+            pq += (double)cc * v;
+        }
+        *reinterpret_cast<float4 *>(q + idx) = make_float4(qv[0], qv[1], qv[2], qv[3]);
+    }
+    put_partial(pq, ws.cpart);
+}
+
 // alpha = rr / p.q; x += alpha p; r -= alpha q; q = 0 when the next P^T
 // adds into q (zero_q; the blocked P^T writes q outright); per-workgroup
 // partials of the new r.r.
@@ -649,11 +722,19 @@ static int height_dev(const tomo_cube &c, const tomo_height *h, HeightDev &hd, c
     return TOMO_OK;
 }
 
-template <typename... Args>
-static void launch_cg_q(bool hw, unsigned blocks, hipStream_t s, Args... a)
+// The fused q pass of every CG: the four-voxel kernel where the rows allow
+// it (plain prior, rows of a multiple of four voxels, map mask on a 4-byte
+// boundary), else the one-voxel kernel.
+static void launch_cg_q(bool hw, unsigned blocks, hipStream_t s, const float *p, float *q, const uint8_t *mm,
+                        const Dims &d, float lr, float lt, const Workspace &ws, const HeightDev &hd)
 {
-    if (hw) hipLaunchKernelGGL(k_cg_q<true>, dim3(blocks), dim3(kThreads), 0, s, a...);
-    else hipLaunchKernelGGL(k_cg_q<false>, dim3(blocks), dim3(kThreads), 0, s, a...);
+    if (hw) {
+        hipLaunchKernelGGL(k_cg_q<true>, dim3(blocks), dim3(kThreads), 0, s, p, q, mm, d, lr, lt, ws, hd);
+    } else if (d.nx % 4 == 0 && ((uintptr_t)mm & 3u) == 0) {
+        hipLaunchKernelGGL(k_cg_q4, dim3(blocks), dim3(kThreads), 0, s, p, q, mm, d, lr, lt, ws);
+    } else {
+        hipLaunchKernelGGL(k_cg_q<false>, dim3(blocks), dim3(kThreads), 0, s, p, q, mm, d, lr, lt, ws, hd);
+    }
 }
 
 template <typename... Args>
