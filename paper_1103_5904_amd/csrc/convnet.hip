@@ -30,6 +30,9 @@
 //   sums, reduced in a fixed order (deterministic).
 #include <math.h>
 
+#include <map>
+#include <mutex>
+
 #include "common.h"
 
 namespace tomo {
@@ -302,6 +305,53 @@ __global__ __launch_bounds__(kThreads) void k_conv1(const bf16x8 *__restrict__ f
     }
 }
 
+// Epilogue of a 16 -> 16 layer for the tile at (x0, y0, z0): out =
+// act(bias + acc) as BF16, act as for conv16_tile.
+__device__ inline void conv16_store(const f32x4 (&acc)[kTY], const float (&b)[4], const Vol &d, int x0, int y0,
+                                    int z0, int relu, const uint16_t *__restrict__ mask, uint16_t *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int vl = lane % 16, cg = 4 * (lane / 16);
+    const int xo = x0 + vl, zo = z0 + wave;
+#pragma unroll
+    for (int y = 0; y < kTY; ++y) {
+        const int yo = y0 + y;
+        if (xo < d.nx && yo < d.ny && zo < d.nz) {
+            const int64_t vo = ((int64_t)zo * d.ny + yo) * d.nx + xo;
+            bf16x4 m = {1, 1, 1, 1};
+            if (mask) m = *reinterpret_cast<const bf16x4 *>(mask + vo * kC + cg);
+            bf16x4 ov;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                float val = acc[y][r] + b[r];
+                if (relu) val = fmaxf(val, 0.0f);
+                if (mask && !(bf2f((uint16_t)m[r]) > 0.0f)) val = 0.0f;
+                ov[r] = (short)f2bf(val);
+            }
+            *reinterpret_cast<bf16x4 *>(out + vo * kC + cg) = ov;
+        }
+    }
+}
+
+// Epilogue of the 16 -> 1 layer: out = s (b3 + row 0 + row 1), zero where
+// the map mask is 0.
+__device__ inline void conv3_store(const f32x4 (&acc)[kTY], float s, float b3, const Vol &d, int x0, int y0, int z0,
+                                   const uint8_t *__restrict__ map_mask, float *__restrict__ out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int xo = x0 + lane % 16, zo = z0 + wave;
+#pragma unroll
+    for (int y = 0; y < kTY; ++y) {
+        const int yo = y0 + y;
+        if (lane < 16 && xo < d.nx && yo < d.ny && zo < d.nz) {
+            const int64_t vo = ((int64_t)zo * d.ny + yo) * d.nx + xo;
+            float ov = s * ((acc[y][0] + acc[y][1]) + b3);
+            if (map_mask && !map_mask[vo]) ov = 0.0f;
+            out[vo] = ov;
+        }
+    }
+}
+
 // 16 -> 16 convolution of the tile at (x0, y0, z0) from its staged LDS
 // region: fourteen MFMA instructions per 16-voxel row with the weights in
 // registers.  out = act(bias + conv) where act is ReLU (relu = 1), or
@@ -327,25 +377,7 @@ __device__ inline void conv16_tile(const uint4 *region, const bf16x8 *__restrict
 #pragma unroll
     for (int y = 0; y < kTY; ++y) acc[y] = f32x4{0.f, 0.f, 0.f, 0.f};
     conv_rows(reinterpret_cast<const char *>(region), o, w, wt, acc);
-    const int xo = x0 + vl, zo = z0 + wave;
-#pragma unroll
-    for (int y = 0; y < kTY; ++y) {
-        const int yo = y0 + y;
-        if (xo < d.nx && yo < d.ny && zo < d.nz) {
-            const int64_t vo = ((int64_t)zo * d.ny + yo) * d.nx + xo;
-            bf16x4 m = {1, 1, 1, 1};
-            if (mask) m = *reinterpret_cast<const bf16x4 *>(mask + vo * kC + cg);
-            bf16x4 ov;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                float val = acc[y][r] + b[r];
-                if (relu) val = fmaxf(val, 0.0f);
-                if (mask && !(bf2f((uint16_t)m[r]) > 0.0f)) val = 0.0f;
-                ov[r] = (short)f2bf(val);
-            }
-            *reinterpret_cast<bf16x4 *>(out + vo * kC + cg) = ov;
-        }
-    }
+    conv16_store(acc, b, d, x0, y0, z0, relu, mask, out);
 }
 
 // 16 -> 16 convolution of a stored activation (training forward, and the
@@ -393,17 +425,142 @@ __global__ __launch_bounds__(kThreads) void k_conv3(const bf16x8 *__restrict__ f
 #pragma unroll
     for (int y = 0; y < kTY; ++y) acc[y] = f32x4{0.f, 0.f, 0.f, 0.f};
     conv_rows(reinterpret_cast<const char *>(region), o, w, wt, acc);
-    const int xo = x0 + vl, zo = z0 + wave;
-#pragma unroll
-    for (int y = 0; y < kTY; ++y) {
-        const int yo = y0 + y;
-        if (lane < 16 && xo < d.nx && yo < d.ny && zo < d.nz) {
-            const int64_t vo = ((int64_t)zo * d.ny + yo) * d.nx + xo;
-            float ov = s * ((acc[y][0] + acc[y][1]) + b3);
-            if (map_mask && !map_mask[vo]) ov = 0.0f;
-            out[vo] = ov;
+    conv3_store(acc, s, b3, d, x0, y0, z0, map_mask, out);
+}
+
+// ---- persistent forward kernels (inference): each workgroup takes tiles
+// t, t + G, t + 2G, ... (G workgroups) and, while it computes one, the
+// region of its next tile arrives in the other of two LDS buffers through
+// direct-to-LDS buffer loads (no registers, no staging stores), so the
+// staging latency hides behind the MFMA work instead of adding to it.
+// Each tile's arithmetic is that of k_conv16 / k_conv3, bit for bit.
+constexpr int kChunks = (2 * kRegion + 63) / 64;  // 64-slot wave loads per region
+constexpr int kSlots = kChunks * 64;              // region buffer with its padding
+
+// Issues the loads of the region of the tile at (x0, y0, z0) into buf: slot
+// s of plane h = s / kRegion holds channels 8h..8h+7 of region voxel
+// s % kRegion; voxels outside the volume and the padding get offsets past
+// the buffer's range, which the hardware reads as zeros.  Lane l of a wave
+// load writes slot 64 c + l.  rs spans the [voxel][16] BF16 activation.
+__device__ inline void stage_channels_lds(__amdgpu_buffer_rsrc_t rs, const Vol &d, int x0, int y0, int z0,
+                                          uint4 *buf)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int c = wave; c < kChunks; c += kThreads / 64) {
+        const int sl = c * 64 + lane;
+        uint32_t off = 0xFFFFFFF0u;
+        if (sl < 2 * kRegion) {
+            const int h = sl >= kRegion ? 1 : 0, rv = sl - h * kRegion;
+            const int ex = rv % kRX, ey = (rv / kRX) % kRY, ez = rv / (kRX * kRY);
+            const int gx = x0 + ex - 1, gy = y0 + ey - 1, gz = z0 + ez - 1;
+            if (gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny && gz >= 0 && gz < d.nz)
+                off = (uint32_t)((((int64_t)gz * d.ny + gy) * d.nx + gx) * (kC * 2) + h * 16);
         }
+        __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void *)(buf + c * 64), 16,
+                                                 (int)off, 0, 0, 0);
     }
+}
+
+// Largest activation the persistent kernels address through one buffer
+// resource (offsets below the out-of-range marker).
+constexpr int64_t kMaxPipelinedVoxels = ((int64_t)1 << 27) - 1;
+
+// The tile loop of a persistent forward kernel: tile(region, x0, y0, z0)
+// computes and stores one tile from a published region.  The two buffers
+// alternate at compile time (two tiles per round).
+template <class Tile>
+__device__ inline void pipelined_tiles(const uint16_t *__restrict__ in, const Vol &d, uint4 *buf0, uint4 *buf1,
+                                       Tile &&tile)
+{
+    const int ntx = (d.nx + kTX - 1) / kTX, nty = (d.ny + kTY - 1) / kTY, ntz = (d.nz + kTZ - 1) / kTZ;
+    const int T = ntx * nty * ntz;
+    const auto rs = make_rsrc(in, (uint32_t)(d.n * kC * 2));
+    auto origin = [&](int t, int &x0, int &y0, int &z0) {
+        x0 = (t % ntx) * kTX;
+        const int r = t / ntx;
+        y0 = (r % nty) * kTY;
+        z0 = (r / nty) * kTZ;
+    };
+    int t = blockIdx.x, x0, y0, z0;
+    if (t >= T) return;
+    origin(t, x0, y0, z0);
+    stage_channels_lds(rs, d, x0, y0, z0, buf0);
+    // one step: publish cur (its loads done, every wave past the previous
+    // tile, so next is free), prefetch the next tile into next, compute t
+    auto step = [&](uint4 *cur, uint4 *next) -> bool {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        const int tn = t + (int)gridDim.x;
+        int nx0 = 0, ny0 = 0, nz0 = 0;
+        if (tn < T) {
+            origin(tn, nx0, ny0, nz0);
+            stage_channels_lds(rs, d, nx0, ny0, nz0, next);
+        }
+        tile(cur, x0, y0, z0);
+        if (tn >= T) return false;
+        t = tn;
+        x0 = nx0;
+        y0 = ny0;
+        z0 = nz0;
+        return true;
+    };
+    while (step(buf0, buf1) && step(buf1, buf0)) {
+    }
+}
+
+// Persistent 16 -> 16 layer with ReLU (the inference forward's layer 2).
+__global__ __launch_bounds__(kThreads) void k_conv16p(const uint16_t *__restrict__ in,
+                                                      const bf16x8 *__restrict__ frag,
+                                                      const float *__restrict__ bias, Vol d,
+                                                      uint16_t *__restrict__ out, const int *__restrict__ skip)
+{
+    __shared__ uint4 buf0[kSlots];
+    __shared__ uint4 buf1[kSlots];
+    if (skip && *skip) return;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bf16x8 w[kTriples];
+    bf16x4 wt[kTriples];
+    load_conv_frags(frag, lane, w, wt);
+    const int vl = lane % 16, g = lane / 16, cg = 4 * g;
+    const ConvOffsets o = conv_offsets(vl, wave, g);
+    float b[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) b[r] = bias[cg + r];
+    pipelined_tiles(in, d, buf0, buf1, [&](const uint4 *region, int x0, int y0, int z0) {
+        f32x4 acc[kTY];
+#pragma unroll
+        for (int y = 0; y < kTY; ++y) acc[y] = f32x4{0.f, 0.f, 0.f, 0.f};
+        conv_rows(reinterpret_cast<const char *>(region), o, w, wt, acc);
+        conv16_store(acc, b, d, x0, y0, z0, 1, nullptr, out);
+    });
+}
+
+// Persistent 16 -> 1 layer (the inference forward's layer 3).
+__global__ __launch_bounds__(kThreads) void k_conv3p(const bf16x8 *__restrict__ frag3,
+                                                     const float *__restrict__ P,
+                                                     const uint16_t *__restrict__ a2, Vol d,
+                                                     const double *__restrict__ norm2,
+                                                     const uint8_t *__restrict__ map_mask,
+                                                     float *__restrict__ out, const int *__restrict__ skip)
+{
+    __shared__ uint4 buf0[kSlots];
+    __shared__ uint4 buf1[kSlots];
+    if (skip && *skip) return;
+    const float s = read_scale(norm2);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    bf16x8 w[kTriples];
+    bf16x4 wt[kTriples];
+    load_conv_frags(frag3, lane, w, wt);
+    const int vl = lane % 16, g = lane / 16;
+    const ConvOffsets o = conv_offsets(vl, wave, g);
+    const float b3 = P[OB3];
+    pipelined_tiles(a2, d, buf0, buf1, [&](const uint4 *region, int x0, int y0, int z0) {
+        f32x4 acc[kTY];
+#pragma unroll
+        for (int y = 0; y < kTY; ++y) acc[y] = f32x4{0.f, 0.f, 0.f, 0.f};
+        conv_rows(reinterpret_cast<const char *>(region), o, w, wt, acc);
+        conv3_store(acc, s, b3, d, x0, y0, z0, map_mask, out);
+    });
 }
 
 // ------------------------------------------------------------ training
@@ -634,6 +791,31 @@ static dim3 tile_grid(const Vol &d)
                 (unsigned)((d.nz + kTZ - 1) / kTZ));
 }
 
+// Workgroups of a persistent forward kernel: as many as stay resident on the
+// device (occupancy x compute units, queried once per kernel), at most one
+// per tile.
+static unsigned persistent_grid(const void *kernel, int64_t tiles)
+{
+    static std::mutex mu;
+    static std::map<const void *, int64_t> resident;
+    int64_t r = 0;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        auto it = resident.find(kernel);
+        if (it != resident.end()) {
+            r = it->second;
+        } else {
+            int dev = 0, cus = 0, per = 0;
+            (void)hipGetDevice(&dev);
+            (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+            (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, kernel, kThreads, 0);
+            r = (int64_t)(cus > 0 ? cus : 256) * (per > 0 ? per : 1);
+            resident[kernel] = r;
+        }
+    }
+    return (unsigned)(tiles < r ? (tiles > 0 ? tiles : 1) : r);
+}
+
 static unsigned vox_blocks(int64_t n)
 {
     int64_t b = (n + kThreads - 1) / kThreads;
@@ -655,10 +837,20 @@ int convnet_forward_dev(const tomo_cube &c, const float *P, const float *x, floa
     if (prep_frags)
         hipLaunchKernelGGL(k_conv_frags, dim3((kFragFwd + 255) / 256), dim3(256), 0, s, P, 0, frag);
     hipLaunchKernelGGL(k_conv1, tile_grid(d), dim3(kThreads), 0, s, frag + kFrag1, P, x, d, norm2, a1, skip);
-    hipLaunchKernelGGL(k_conv16, tile_grid(d), dim3(kThreads), 0, s, a1, frag, P + OB2, d, 1,
-                       (const uint16_t *)nullptr, a2, skip);
-    hipLaunchKernelGGL(k_conv3, tile_grid(d), dim3(kThreads), 0, s, frag + kFrag3, P, a2, d, norm2, map_mask,
-                       out, skip);
+    if (d.n <= kMaxPipelinedVoxels) {  // persistent, pipelined layers 2 and 3
+        const dim3 tg = tile_grid(d);
+        const int64_t tiles = (int64_t)tg.x * tg.y * tg.z;
+        const unsigned g16 = persistent_grid(reinterpret_cast<const void *>(k_conv16p), tiles);
+        const unsigned g3 = persistent_grid(reinterpret_cast<const void *>(k_conv3p), tiles);
+        hipLaunchKernelGGL(k_conv16p, dim3(g16), dim3(kThreads), 0, s, a1, frag, P + OB2, d, a2, skip);
+        hipLaunchKernelGGL(k_conv3p, dim3(g3), dim3(kThreads), 0, s, frag + kFrag3, P, a2, d, norm2, map_mask, out,
+                           skip);
+    } else {
+        hipLaunchKernelGGL(k_conv16, tile_grid(d), dim3(kThreads), 0, s, a1, frag, P + OB2, d, 1,
+                           (const uint16_t *)nullptr, a2, skip);
+        hipLaunchKernelGGL(k_conv3, tile_grid(d), dim3(kThreads), 0, s, frag + kFrag3, P, a2, d, norm2, map_mask,
+                           out, skip);
+    }
     return hip_fail(hipGetLastError(), "convnet forward launch");
 }
 
