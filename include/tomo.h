@@ -427,6 +427,11 @@ typedef struct tomo_cg_params {
     const tomo_height *height; /* HOST pointer or NULL: spatial prior
                                   lambda_r R D^T D R (Eq. srt_inversion)
                                   instead of lambda_r D^T D                  */
+    void *workspace;       /* DEVICE, 256-byte aligned, or NULL: memory for all
+                              of the solve's device buffers (see
+                              tomo_cg_workspace_bytes); NULL takes stream-
+                              ordered scratch (hipMallocAsync) per call      */
+    size_t workspace_bytes; /* size of workspace                              */
 } tomo_cg_params;
 
 typedef struct tomo_cg_report {
@@ -476,6 +481,21 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d,
 /* Default parameters: lambda_r 1e-2, max_iter 50, check_every 10,
  * fallback_window 3, min_drop 1e-6, everything else 0 / NULL. */
 void tomo_cg_default_params(tomo_cg_params *p);
+
+/*
+ * Bytes of device workspace tomo_cg_solve(g, ..., p, ...) takes when
+ * p->workspace is set (the vectors of Eq. criterion's CG, the reductions'
+ * partials, the blocked P^T's scratch, P's bricked copy of the iterate if the
+ * geometry's tuning walks bricks, and the network's activations with a
+ * preconditioner).  The figure depends on the launch tuning in effect for
+ * g's size class: query again after tomo_autotune or tomo_set_tuning.
+ * Returns 0 for invalid arguments and for use_graph = 1 (a batch of one
+ * takes its own memory; tomo_cg_solve refuses a workspace with it).  With a
+ * workspace the solve allocates no device memory (the first call on a new
+ * geometry still uploads its view table, as every call does); a workspace
+ * smaller than this figure is rejected with TOMO_EINVAL.
+ */
+size_t tomo_cg_workspace_bytes(const tomo_geometry *g, const tomo_cg_params *p);
 
 /*
  * Autotuner (the batched launches of Eq. srt_t and every single-system call

@@ -5,7 +5,7 @@ in include/tomo.h.  This package is the thin Python binding."""
 from .tomo import (  # noqa: F401
     NPARAMS, Batch, ConvNet, adam_step, autotune, autotune_clear, class_tuning,
     BP_ATOMIC, BP_AUTO, BP_BINNED, BP_BLOCKED, DeviceGeometry, TomoError, apply_prior, backproject,
-    backproject_noalloc, binning_spills, cg_solve, get_tuning, set_tuning,
+    backproject_noalloc, binning_spills, cg_solve, cg_workspace_bytes, get_tuning, set_tuning,
     count_crossings, lib, project, status_string, thomson_backproject, thomson_project, trace_ray, validate,
     view_from_wcs,
 )

@@ -225,8 +225,13 @@ int launch_backproject(const Plan &p, const tomo_geometry *g, const float *image
                        bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
                        const int *done_flag = nullptr, void *scratch = nullptr,
                        size_t scratch_bytes = 0);
+// P of the plan's tuning without a map mask; a tuning that walks bricks
+// copies the cube into `bricks` (bricked_copy_bytes of them) when given,
+// else into stream-ordered scratch for this launch.
 int launch_project_flagged(const Plan &p, const tomo_geometry *g, const float *cube,
-                           float *images, hipStream_t s, const int *done_flag);
+                           float *images, hipStream_t s, const int *done_flag, float *bricks = nullptr);
+// Bytes of the bricked copy P takes with tuning tu on this plan (0: none).
+size_t bricked_copy_bytes(const Plan &p, const tomo_tuning &tu);
 int launch_project_tuned(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
                          bool use_map_mask, hipStream_t s, const int *done_flag, const tomo_tuning &tu);
 int launch_backproject_tuned(const Plan &p, const tomo_geometry *g, const float *images, float *cube,

@@ -301,11 +301,26 @@ int launch_project_with(const Plan &p, const tomo_geometry *g, const float *cube
     return launch_project_tuned(p, g, cube, images, use_map_mask, s, nullptr, tu);
 }
 
+size_t bricked_copy_bytes(const Plan &p, const tomo_tuning &tu)
+{
+    BrickDev bk;
+    if (tu.p_layout < 2 || !brick_layout(p, tu.p_layout, bk)) return 0;
+    return sizeof(float) * (size_t)(bk.frame_stride * p.grid.nframes);
+}
+
 int launch_project_flagged(const Plan &p, const tomo_geometry *g, const float *cube,
-                           float *images, hipStream_t s, const int *done_flag)
+                           float *images, hipStream_t s, const int *done_flag, float *bricks)
 {
     const tomo_tuning tu = tuning_for(p);
-    if (tu.p_layout >= 2) return launch_project_bricked(p, g, cube, images, false, s, done_flag, tu);
+    if (tu.p_layout >= 2) {
+        BrickDev bk;
+        if (bricks && brick_layout(p, tu.p_layout, bk)) {
+            int rc = brick_copy_launch(p, cube, nullptr, bk, bricks, s, done_flag);
+            if (!rc) rc = launch_project_from_bricks(p, g, bricks, bk, images, s, done_flag, tu);
+            return rc;
+        }
+        return launch_project_bricked(p, g, cube, images, false, s, done_flag, tu);
+    }
     return launch_project_tuned(p, g, cube, images, false, s, done_flag, tu);
 }
 

@@ -744,12 +744,29 @@ static void launch_true_res(bool hw, unsigned blocks, hipStream_t s, Args... a)
     else hipLaunchKernelGGL(k_true_res<false>, dim3(blocks), dim3(kThreads), 0, s, a...);
 }
 
-// Device allocations of one solve, released on every exit path.
+// Device allocations of one solve, released on every exit path: stream-
+// ordered scratch; or consecutive 256-byte aligned pieces of a caller's
+// workspace (arena); or, to size such a workspace (measure), no memory at
+// all: every piece is a non-null placeholder that nothing dereferences.
 struct SolveBuffers {
     hipStream_t s = nullptr;
     std::vector<void *> ptrs;
+    char *arena = nullptr;
+    size_t arena_bytes = 0;
+    bool measure = false;
+    size_t used = 0;  // arena or measure: bytes taken so far
     void *alloc(size_t bytes)
     {
+        if (arena || measure) {
+            const size_t at = (used + 255) & ~(size_t)255;
+            if (measure) {
+                used = at + bytes;
+                return reinterpret_cast<void *>((uintptr_t)256);
+            }
+            if (at + bytes > arena_bytes) return nullptr;
+            used = at + bytes;
+            return arena + at;
+        }
         void *p = nullptr;
         if (scratch_alloc(&p, bytes, s) != hipSuccess) return nullptr;
         ptrs.push_back(p);
@@ -760,6 +777,59 @@ struct SolveBuffers {
         for (void *p : ptrs) (void)scratch_free(p, s);
     }
 };
+
+// The device buffers of tomo_cg_solve on one geometry: the vectors, the
+// reduction workspace, the blocked P^T's scratch, P's bricked copy (when the
+// tuning walks bricks) and the network's activations (flexible CG).  One
+// sequence of allocations serves the solve and the workspace size query.
+struct CgBufs {
+    float *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *img = nullptr, *z = nullptr;
+    float *bricks = nullptr;
+    Workspace ws;
+    int bps = TOMO_BP_BLOCKED;
+    void *bscr = nullptr;
+    size_t bscr_bytes = 0;
+    void *netws = nullptr;
+};
+
+static bool cg_buffers(SolveBuffers &buf, const Plan &plan, const tomo_geometry *g, const tomo_cg_params *prm,
+                       CgBufs &o)
+{
+    const Dims d = dims_of(g->cube);
+    const int64_t n = d.total;
+    const tomo_tuning tu = tuning_for(plan);
+    o.b = (float *)buf.alloc(sizeof(float) * n);
+    o.r = (float *)buf.alloc(sizeof(float) * n);
+    o.p = (float *)buf.alloc(sizeof(float) * n);
+    o.q = (float *)buf.alloc(sizeof(float) * n);
+    o.img = (float *)buf.alloc(sizeof(float) * plan.npix);
+    o.ws.partials = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
+    o.ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
+    o.ws.cpart = (double *)buf.alloc(sizeof(double) * 4 * kIterBlocks);
+    o.ws.nq = (int32_t)iter_blocks(n);
+    o.ws.st = (CgState *)buf.alloc(sizeof(CgState));
+    o.ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)prm->max_iter + 1));
+    bool ok = o.b && o.r && o.p && o.q && o.img && o.ws.partials && o.ws.counter && o.ws.cpart && o.ws.st &&
+              o.ws.hist;
+    // back-projection strategy and its scratch, fixed for the whole solve
+    o.bps = resolve_bp_strategy(plan, prm->bp_strategy);
+    if (o.bps == TOMO_BP_BLOCKED) {
+        o.bscr_bytes = blocked_scratch_bytes(plan, blocked_shape(plan, tu), g->data_mask != nullptr);
+        o.bscr = buf.alloc(o.bscr_bytes);
+        ok = ok && o.bscr;
+    }
+    const size_t nbr = bricked_copy_bytes(plan, tu);
+    if (nbr) {
+        o.bricks = (float *)buf.alloc(nbr);
+        ok = ok && o.bricks;
+    }
+    if (prm->precond) {
+        o.z = (float *)buf.alloc(sizeof(float) * n);
+        o.netws = buf.alloc(convnet_forward_ws_bytes(d.nvox));
+        ok = ok && o.z && o.netws;
+    }
+    return ok;
+}
 
 struct EventPool {
     std::vector<hipEvent_t> ev;
@@ -822,6 +892,21 @@ int tomo_apply_prior(const tomo_cube *cube, double lambda_r, double lambda_t, co
     return tomo_apply_height_prior(cube, nullptr, lambda_r, lambda_t, x_d, out_d, accumulate, stream);
 }
 
+size_t tomo_cg_workspace_bytes(const tomo_geometry *g, const tomo_cg_params *prm)
+{
+    if (!g || !prm || prm->max_iter < 0 || prm->use_graph || prm->bp_strategy < TOMO_BP_AUTO ||
+        prm->bp_strategy > TOMO_BP_BLOCKED)
+        return 0;
+    int st = TOMO_OK;
+    PlanRef plan = get_plan(g, &st);
+    if (!plan) return 0;
+    SolveBuffers m;
+    m.measure = true;
+    CgBufs sized;
+    (void)cg_buffers(m, *plan, g, prm, sized);
+    return m.used;
+}
+
 int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const tomo_cg_params *prm,
                   tomo_cg_report *rep, tomo_stream stream)
 {
@@ -843,6 +928,8 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     if (prm->precond && g->cube.nframes != 1)
         return set_error(TOMO_EUNSUPPORTED, "tomo_cg_solve: the preconditioner needs nframes == 1");
     if (prm->use_graph) {  // graph-captured iterations: a batch of one
+        if (prm->workspace)
+            return set_error(TOMO_EUNSUPPORTED, "tomo_cg_solve: use_graph takes no caller workspace");
         if (prm->precond || prm->record_count > 0)
             return set_error(TOMO_EUNSUPPORTED, "tomo_cg_solve: use_graph without preconditioner or recording");
         tomo_batch bt = nullptr;
@@ -865,35 +952,30 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
 
     SolveBuffers buf;
     buf.s = s;
-    float *b = (float *)buf.alloc(sizeof(float) * n);
-    float *r = (float *)buf.alloc(sizeof(float) * n);
-    float *p = (float *)buf.alloc(sizeof(float) * n);
-    float *q = (float *)buf.alloc(sizeof(float) * n);
-    float *img = (float *)buf.alloc(sizeof(float) * plan->npix);
-    Workspace ws;
-    ws.partials = (double *)buf.alloc(sizeof(double) * 4 * kRedBlocks);
-    ws.counter = (unsigned *)buf.alloc(sizeof(unsigned));
-    ws.cpart = (double *)buf.alloc(sizeof(double) * 4 * kIterBlocks);
-    ws.nq = (int32_t)iter_blocks(n);
-    ws.st = (CgState *)buf.alloc(sizeof(CgState));
-    ws.hist = (double *)buf.alloc(sizeof(double) * ((size_t)maxit + 1));
-    // back-projection strategy and its scratch, fixed for the whole solve
-    const int bps = resolve_bp_strategy(*plan, prm->bp_strategy);
+    if (prm->workspace) {
+        if ((uintptr_t)prm->workspace & 255u)
+            return set_error(TOMO_EINVAL, "tomo_cg_solve: the workspace must be 256-byte aligned");
+        SolveBuffers m;
+        m.measure = true;
+        CgBufs sized;
+        (void)cg_buffers(m, *plan, g, prm, sized);
+        if (prm->workspace_bytes < m.used)
+            return set_error(TOMO_EINVAL, "tomo_cg_solve: workspace of %zu bytes, %zu needed", prm->workspace_bytes,
+                             m.used);
+        buf.arena = (char *)prm->workspace;
+        buf.arena_bytes = prm->workspace_bytes;
+    }
+    CgBufs cb;
+    if (!cg_buffers(buf, *plan, g, prm, cb)) return set_error(TOMO_ENOMEM, "tomo_cg_solve: device allocation failed");
+    float *b = cb.b, *r = cb.r, *p = cb.p, *q = cb.q, *img = cb.img, *z = cb.z;
+    Workspace ws = cb.ws;
+    const int bps = cb.bps;
     // the blocked P^T writes every voxel of q; the atomic ones add into a
     // q that the x/r update has cleared
     const int bp_acc = bps == TOMO_BP_BLOCKED ? 0 : 1;
-    size_t bscr_bytes = 0;
-    void *bscr = nullptr;
-    if (bps == TOMO_BP_BLOCKED) {
-        bscr_bytes = blocked_scratch_bytes(*plan, blocked_shape(*plan, tuning_for(*plan)), g->data_mask != nullptr);
-        bscr = buf.alloc(bscr_bytes);
-        if (!bscr) return set_error(TOMO_ENOMEM, "tomo_cg_solve: device allocation failed");
-    }
-    float *z = fcg ? (float *)buf.alloc(sizeof(float) * n) : nullptr;
-    void *netws = fcg ? buf.alloc(convnet_forward_ws_bytes(d.nvox)) : nullptr;
-    if (!b || !r || !p || !q || !img || !ws.partials || !ws.counter || !ws.cpart || !ws.st || !ws.hist ||
-        (fcg && (!z || !netws)))
-        return set_error(TOMO_ENOMEM, "tomo_cg_solve: device allocation failed");
+    void *bscr = cb.bscr;
+    const size_t bscr_bytes = cb.bscr_bytes;
+    void *netws = cb.netws;
     int rc = hip_fail(hipMemsetAsync(ws.counter, 0, sizeof(unsigned), s), "counter init");
     if (!rc) rc = hip_fail(hipMemsetAsync(ws.st, 0, sizeof(CgState), s), "state init");
     if (rc) return rc;
@@ -940,7 +1022,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         hipLaunchKernelGGL(k_mask, dim3(eb), dim3(kThreads), 0, s, x_d, g->map_mask, d);
     }
     auto apply_A_to = [&](const float *v) -> int {  // q = M (P^T P + prior) v, excluding the prior
-        int e = launch_project(*plan, g, v, img, false, s);
+        int e = launch_project_flagged(*plan, g, v, img, s, nullptr, cb.bricks);
         if (!e) e = launch_backproject(*plan, g, img, q, false, false, bps, s, nullptr, bscr, bscr_bytes);
         n_proj++;
         n_bp++;
@@ -997,7 +1079,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
             e2 = evp.get();
             (void)hipEventRecord(e0, s);
         }
-        int e = launch_project_flagged(*plan, g, p, img, s, &ws.st->done);
+        int e = launch_project_flagged(*plan, g, p, img, s, &ws.st->done, cb.bricks);
         if (timed) (void)hipEventRecord(e1, s);
         if (!e) e = launch_backproject(*plan, g, img, q, bp_acc != 0, false, bps, s, &ws.st->done, bscr, bscr_bytes);
         if (timed) {

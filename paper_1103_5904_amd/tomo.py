@@ -78,7 +78,7 @@ class CgParams(ctypes.Structure):
                 ("use_graph", c_int32), ("precond", c_void_p), ("fallback_window", c_int32),
                 ("bp_strategy", c_int32), ("min_drop", c_double), ("record_x", c_void_p),
                 ("record_r", c_void_p), ("record_count", c_int32), ("reserved", c_int32),
-                ("height", POINTER(TomoHeight))]
+                ("height", POINTER(TomoHeight)), ("workspace", c_void_p), ("workspace_bytes", ctypes.c_size_t)]
 
 
 class CgReport(ctypes.Structure):
@@ -100,7 +100,7 @@ EXPORTS = [
     "tomo_convnet_loss_grad", "tomo_convnet_backward", "tomo_adam_step", "tomo_autotune",
     "tomo_get_class_tuning", "tomo_autotune_clear", "tomo_batch_create", "tomo_batch_destroy",
     "tomo_batch_project", "tomo_batch_backproject", "tomo_batch_binning_spills", "tomo_batch_items",
-    "tomo_batch_cg_solve", "tomo_backproject_noalloc", "tomo_autotune_data",
+    "tomo_batch_cg_solve", "tomo_backproject_noalloc", "tomo_autotune_data", "tomo_cg_workspace_bytes",
 ]
 NPARAMS = 7809
 
@@ -135,6 +135,8 @@ def lib():
         L.tomo_cg_solve.argtypes = [POINTER(TomoGeometry), c_void_p, c_void_p, POINTER(CgParams),
                                     POINTER(CgReport), c_void_p]
         L.tomo_cg_default_params.argtypes = [POINTER(CgParams)]
+        L.tomo_cg_workspace_bytes.argtypes = [POINTER(TomoGeometry), POINTER(CgParams)]
+        L.tomo_cg_workspace_bytes.restype = ctypes.c_size_t
         L.tomo_view_from_wcs.argtypes = [c_double] * 10 + [c_int32, c_int32, POINTER(TomoView)]
         L.tomo_validate_geometry.argtypes = [POINTER(TomoGeometry)]
         L.tomo_binning_spills.argtypes = [POINTER(TomoGeometry), POINTER(c_int64)]
@@ -392,8 +394,9 @@ _REPORT_KEYS = ("iters", "status", "fell_back", "n_project", "n_backproject", "r
 
 
 class Batch:
-    """Several independent systems (DeviceGeometry each) behind one persistent
-    P launch and one persistent P^T launch (tomo_batch_*)."""
+    """Several independent systems (DeviceGeometry each): one persistent P^T
+    launch over all of them, P through each system's own launch
+    (tomo_batch_*)."""
 
     def __init__(self, geoms):
         self.geoms = list(geoms)  # keeps the masks alive
@@ -559,10 +562,13 @@ def cg_solve(geom: DeviceGeometry, y: torch.Tensor, x0: torch.Tensor | None = No
              check_every: int = 10, use_graph: bool = False, precond: torch.Tensor | None = None,
              fallback_window: int = 3, min_drop: float = 1e-6, bp_strategy: int = BP_AUTO,
              time_kernels: bool = False, out: torch.Tensor | None = None,
-             record_x: torch.Tensor | None = None, record_r: torch.Tensor | None = None, height=None):
+             record_x: torch.Tensor | None = None, record_r: torch.Tensor | None = None, height=None,
+             workspace: torch.Tensor | None = None):
     """Solve M (P^T G^2 P + lam_r R D^T D R + lam_t D_t^T D_t) M x = M P^T G y
     (G the geometry's gains; R the voxel heights for height = (cx, cy, cz,
-    offset), else the identity).  Returns (x, report dict)."""
+    offset), else the identity).  workspace: a CUDA uint8 tensor of at least
+    cg_workspace_bytes(...) bytes for all of the solve's device buffers, or
+    None (stream-ordered scratch).  Returns (x, report dict)."""
     p = CgParams()
     lib().tomo_cg_default_params(ctypes.byref(p))
     h = _height(height)
@@ -581,6 +587,11 @@ def cg_solve(geom: DeviceGeometry, y: torch.Tensor, x0: torch.Tensor | None = No
             p.record_x = _dev_f32(record_x, count * nv, "record_x")
         if record_r is not None:
             p.record_r = _dev_f32(record_r, count * nv, "record_r")
+    if workspace is not None:
+        if not workspace.is_cuda or not workspace.is_contiguous():
+            raise ValueError("workspace must be a contiguous CUDA tensor")
+        p.workspace = workspace.data_ptr()
+        p.workspace_bytes = workspace.numel() * workspace.element_size()
     if out is None:
         out = torch.empty(geom.cube_shape, dtype=torch.float32, device=y.device)
     if x0 is not None:
@@ -597,6 +608,18 @@ def cg_solve(geom: DeviceGeometry, y: torch.Tensor, x0: torch.Tensor | None = No
     report = {k: getattr(rep, k) for k in _REPORT_KEYS}
     report["history"] = np.ctypeslib.as_array(hist)[:rep.history_len].copy()
     return out, report
+
+
+def cg_workspace_bytes(geom: DeviceGeometry, *, max_iter: int = 50, precond: torch.Tensor | None = None,
+                       bp_strategy: int = BP_AUTO) -> int:
+    """Device workspace bytes cg_solve takes with these settings
+    (tomo_cg_workspace_bytes); 0 for settings it rejects."""
+    p = CgParams()
+    lib().tomo_cg_default_params(ctypes.byref(p))
+    p.max_iter, p.bp_strategy = int(max_iter), int(bp_strategy)
+    if precond is not None:
+        p.precond = _dev_f32(precond, precond.numel(), "precond")
+    return int(lib().tomo_cg_workspace_bytes(geom.ref, ctypes.byref(p)))
 
 
 class ConvNet:
