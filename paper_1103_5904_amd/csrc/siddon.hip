@@ -172,6 +172,27 @@ __global__ __launch_bounds__(kThreads) void k_project_bricked(
                                                data_mask, images);
 }
 
+// The same with the per-axis offset terms in LDS (n0 + n1 + n2 entries of
+// dynamic shared memory), filled by the workgroup before its walk.
+template <bool kDataMask, bool kObstacle>
+__global__ __launch_bounds__(kThreads) void k_project_bricked_lut(
+    GridDev g, const ViewDev *__restrict__ views, int32_t nviews, Bundle bun, int32_t maxit,
+    const float *__restrict__ bricked, BrickDev bk, const uint8_t *__restrict__ data_mask,
+    float *__restrict__ images, const int *__restrict__ done_flag)
+{
+    extern __shared__ uint32_t lut[];
+    if (done_flag && *done_flag) return;
+    const int ntab = g.n[0] + g.n[1] + g.n[2];
+    for (int e = threadIdx.x; e < ntab; e += kThreads) {
+        const int a = e < g.n[0] ? 0 : (e < g.n[0] + g.n[1] ? 1 : 2);
+        const int i = a == 0 ? e : (a == 1 ? e - g.n[0] : e - g.n[0] - g.n[1]);
+        lut[e] = brick_axis_term(bk, a, i);
+    }
+    __syncthreads();
+    project_tile_bricked<kDataMask, kObstacle, true>(g, views, nviews, bun.log2_bw, block_tile(bun), maxit,
+                                                     bricked, bk, data_mask, images, lut);
+}
+
 // ------------------------------------------------------------ launchers
 
 static int64_t grid_blocks(int64_t n) { return (n + kThreads - 1) / kThreads; }
@@ -245,6 +266,22 @@ int launch_project_from_bricks(const Plan &p, const tomo_geometry *g, const floa
     const Bundle b{tu.p_bundle, tu.p_xcd_remap};
     const bool dm = g->data_mask != nullptr;
     const dim3 grid((unsigned)p.ntiles), blk(kThreads);
+    // the per-axis offset terms in LDS when they fit in 32 KiB
+    const size_t lut = sizeof(uint32_t) * ((size_t)p.grid.n[0] + p.grid.n[1] + p.grid.n[2]);
+    if (lut <= 32768) {
+#define TOMO_LAUNCH_PB(D, O)                                                                                       \
+    hipLaunchKernelGGL((k_project_bricked_lut<D, O>), grid, blk, lut, s, p.grid, p.views_d, p.nviews, b,          \
+                       p.max_steps, br, bk, g->data_mask, images, done_flag)
+        if (dm) {
+            if (p.grid.has_sph) TOMO_LAUNCH_PB(true, true);
+            else TOMO_LAUNCH_PB(true, false);
+        } else {
+            if (p.grid.has_sph) TOMO_LAUNCH_PB(false, true);
+            else TOMO_LAUNCH_PB(false, false);
+        }
+#undef TOMO_LAUNCH_PB
+        return hip_fail(hipGetLastError(), "bricked projection kernel launch");
+    }
 #define TOMO_LAUNCH_PB(D, O)                                                                                   \
     hipLaunchKernelGGL((k_project_bricked<D, O>), grid, blk, 0, s, p.grid, p.views_d, p.nviews, b, p.max_steps, \
                        br, bk, g->data_mask, images, done_flag)

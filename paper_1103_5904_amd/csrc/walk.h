@@ -353,15 +353,29 @@ __device__ inline uint32_t brick_offset(const BrickDev &bk, int i0, int i1, int 
            ((uint32_t)i0 & m);
 }
 
+// The bricked offset is a sum of one term per axis: brick_offset(i0, i1,
+// i2) = f0(i0) + f1(i1) + f2(i2) with f_a(i) = (i >> k) S_a 2^3k + (i & m)
+// 2^(k a), S = (1, nb0, nb0 nb1), since the brick index is linear in the
+// per-axis brick coordinates and the in-brick bits do not overlap it.
+__device__ inline uint32_t brick_axis_term(const BrickDev &bk, int a, int i)
+{
+    const uint32_t m = (1u << bk.k) - 1u;
+    const uint32_t s = a == 0 ? 1u : (a == 1 ? (uint32_t)bk.nb[0] : (uint32_t)bk.nb[0] * (uint32_t)bk.nb[1]);
+    return ((((uint32_t)i >> bk.k) * s) << (3 * bk.k)) + (((uint32_t)i & m) << (bk.k * a));
+}
+
 // P for one 16x16 tile from a bricked copy of M x (the map mask applied by
 // the copy): the same walk as project_tile, the voxel indices carried per
 // axis and the offset formed from them; the same segments summed in the
-// same order, so the same bits.
-template <bool kDataMask, bool kObstacle>
+// same order, so the same bits.  With kLut the offset is the sum of three
+// per-axis terms read from LDS (lut: f0 over the n0 x indices, then f1,
+// then f2), one add and three LDS reads per step instead of the shifts,
+// masks and multiplies of brick_offset.
+template <bool kDataMask, bool kObstacle, bool kLut = false>
 __device__ inline void project_tile_bricked(const GridDev &g, const ViewDev *__restrict__ views, int32_t nviews,
                                             int log2_bw, int64_t tile, int32_t maxit, const float *__restrict__ bricked,
                                             const BrickDev &bk, const uint8_t *__restrict__ data_mask,
-                                            float *__restrict__ images)
+                                            float *__restrict__ images, const uint32_t *lut = nullptr)
 {
     const LanePixel lp = lane_pixel(views, nviews, tile, log2_bw);
     const ViewDev &v = views[lp.view];
@@ -384,7 +398,8 @@ __device__ inline void project_tile_bricked(const GridDev &g, const ViewDev *__r
         float x_prev = 0.0f;
         auto step = [&]() {
             const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
-            const uint32_t off = brick_offset(bk, i[0], i[1], i[2]);
+            const uint32_t off = kLut ? lut[i[0]] + lut[g.n[0] + i[1]] + lut[g.n[0] + g.n[1] + i[2]]
+                                      : brick_offset(bk, i[0], i[1], i[2]);
             const double dl = m - scur;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
