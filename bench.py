@@ -56,10 +56,11 @@ VALU_PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 # VALU instructions of one voxel crossing in the walk loop of each kernel of
 # an iteration (its four-crossing loop body in the gfx950 ISA, divided by
 # four): the P^T walk with its fixed-point LDS deposit (batch.hip), and the
-# P gather-FMA walk over the 16^3-bricked cube of the dominant system
-# (siddon.hip; its loop body holds both the buffer and the clamped global
-# load, of which a launch runs one).
-WALK_VALU_PER_CROSSING = {"k_project_bricked": 158 / 4, "k_batch_backproject": 92 / 4}
+# P gather-FMA walk over the 16^3-bricked cube of the dominant system with
+# its offsets from the LDS table of per-axis terms (siddon.hip; 120 VALU per
+# loop body, of which the clamped global-load path a launch does not run
+# takes 12).
+WALK_VALU_PER_CROSSING = {"k_project_bricked_lut": 108 / 4, "k_batch_backproject": 92 / 4}
 
 # Per-launch counters of the batched kernels on the headline step, from
 # rocprofv3 --pmc passes of `bench.py --headline-only` (profiles/
@@ -233,7 +234,7 @@ def roofline(h):
         kern, ms, cross = "k_batch_backproject", h["ms_b"], h["cross_b"]
         alg = 8.0 * cross + 4.0 * h["rays"]
     else:
-        kern, ms, cross = "k_project_bricked", h["ms_p"], h["cross_p"]
+        kern, ms, cross = "k_project_bricked_lut", h["ms_p"], h["cross_p"]
         alg = 4.0 * cross + 4.0 * h["rays"]
     sec = ms * 1e-3
     per = WALK_VALU_PER_CROSSING[kern]
