@@ -143,18 +143,30 @@ __global__ __launch_bounds__(kThreads) void k_mask_copy(const float *__restrict_
     }
 }
 
-// The bricked copy of M x (every frame): one thread per voxel of a frame,
-// reading the x-fastest cube in order.
+// The bricked copy of M x (every frame): one thread per position of a
+// bricked frame, in the copy's own order, so that a wavefront writes 256
+// contiguous bytes and reads runs of 2^k voxels of x rows (a row's other
+// runs are read by the neighbouring bricks' threads soon after, from L2).
+// Positions in the padding of partial bricks are left alone: no walk reads
+// them.
 __global__ __launch_bounds__(kThreads) void k_brick_copy(const float *__restrict__ x,
                                                          const uint8_t *__restrict__ mask, GridDev g, BrickDev bk,
                                                          float *__restrict__ out, const int *__restrict__ done_flag)
 {
     if (done_flag && *done_flag) return;
-    const int32_t nx = g.n[0], ny = g.n[1];
-    for (int64_t v = (int64_t)blockIdx.x * kThreads + threadIdx.x; v < g.nvox; v += (int64_t)gridDim.x * kThreads) {
-        const int32_t i0 = (int32_t)(v % nx), r = (int32_t)(v / nx);
-        const int32_t i1 = r % ny, i2 = r / ny;
-        const int64_t o = brick_offset(bk, i0, i1, i2);
+    const int32_t nx = g.n[0], ny = g.n[1], nz = g.n[2];
+    const uint32_t k = (uint32_t)bk.k, m = (1u << k) - 1u;
+    const uint32_t nb0 = (uint32_t)bk.nb[0], nb01 = (uint32_t)bk.nb[0] * (uint32_t)bk.nb[1];
+    for (int64_t o = (int64_t)blockIdx.x * kThreads + threadIdx.x; o < bk.frame_stride;
+         o += (int64_t)gridDim.x * kThreads) {
+        const uint32_t b = (uint32_t)((uint64_t)o >> (3 * k)), l = (uint32_t)o & ((1u << (3 * k)) - 1u);
+        const uint32_t b2 = b / nb01, rb = b - b2 * nb01;
+        const uint32_t b1 = rb / nb0, b0 = rb - b1 * nb0;
+        const int32_t i0 = (int32_t)((b0 << k) | (l & m));
+        const int32_t i1 = (int32_t)((b1 << k) | ((l >> k) & m));
+        const int32_t i2 = (int32_t)((b2 << k) | (l >> (2 * k)));
+        if (i0 >= nx || i1 >= ny || i2 >= nz) continue;
+        const int64_t v = ((int64_t)i2 * ny + i1) * nx + i0;
         const bool keep = !mask || mask[v] != 0;
         for (int32_t f = 0; f < g.nframes; ++f)
             out[(int64_t)f * bk.frame_stride + o] = keep ? x[(int64_t)f * g.nvox + v] : 0.0f;
@@ -253,7 +265,7 @@ bool brick_layout(const Plan &p, int k, BrickDev &bk)
 int brick_copy_launch(const Plan &p, const float *cube, const uint8_t *map_mask, const BrickDev &bk, float *out,
                       hipStream_t s, const int *done_flag)
 {
-    int64_t nb = grid_blocks(p.grid.nvox);
+    int64_t nb = grid_blocks(bk.frame_stride);
     nb = nb > 8192 ? 8192 : nb;
     hipLaunchKernelGGL(k_brick_copy, dim3((unsigned)nb), dim3(kThreads), 0, s, cube, map_mask, p.grid, bk, out,
                        done_flag);
