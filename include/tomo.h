@@ -247,6 +247,12 @@ int tomo_trace_ray(const tomo_geometry *g, int32_t view, int32_t col,
  *     the cube; it pays where the cube is far larger than the caches and
  *     the rays are sparser than the voxels, so that a ray's consecutive
  *     gathers would otherwise each fetch a cache line of their own.
+ *   bp_ray_table: 1 = where one geometry serves several blocked
+ *     back-projections (tomo_cg_solve, a batch), its rays are set up once
+ *     into a table (96 bytes per pixel: in the solve's scratch or workspace,
+ *     or held by the batch) that every launch reads, instead of once per
+ *     (ray, block) pair; 0 = no table.  Results are the same bit for bit.
+ *     Cubes with a side above 2^20 voxels take no table.
  * tomo_set_tuning returns TOMO_EINVAL (and changes nothing) for values out
  * of range.  Not synchronised with launches in flight on other threads.
  */
@@ -261,6 +267,7 @@ typedef struct tomo_tuning {
     int32_t bp_splits;
     int32_t bp_threads;
     int32_t p_layout;
+    int32_t bp_ray_table;
 } tomo_tuning;
 
 int tomo_get_tuning(tomo_tuning *out);
@@ -485,8 +492,9 @@ void tomo_cg_default_params(tomo_cg_params *p);
 /*
  * Bytes of device workspace tomo_cg_solve(g, ..., p, ...) takes when
  * p->workspace is set (the vectors of Eq. criterion's CG, the reductions'
- * partials, the blocked P^T's scratch, P's bricked copy of the iterate if the
- * geometry's tuning walks bricks, and the network's activations with a
+ * partials, the blocked P^T's scratch and, if the tuning's bp_ray_table is
+ * set, its ray table, P's bricked copy of the iterate if the geometry's
+ * tuning walks bricks, and the network's activations with a
  * preconditioner).  The figure depends on the launch tuning in effect for
  * g's size class: query again after tomo_autotune or tomo_set_tuning.
  * Returns 0 for invalid arguments and for use_graph = 1 (a batch of one
@@ -542,8 +550,10 @@ void tomo_autotune_clear(void);
  * tomo_backproject_ex with TOMO_BP_BLOCKED) bit for bit.
  *   systems: HOST array of nsystems geometries (1..32); their masks (DEVICE)
  *   must stay valid while the batch exists, their view arrays need not.
- * The batch owns its device work queues and scratch: use it from one stream
- * at a time.  tomo_batch_destroy synchronises the device.
+ * The batch owns its device work queues and scratch, and the ray tables of
+ * the systems whose tuning sets bp_ray_table (96 bytes per pixel, built
+ * when the batch is created, which then synchronises the device): use it
+ * from one stream at a time.  tomo_batch_destroy synchronises the device.
  */
 typedef struct tomo_batch_s *tomo_batch;
 int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems,

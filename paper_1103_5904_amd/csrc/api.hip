@@ -29,7 +29,7 @@ static std::mutex g_tuning_mu;
 // 1.27 ms against 1.46 ms for 64x32x2 with 256 lanes on the EUVI-like
 // problem, 5.50 against 6.65 ms on a COR1-like frame).  The binned strategy,
 // which alone takes the bundle field, prefers 8x8 bundles and 4096 bins.
-static tomo_tuning g_tuning = {2, 1, 3, 0, 4096, TOMO_BP_BLOCKED, {128, 32, 2}, 0, 512, 0};
+static tomo_tuning g_tuning = {2, 1, 3, 0, 4096, TOMO_BP_BLOCKED, {128, 32, 2}, 0, 512, 0, 1};
 
 tomo_tuning current_tuning()
 {
@@ -365,6 +365,8 @@ int tomo_set_tuning(const tomo_tuning *in)
         return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_threads must be 256, 512 or 1024");
     if (in->p_layout != 0 && (in->p_layout < 2 || in->p_layout > 4))
         return set_error(TOMO_EINVAL, "tomo_set_tuning: p_layout must be 0, 2, 3 or 4");
+    if (in->bp_ray_table != 0 && in->bp_ray_table != 1)
+        return set_error(TOMO_EINVAL, "tomo_set_tuning: bp_ray_table must be 0 or 1");
     std::lock_guard<std::mutex> lock(g_tuning_mu);
     g_tuning = *in;
     return TOMO_OK;

@@ -23,6 +23,7 @@ struct SysDev {
     uint16_t *kept_pre;   // kept-pixel rows of the data mask (row intervals only), or null
     uint16_t *kept_cols;
     float *bricked;       // P's bricked copy of M x (the system's tuning asks for bricks), or null
+    RayTable tab;         // the system's ray table (tab.d null: P^T sets its rays up)
     BrickDev bk;
     BlockDev bd;
     int32_t nviews;
@@ -68,5 +69,6 @@ struct tomo_batch_s {
     int32_t nt = 256;   // lanes per workgroup of the persistent P^T (the dominant system's tuning)
     uint16_t *kept = nullptr;  // kept-pixel rows of the systems' data masks
     float *bricks = nullptr;   // bricked copies of the cubes of the systems that walk bricks in P
+    char *tables = nullptr;    // ray tables of the systems whose tuning asks for one
     ~tomo_batch_s();
 };

@@ -29,6 +29,7 @@
 //   check interval are captured once as a HIP graph and replayed.
 #include <math.h>
 #include <stddef.h>
+#include <stdint.h>
 #include <string.h>
 
 #include <vector>
@@ -133,7 +134,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
         const KeptRows kept{sd.kept_pre, sd.kept_cols};
 #define TOMO_ITEM(M, D, O)                                                                                      \
     blocked_item<NT, M, D, O, kRows>(sd.grid, sd.views, sd.frame_views, sd.frame_voff, sd.bd, li, ops.src[k],  \
-                                     sd.map_mask, sd.data_mask, kept, ym, out, ops.acc, spill, bins, sh)
+                                     sd.map_mask, sd.data_mask, kept, ym, out, ops.acc, spill, sd.tab, bins, sh)
         if (sd.grid.has_sph) {  // the obstacle's variant: one code path for every mask combination
             if (mm && dm) TOMO_ITEM(true, true, true);
             else if (mm) TOMO_ITEM(true, false, true);
@@ -190,6 +191,7 @@ tomo_batch_s::~tomo_batch_s()
     if (part) (void)hipFree(part);
     if (kept) (void)hipFree(kept);
     if (bricks) (void)hipFree(bricks);
+    if (tables) (void)hipFree(tables);
     if (spill) (void)hipFree(spill);
     (void)hipSetDevice(cur);
 }
@@ -285,6 +287,8 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
     (void)hipGetDevice(&b->device);
     b->nsys = nsystems;
     int64_t part_floats = 0, kept_pix = 0, brick_floats = 0;
+    size_t table_bytes = 0;
+    std::vector<size_t> table_at;  // offset of each system's ray table (SIZE_MAX: none)
     int nrows = 0;  // systems whose plans ask for footprint row intervals
     std::vector<PlanRef> plans;
     std::vector<tomo_tuning> tunings;
@@ -338,6 +342,9 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
             bricked[(size_t)k] = true;
             brick_floats += sd.bk.frame_stride * p->grid.nframes;
         }
+        const size_t tb = tu.bp_ray_table ? ray_table_bytes(*p) : 0;
+        table_at.push_back(tb ? table_bytes : SIZE_MAX);
+        table_bytes += (tb + 255) & ~(size_t)255;
         sd.maxit = p->max_steps;
         sd.view_begin = b->nviews;
         sd.tile_begin = b->ntiles;
@@ -373,6 +380,7 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
     if (e == hipSuccess && b->rows && kept_pix > 0)
         e = hipMalloc((void **)&b->kept, 2 * sizeof(uint16_t) * (size_t)kept_pix);
     if (e == hipSuccess && brick_floats > 0) e = hipMalloc((void **)&b->bricks, sizeof(float) * (size_t)brick_floats);
+    if (e == hipSuccess && table_bytes > 0) e = hipMalloc((void **)&b->tables, table_bytes);
     if (e != hipSuccess) {
         delete b;
         return set_error(TOMO_ENOMEM, "tomo_batch_create: device allocation failed (%s)", hipGetErrorString(e));
@@ -394,6 +402,19 @@ int tomo_batch_create(const tomo_geometry *systems, int32_t nsystems, tomo_batch
             sd.kept_cols = b->kept + koff + np;
             koff += 2 * np;
         }
+        if (table_at[k] != SIZE_MAX) {  // the system's rays, set up once for the batch's life
+            RayTable t;
+            const int rc = ray_table_build(*b->plans[k], b->tables + table_at[k], t, nullptr);
+            if (rc) {
+                delete b;
+                return rc;
+            }
+            sd.tab = t;
+        }
+    }
+    if (table_bytes > 0 && (e = hipStreamSynchronize(nullptr)) != hipSuccess) {
+        delete b;
+        return set_error(TOMO_ENOMEM, "tomo_batch_create: ray table build failed (%s)", hipGetErrorString(e));
     }
     e = hipMalloc((void **)&b->sys_d, sizeof(SysDev) * b->sys_h.size());
     if (e == hipSuccess) e = hipMemcpy(b->sys_d, b->sys_h.data(), sizeof(SysDev) * b->sys_h.size(), hipMemcpyHostToDevice);

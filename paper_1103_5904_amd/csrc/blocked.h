@@ -155,7 +155,8 @@ __device__ inline bool row_interval(const V &v, int row, const float (&lo)[3], c
 // inside it, and the block written once.  bins: nbins 64-bit LDS words plus
 // a dummy.  Called by all NT threads of the workgroup.  kept.cols != null
 // (with kDataMask) takes the passes over kept pixels only, in row-interval
-// footprints.
+// footprints.  tab.d != null: each ray's set-up is read from the geometry's
+// ray table instead of computed.
 template <int NT, bool kMapMask, bool kDataMask, bool kObstacle, bool kRows>
 __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict__ views,
                                     const int32_t *__restrict__ frame_views,
@@ -164,7 +165,7 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                                     const uint8_t *__restrict__ map_mask,
                                     const uint8_t *__restrict__ data_mask, KeptRows kept,
                                     const uint32_t *__restrict__ ymax_parts, float *__restrict__ out,
-                                    int32_t accumulate, unsigned *__restrict__ spill,
+                                    int32_t accumulate, unsigned *__restrict__ spill, const RayTable &tab,
                                     unsigned long long *bins, BlockedShared<NT, kRows> &sh)
 {
     using Sh = BlockedShared<NT, kRows>;
@@ -402,17 +403,19 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
         int col = 0, row = 0;
         bool ok = L < total;
         int jn = 0;
+        int64_t pixn = 0;
         float ynext = 0.0f;
         bool mnext = true;
         if (ok) {
             const bool known = locate(L, col, row);
             jn = j;
-            const int64_t pix = sh.view[j].pix_off + (int64_t)row * sh.view[j].ncol + col;
-            ynext = images[pix];
-            if (kDataMask && !known) mnext = data_mask[pix] != 0;
+            pixn = sh.view[j].pix_off + (int64_t)row * sh.view[j].ncol + col;
+            ynext = images[pixn];
+            if (kDataMask && !known) mnext = data_mask[pixn] != 0;
         }
         for (int64_t base = 0; base < total; base += NT) {
             const int pcol = col, prow = row, pj = jn;
+            const int64_t ppix = pixn;
             const bool pok = ok, pm = mnext;
             const float yv = ynext;
             L += NT;
@@ -420,16 +423,20 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
             if (ok) {
                 const bool known = locate(L, col, row);
                 jn = j;
-                const int64_t pix = sh.view[j].pix_off + (int64_t)row * sh.view[j].ncol + col;
-                ynext = images[pix];
+                pixn = sh.view[j].pix_off + (int64_t)row * sh.view[j].ncol + col;
+                ynext = images[pixn];
                 mnext = true;
-                if (kDataMask && !known) mnext = data_mask[pix] != 0;
+                if (kDataMask && !known) mnext = data_mask[pixn] != 0;
             }
             if (!pok || !nonzero_bits(yv) || (kDataMask && !pm)) continue;
             const StagedView &v = sh.view[pj];
             RayState r;
             RayAxes ax;
-            if (!ray_setup<kObstacle>(g, v, pcol, prow, r, &ax)) continue;
+            if (tab.d) {
+                if (!ray_table_get(tab, ppix, r, ax)) continue;
+            } else if (!ray_setup<kObstacle>(g, v, pcol, prow, r, &ax)) {
+                continue;
+            }
             // parameter interval [E, X) inside the block, exact on the ray's grid
             double E = 0.0, X = r.send;
             bool hit = true;

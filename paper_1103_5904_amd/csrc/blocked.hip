@@ -90,13 +90,58 @@ __global__ __launch_bounds__(kThreads) void k_kept_rows(const ViewDev *__restric
     }
 }
 
+// The ray table of a geometry (RayTable): one thread per pixel, views along
+// the grid's y.
+__global__ __launch_bounds__(kThreads) void k_ray_table(GridDev g, const ViewDev *__restrict__ views, int32_t nviews,
+                                                        double *__restrict__ d, uint64_t *__restrict__ k, int64_t n)
+{
+    for (int vi = blockIdx.y; vi < nviews; vi += gridDim.y) {
+        const ViewDev &v = views[vi];
+        const int64_t np = (int64_t)v.ncol * v.nrow;
+        for (int64_t q = (int64_t)blockIdx.x * kThreads + threadIdx.x; q < np; q += (int64_t)gridDim.x * kThreads) {
+            const int row = (int)(q / v.ncol), col = (int)(q - (int64_t)row * v.ncol);
+            RayState r;
+            RayAxes ax;
+            const bool ok = ray_setup<true>(g, v, col, row, r, &ax);
+            ray_table_put(d, k, n, v.pix_off + q, ok, r, ax);
+        }
+    }
+}
+
+size_t ray_table_bytes(const Plan &p)
+{
+    for (int a = 0; a < 3; ++a)
+        if (p.grid.n[a] > (1 << kRayTableSideBits)) return 0;
+    if (p.npix <= 0) return 0;
+    const size_t n = (size_t)p.npix;
+    return ((sizeof(double) * kRayTableCols * n + 255) & ~(size_t)255) + sizeof(uint64_t) * n;
+}
+
+int ray_table_build(const Plan &p, void *mem, RayTable &out, hipStream_t s)
+{
+    if (!ray_table_bytes(p) || !mem) return set_error(TOMO_EINVAL, "ray table: none for this geometry");
+    const size_t n = (size_t)p.npix;
+    double *d = (double *)mem;
+    uint64_t *k = (uint64_t *)((char *)mem + ((sizeof(double) * kRayTableCols * n + 255) & ~(size_t)255));
+    // a view's pixels grid-stride over gx workgroups, sized for the mean view
+    const int64_t per_view = (p.npix + p.nviews - 1) / p.nviews;
+    int64_t gx = (per_view + kThreads - 1) / kThreads;
+    gx = gx < 1 ? 1 : (gx > 1024 ? 1024 : gx);
+    const dim3 grid((unsigned)gx, (unsigned)(p.nviews < 65535 ? p.nviews : 65535));
+    hipLaunchKernelGGL(k_ray_table, grid, dim3(kThreads), 0, s, p.grid, p.views_d, p.nviews, d, k, p.npix);
+    out.d = d;
+    out.k = k;
+    out.n = p.npix;
+    return hip_fail(hipGetLastError(), "ray table kernel launch");
+}
+
 template <int NT, bool kMapMask, bool kDataMask, bool kObstacle, bool kRows>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_backproject_blocked(
     GridDev g, const ViewDev *__restrict__ views, const int32_t *__restrict__ frame_views,
     const int32_t *__restrict__ frame_voff, BlockDev bd, Bundle bun, const float *__restrict__ images,
     const uint8_t *__restrict__ map_mask, const uint8_t *__restrict__ data_mask, KeptRows kept,
     const uint32_t *__restrict__ ymax_parts, float *__restrict__ out, int32_t accumulate,
-    const int *__restrict__ done_flag, unsigned *__restrict__ spill)
+    const int *__restrict__ done_flag, unsigned *__restrict__ spill, RayTable tab)
 {
     extern __shared__ unsigned long long bins[];  // bx*by*bz fixed-point (or FP32) sums
     __shared__ BlockedShared<NT, kRows> sh;
@@ -106,7 +151,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
     if (item >= nitems) return;
     blocked_item<NT, kMapMask, kDataMask, kObstacle, kRows>(g, views, frame_views, frame_voff, bd, item, images,
                                                             map_mask, data_mask, kept, ymax_parts, out, accumulate,
-                                                            spill, bins, sh);
+                                                            spill, tab, bins, sh);
 }
 
 // out[i] = M (sum over owners of part[s][i]) (+ out[i]), owners in order.
@@ -249,7 +294,7 @@ template <int NT>
 static int launch_blocked_nt(const Plan &p, const tomo_geometry *g, const BlockDev &bd, const Bundle &bun,
                              const BlockedShape &bs, size_t lds, const float *images, const KeptRows &kept,
                              const uint32_t *ymax, float *dst, int acc, bool mm, bool dm, hipStream_t s,
-                             const int *done_flag)
+                             const int *done_flag, const RayTable &tab)
 {
     int rc = TOMO_OK;
 #define TOMO_LAUNCH_BK4(M, D, O, R)                                                                             \
@@ -258,7 +303,7 @@ static int launch_blocked_nt(const Plan &p, const tomo_geometry *g, const BlockD
         if (!rc)                                                                                                \
             hipLaunchKernelGGL((k_backproject_blocked<NT, M, D, O, R>), dim3((unsigned)bs.items), dim3(NT), lds, \
                                s, p.grid, p.views_d, p.frame_views_d, p.frame_voff_d, bd, bun, images,          \
-                               g->map_mask, g->data_mask, kept, ymax, dst, acc, done_flag, p.spill_d);         \
+                               g->map_mask, g->data_mask, kept, ymax, dst, acc, done_flag, p.spill_d, tab);    \
     } while (0)
 #define TOMO_LAUNCH_BK3(M, D, O)                       \
     do {                                               \
@@ -282,9 +327,12 @@ static int launch_blocked_nt(const Plan &p, const tomo_geometry *g, const BlockD
 
 int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
                                bool accumulate, bool use_map_mask, hipStream_t s, const int *done_flag,
-                               void *scratch, size_t scratch_bytes, const tomo_tuning &tu)
+                               void *scratch, size_t scratch_bytes, const tomo_tuning &tu, const RayTable *tab)
 {
     const BlockedShape bs = blocked_shape(p, tu);
+    const RayTable rt = tab ? *tab : RayTable{};
+    if (rt.d && rt.n != p.npix)
+        return set_error(TOMO_EINVAL, "blocked back-projection: ray table of another geometry");
     const bool mm = use_map_mask && g->map_mask, dm = g->data_mask != nullptr;
     const size_t need = blocked_scratch_bytes(p, bs, dm);
     if (!scratch || scratch_bytes < need)
@@ -318,14 +366,16 @@ int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const floa
     const int acc = accumulate ? 1 : 0;
     switch (bs.nt) {
     case 512:
-        rc = launch_blocked_nt<512>(p, g, bd, bun, bs, lds, images, sc.kept, sc.ymax, dst, acc, mm, dm, s, done_flag);
+        rc = launch_blocked_nt<512>(p, g, bd, bun, bs, lds, images, sc.kept, sc.ymax, dst, acc, mm, dm, s, done_flag,
+                                    rt);
         break;
     case 1024:
         rc = launch_blocked_nt<1024>(p, g, bd, bun, bs, lds, images, sc.kept, sc.ymax, dst, acc, mm, dm, s,
-                                     done_flag);
+                                     done_flag, rt);
         break;
     default:
-        rc = launch_blocked_nt<256>(p, g, bd, bun, bs, lds, images, sc.kept, sc.ymax, dst, acc, mm, dm, s, done_flag);
+        rc = launch_blocked_nt<256>(p, g, bd, bun, bs, lds, images, sc.kept, sc.ymax, dst, acc, mm, dm, s, done_flag,
+                                    rt);
     }
     if (rc || bs.splits == 1) return rc;
     const int64_t total = p.grid.nvox * p.grid.nframes;

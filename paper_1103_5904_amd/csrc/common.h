@@ -197,6 +197,30 @@ uint64_t size_class_of(const tomo_geometry *g, int64_t npix);
 // there is one, else the process-wide tuning.
 tomo_tuning tuning_for(const Plan &p);
 
+// Per-ray results of the ray set-up over a whole geometry, for launches
+// that would otherwise redo the set-up of one ray many times (the blocked
+// P^T sets a ray up once per block it crosses).  Built once for a geometry
+// that several P^T applications share (a CG solve, a batch); the walk state
+// read back is bit for bit the set-up's, so results do not change.
+// Structure of arrays over the geometry's n pixels (image-vector order):
+//   d[c n + i], c = 0..10: next crossing s0 s1 s2, spacing ds0 ds1 ds2, exit
+//                          parameter send (0: the ray misses), |d|, and
+//                          ~1 / spacing rds0 rds1 rds2 (0: axis not crossed)
+//   k[i]:                  entry voxel index per axis, 20 bits each from
+//                          bit 0, 20, 40; bit 60 + a set: the ray moves up axis a
+struct RayTable {
+    const double *d = nullptr;
+    const uint64_t *k = nullptr;
+    int64_t n = 0;
+};
+constexpr int kRayTableCols = 11;
+constexpr int kRayTableSideBits = 20;  // largest cube side a table holds: 2^20 voxels
+// Bytes of a plan's table (0: its cube is too large for one).
+size_t ray_table_bytes(const Plan &p);
+// Lays the table out over `mem` (ray_table_bytes of device memory) and
+// launches its build on s.
+int ray_table_build(const Plan &p, void *mem, RayTable &out, hipStream_t s);
+
 // Launchers (siddon.hip)
 int launch_project(const Plan &p, const tomo_geometry *g, const float *cube, float *images,
                    bool use_map_mask, hipStream_t s);
@@ -221,10 +245,12 @@ int launch_project_with(const Plan &p, const tomo_geometry *g, const float *cube
                         bool use_map_mask, hipStream_t s, const tomo_tuning &tu);
 // scratch: blocked strategy only; when null the launcher takes stream-ordered
 // scratch from the pool for this launch.
+// tab: a built ray table of the plan, read by the blocked strategy instead
+// of setting rays up (null: set up in the launch).
 int launch_backproject(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
                        bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
                        const int *done_flag = nullptr, void *scratch = nullptr,
-                       size_t scratch_bytes = 0);
+                       size_t scratch_bytes = 0, const RayTable *tab = nullptr);
 // P of the plan's tuning without a map mask; a tuning that walks bricks
 // copies the cube into `bricks` (bricked_copy_bytes of them) when given,
 // else into stream-ordered scratch for this launch.
@@ -237,7 +263,7 @@ int launch_project_tuned(const Plan &p, const tomo_geometry *g, const float *cub
 int launch_backproject_tuned(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
                              bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
                              const int *done_flag, void *scratch, size_t scratch_bytes,
-                             const tomo_tuning &tu);
+                             const tomo_tuning &tu, const RayTable *tab = nullptr);
 int launch_fill(float *x, int64_t n, float v, hipStream_t s);
 int launch_backproject_binned(const Plan &p, const tomo_geometry *g, const float *images,
                               float *cube, bool use_map_mask, hipStream_t s, const int *done_flag,
@@ -264,7 +290,8 @@ int kept_rows_launch(const Plan &p, const ViewDev *views, int32_t nviews, const 
                      uint16_t *cols, hipStream_t s, const int *done_flag);
 int launch_backproject_blocked(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
                                bool accumulate, bool use_map_mask, hipStream_t s, const int *done_flag,
-                               void *scratch, size_t scratch_bytes, const tomo_tuning &tu);
+                               void *scratch, size_t scratch_bytes, const tomo_tuning &tu,
+                               const RayTable *tab = nullptr);
 // Strategy a TOMO_BP_* request resolves to under the plan's tuning.
 int resolve_bp_strategy(const Plan &p, int strategy);
 

@@ -380,28 +380,28 @@ int resolve_bp_strategy(const Plan &p, int strategy)
 
 int launch_backproject(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
                        bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
-                       const int *done_flag, void *scratch, size_t scratch_bytes)
+                       const int *done_flag, void *scratch, size_t scratch_bytes, const RayTable *tab)
 {
     return launch_backproject_tuned(p, g, images, cube, accumulate, use_map_mask, strategy, s, done_flag,
-                                    scratch, scratch_bytes, tuning_for(p));
+                                    scratch, scratch_bytes, tuning_for(p), tab);
 }
 
 int launch_backproject_tuned(const Plan &p, const tomo_geometry *g, const float *images, float *cube,
                              bool accumulate, bool use_map_mask, int strategy, hipStream_t s,
                              const int *done_flag, void *scratch, size_t scratch_bytes,
-                             const tomo_tuning &tu)
+                             const tomo_tuning &tu, const RayTable *tab)
 {
     if (strategy == TOMO_BP_AUTO) strategy = tu.bp_default;
     if (strategy == TOMO_BP_BLOCKED) {
         if (scratch)
             return launch_backproject_blocked(p, g, images, cube, accumulate, use_map_mask, s, done_flag,
-                                              scratch, scratch_bytes, tu);
+                                              scratch, scratch_bytes, tu, tab);
         const size_t need = blocked_scratch_bytes(p, blocked_shape(p, tu), g->data_mask != nullptr);
         void *tmp = nullptr;
         if (scratch_alloc(&tmp, need, s) != hipSuccess)
             return set_error(TOMO_ENOMEM, "back-projection scratch of %zu bytes", need);
         const int rc = launch_backproject_blocked(p, g, images, cube, accumulate, use_map_mask, s,
-                                                  done_flag, tmp, need, tu);
+                                                  done_flag, tmp, need, tu, tab);
         (void)scratch_free(tmp, s);
         return rc;
     }

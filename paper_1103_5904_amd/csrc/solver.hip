@@ -779,9 +779,10 @@ struct SolveBuffers {
 };
 
 // The device buffers of tomo_cg_solve on one geometry: the vectors, the
-// reduction workspace, the blocked P^T's scratch, P's bricked copy (when the
-// tuning walks bricks) and the network's activations (flexible CG).  One
-// sequence of allocations serves the solve and the workspace size query.
+// reduction workspace, the blocked P^T's scratch and ray table (when the
+// tuning asks for one), P's bricked copy (when the tuning walks bricks) and
+// the network's activations (flexible CG).  One sequence of allocations
+// serves the solve and the workspace size query.
 struct CgBufs {
     float *b = nullptr, *r = nullptr, *p = nullptr, *q = nullptr, *img = nullptr, *z = nullptr;
     float *bricks = nullptr;
@@ -789,6 +790,7 @@ struct CgBufs {
     int bps = TOMO_BP_BLOCKED;
     void *bscr = nullptr;
     size_t bscr_bytes = 0;
+    void *table = nullptr;  // ray table memory (null: none)
     void *netws = nullptr;
 };
 
@@ -817,6 +819,11 @@ static bool cg_buffers(SolveBuffers &buf, const Plan &plan, const tomo_geometry 
         o.bscr_bytes = blocked_scratch_bytes(plan, blocked_shape(plan, tu), g->data_mask != nullptr);
         o.bscr = buf.alloc(o.bscr_bytes);
         ok = ok && o.bscr;
+        const size_t nt = tu.bp_ray_table ? ray_table_bytes(plan) : 0;
+        if (nt) {
+            o.table = buf.alloc(nt);
+            ok = ok && o.table;
+        }
     }
     const size_t nbr = bricked_copy_bytes(plan, tu);
     if (nbr) {
@@ -1014,8 +1021,16 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         return TOMO_OK;
     }
 
+    // the rays' set-ups, once for all the solve's P^T
+    RayTable tab_v;
+    const RayTable *tab = nullptr;
+    if (cb.table) {
+        rc = ray_table_build(*plan, cb.table, tab_v, s);
+        if (rc) return rc;
+        tab = &tab_v;
+    }
     // b = M P^T y
-    rc = launch_backproject(*plan, g, y_d, b, false, true, bps, s, nullptr, bscr, bscr_bytes);
+    rc = launch_backproject(*plan, g, y_d, b, false, true, bps, s, nullptr, bscr, bscr_bytes, tab);
     if (rc) return rc;
     ++n_bp;
     if (g->map_mask && prm->x0_given) {
@@ -1023,7 +1038,7 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
     }
     auto apply_A_to = [&](const float *v) -> int {  // q = M (P^T P + prior) v, excluding the prior
         int e = launch_project_flagged(*plan, g, v, img, s, nullptr, cb.bricks);
-        if (!e) e = launch_backproject(*plan, g, img, q, false, false, bps, s, nullptr, bscr, bscr_bytes);
+        if (!e) e = launch_backproject(*plan, g, img, q, false, false, bps, s, nullptr, bscr, bscr_bytes, tab);
         n_proj++;
         n_bp++;
         return e;
@@ -1081,7 +1096,9 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
         }
         int e = launch_project_flagged(*plan, g, p, img, s, &ws.st->done, cb.bricks);
         if (timed) (void)hipEventRecord(e1, s);
-        if (!e) e = launch_backproject(*plan, g, img, q, bp_acc != 0, false, bps, s, &ws.st->done, bscr, bscr_bytes);
+        if (!e)
+            e = launch_backproject(*plan, g, img, q, bp_acc != 0, false, bps, s, &ws.st->done, bscr, bscr_bytes,
+                                   tab);
         if (timed) {
             (void)hipEventRecord(e2, s);
             evP.push_back(e0);

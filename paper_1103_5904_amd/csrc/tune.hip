@@ -18,7 +18,8 @@
 // owner-computes strategy over block shapes for workgroups of 256, 512 and
 // 1024 lanes (larger workgroups own larger blocks, so a ray is set up for
 // fewer of them), two owner counts and the XCD remap on/off, the LDS-binned
-// strategy over three bundles, and the atomic one.
+// strategy over three bundles, and the atomic one.  The blocked candidates
+// read a ray table when the tuning asks for one (as the solves do).
 //
 // Each candidate is screened over `reps` launches; the fastest P and P^T
 // candidates are then timed against the process-wide tuning in alternation
@@ -188,6 +189,18 @@ static int autotune_impl(const tomo_geometry *g, const float *cube_in, const flo
         if (rc) return rc;
     }
 
+    // the blocked candidates read a ray table, as the solves they serve do
+    RayTable tab;
+    void *tab_mem = nullptr;
+    const size_t tab_bytes = base.bp_ray_table ? ray_table_bytes(p) : 0;
+    if (tab_bytes && scratch_alloc(&tab_mem, tab_bytes, s) != hipSuccess)
+        return set_error(TOMO_ENOMEM, "tomo_autotune: device allocation failed");
+    Release release_t{s, tab_mem, nullptr};
+    if (tab_mem) {
+        rc = ray_table_build(p, tab_mem, tab, s);
+        if (rc) return rc;
+    }
+
     Timer tm;
     if (!tm.a || !tm.b) return set_error(TOMO_EHIP, "tomo_autotune: event creation failed");
     // ms per launch over n launches after one untimed one
@@ -203,7 +216,8 @@ static int autotune_impl(const tomo_geometry *g, const float *cube_in, const flo
     };
     auto run_p = [&](const tomo_tuning &t) { return launch_project_with(p, g, xc, img_w, true, s, t); };
     auto run_b = [&](const tomo_tuning &t) {
-        return launch_backproject_tuned(p, g, yc, cube_w, false, true, t.bp_default, s, nullptr, nullptr, 0, t);
+        return launch_backproject_tuned(p, g, yc, cube_w, false, true, t.bp_default, s, nullptr, nullptr, 0, t,
+                                        tab_mem && t.bp_ray_table ? &tab : nullptr);
     };
     // bring the clocks up before anything is timed: the process-wide
     // tuning's P and P^T repeated for at least 30 ms

@@ -195,6 +195,51 @@ __device__ inline bool ray_setup(const GridDev &g, const V &v, int col, int row,
     return true;
 }
 
+// Stores the set-up of pixel i (ok: ray_setup's result) into a ray table's
+// columns d and index words k, n rows each.  Every field is written, also
+// for a ray that misses (send = 0), so the table's contents depend on the
+// geometry alone.
+__device__ inline void ray_table_put(double *__restrict__ d, uint64_t *__restrict__ k, int64_t n, int64_t i,
+                                     bool ok, const RayState &r, const RayAxes &ax)
+{
+    uint64_t w = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        d[a * n + i] = ok ? r.s[a] : 0.0;
+        d[(3 + a) * n + i] = ok ? r.ds[a] : 0.0;
+        d[(8 + a) * n + i] = ok ? ax.rds[a] : 0.0;
+        if (ok) {
+            w |= (uint64_t)(uint32_t)ax.idx[a] << (kRayTableSideBits * a);
+            if (r.st[a] > 0) w |= 1ull << (60 + a);
+        }
+    }
+    d[6 * n + i] = ok ? r.send : 0.0;
+    d[7 * n + i] = ok ? r.dn : 0.0;
+    k[i] = w;
+}
+
+// The set-up of pixel i read back from a ray table: the fields of r and ax
+// that the blocked P^T uses (r.s, r.ds, r.send, r.dn, the signs of r.st;
+// ax.idx, ax.rds), bit for bit as ray_setup left them.  False: the ray
+// misses the box.
+__device__ inline bool ray_table_get(const RayTable &t, int64_t i, RayState &r, RayAxes &ax)
+{
+    const double *__restrict__ d = t.d;
+    const int64_t n = t.n;
+    const uint64_t w = t.k[i];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.s[a] = d[a * n + i];
+        r.ds[a] = d[(3 + a) * n + i];
+        ax.rds[a] = d[(8 + a) * n + i];
+        ax.idx[a] = (int)((w >> (kRayTableSideBits * a)) & ((1u << kRayTableSideBits) - 1u));
+        r.st[a] = r.ds[a] == 0.0 ? 0 : (((w >> (60 + a)) & 1u) ? 1 : -1);
+    }
+    r.send = d[6 * n + i];
+    r.dn = d[7 * n + i];
+    return r.send > 0.0;
+}
+
 // 1.0 if t else 0.0: only the high word differs, so one select; fma(ds, f,
 // s) then equals s + ds or s exactly.
 __device__ inline double tie_factor(bool t)

@@ -69,7 +69,7 @@ class Tuning(ctypes.Structure):
     _fields_ = [("p_bundle", c_int32), ("p_xcd_remap", c_int32), ("bp_bundle", c_int32),
                 ("bp_xcd_remap", c_int32), ("bp_lds_bins", c_int32), ("bp_default", c_int32),
                 ("bp_block", c_int32 * 3), ("bp_splits", c_int32), ("bp_threads", c_int32),
-                ("p_layout", c_int32)]
+                ("p_layout", c_int32), ("bp_ray_table", c_int32)]
 
 
 class CgParams(ctypes.Structure):

@@ -113,10 +113,12 @@ def test_null_arguments_are_rejected_without_gpu_work(tomo):
 def test_tuning_round_trip_and_range_checks(tomo):
     old = tomo.get_tuning()
     try:
-        tomo.set_tuning(p_bundle=4, bp_lds_bins=2048)
+        assert old["bp_ray_table"] == 1  # the default: solves and batches set each ray up once
+        tomo.set_tuning(p_bundle=4, bp_lds_bins=2048, bp_ray_table=0)
         t = tomo.get_tuning()
-        assert t["p_bundle"] == 4 and t["bp_lds_bins"] == 2048
-        for bad in ({"p_bundle": 5}, {"bp_lds_bins": 100}, {"bp_default": 7}, {"p_xcd_remap": 3}):
+        assert t["p_bundle"] == 4 and t["bp_lds_bins"] == 2048 and t["bp_ray_table"] == 0
+        for bad in ({"p_bundle": 5}, {"bp_lds_bins": 100}, {"bp_default": 7}, {"p_xcd_remap": 3},
+                    {"bp_ray_table": 2}, {"bp_ray_table": -1}):
             with pytest.raises(tomo.TomoError):
                 tomo.set_tuning(**bad)
         assert tomo.get_tuning() == t  # unchanged by rejected calls
