@@ -173,20 +173,20 @@ __global__ __launch_bounds__(kThreads) void k_brick_copy(const float *__restrict
     }
 }
 
-template <bool kDataMask, bool kObstacle>
+template <bool kDataMask, bool kObstacle, bool kWide>
 __global__ __launch_bounds__(kThreads) void k_project_bricked(
     GridDev g, const ViewDev *__restrict__ views, int32_t nviews, Bundle bun, int32_t maxit,
     const float *__restrict__ bricked, BrickDev bk, const uint8_t *__restrict__ data_mask,
     float *__restrict__ images, const int *__restrict__ done_flag)
 {
     if (done_flag && *done_flag) return;
-    project_tile_bricked<kDataMask, kObstacle>(g, views, nviews, bun.log2_bw, block_tile(bun), maxit, bricked, bk,
-                                               data_mask, images);
+    project_tile_bricked<kDataMask, kObstacle, false, kWide>(g, views, nviews, bun.log2_bw, block_tile(bun), maxit,
+                                                             bricked, bk, data_mask, images);
 }
 
 // The same with the per-axis offset terms in LDS (n0 + n1 + n2 entries of
 // dynamic shared memory), filled by the workgroup before its walk.
-template <bool kDataMask, bool kObstacle>
+template <bool kDataMask, bool kObstacle, bool kWide>
 __global__ __launch_bounds__(kThreads) void k_project_bricked_lut(
     GridDev g, const ViewDev *__restrict__ views, int32_t nviews, Bundle bun, int32_t maxit,
     const float *__restrict__ bricked, BrickDev bk, const uint8_t *__restrict__ data_mask,
@@ -201,8 +201,8 @@ __global__ __launch_bounds__(kThreads) void k_project_bricked_lut(
         lut[e] = brick_axis_term(bk, a, i);
     }
     __syncthreads();
-    project_tile_bricked<kDataMask, kObstacle, true>(g, views, nviews, bun.log2_bw, block_tile(bun), maxit,
-                                                     bricked, bk, data_mask, images, lut);
+    project_tile_bricked<kDataMask, kObstacle, true, kWide>(g, views, nviews, bun.log2_bw, block_tile(bun), maxit,
+                                                            bricked, bk, data_mask, images, lut);
 }
 
 // ------------------------------------------------------------ launchers
@@ -280,30 +280,35 @@ int launch_project_from_bricks(const Plan &p, const tomo_geometry *g, const floa
     const dim3 grid((unsigned)p.ntiles), blk(kThreads);
     // the per-axis offset terms in LDS when they fit in 32 KiB
     const size_t lut = sizeof(uint32_t) * ((size_t)p.grid.n[0] + p.grid.n[1] + p.grid.n[2]);
+    // a frame a buffer resource cannot span takes plain global loads
+    const bool wide = bk.frame_stride >= ((int64_t)1 << 30);
+#define TOMO_LAUNCH_PB(K, D, O)                                                                                \
+    do {                                                                                                       \
+        if (wide)                                                                                              \
+            hipLaunchKernelGGL((K<D, O, true>), grid, blk, lut_bytes, s, p.grid, p.views_d, p.nviews, b,       \
+                               p.max_steps, br, bk, g->data_mask, images, done_flag);                         \
+        else                                                                                                   \
+            hipLaunchKernelGGL((K<D, O, false>), grid, blk, lut_bytes, s, p.grid, p.views_d, p.nviews, b,      \
+                               p.max_steps, br, bk, g->data_mask, images, done_flag);                         \
+    } while (0)
+#define TOMO_LAUNCH_PB_ALL(K)                                         \
+    do {                                                              \
+        if (dm) {                                                     \
+            if (p.grid.has_sph) TOMO_LAUNCH_PB(K, true, true);        \
+            else TOMO_LAUNCH_PB(K, true, false);                      \
+        } else {                                                      \
+            if (p.grid.has_sph) TOMO_LAUNCH_PB(K, false, true);       \
+            else TOMO_LAUNCH_PB(K, false, false);                     \
+        }                                                             \
+    } while (0)
     if (lut <= 32768) {
-#define TOMO_LAUNCH_PB(D, O)                                                                                       \
-    hipLaunchKernelGGL((k_project_bricked_lut<D, O>), grid, blk, lut, s, p.grid, p.views_d, p.nviews, b,          \
-                       p.max_steps, br, bk, g->data_mask, images, done_flag)
-        if (dm) {
-            if (p.grid.has_sph) TOMO_LAUNCH_PB(true, true);
-            else TOMO_LAUNCH_PB(true, false);
-        } else {
-            if (p.grid.has_sph) TOMO_LAUNCH_PB(false, true);
-            else TOMO_LAUNCH_PB(false, false);
-        }
-#undef TOMO_LAUNCH_PB
-        return hip_fail(hipGetLastError(), "bricked projection kernel launch");
-    }
-#define TOMO_LAUNCH_PB(D, O)                                                                                   \
-    hipLaunchKernelGGL((k_project_bricked<D, O>), grid, blk, 0, s, p.grid, p.views_d, p.nviews, b, p.max_steps, \
-                       br, bk, g->data_mask, images, done_flag)
-    if (dm) {
-        if (p.grid.has_sph) TOMO_LAUNCH_PB(true, true);
-        else TOMO_LAUNCH_PB(true, false);
+        const size_t lut_bytes = lut;
+        TOMO_LAUNCH_PB_ALL(k_project_bricked_lut);
     } else {
-        if (p.grid.has_sph) TOMO_LAUNCH_PB(false, true);
-        else TOMO_LAUNCH_PB(false, false);
+        const size_t lut_bytes = 0;
+        TOMO_LAUNCH_PB_ALL(k_project_bricked);
     }
+#undef TOMO_LAUNCH_PB_ALL
 #undef TOMO_LAUNCH_PB
     return hip_fail(hipGetLastError(), "bricked projection kernel launch");
 }

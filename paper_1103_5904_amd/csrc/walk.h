@@ -416,7 +416,7 @@ __device__ inline uint32_t brick_axis_term(const BrickDev &bk, int a, int i)
 // per-axis terms read from LDS (lut: f0 over the n0 x indices, then f1,
 // then f2), one add and three LDS reads per step instead of the shifts,
 // masks and multiplies of brick_offset.
-template <bool kDataMask, bool kObstacle, bool kLut = false>
+template <bool kDataMask, bool kObstacle, bool kLut, bool kWide>
 __device__ inline void project_tile_bricked(const GridDev &g, const ViewDev *__restrict__ views, int32_t nviews,
                                             int log2_bw, int64_t tile, int32_t maxit, const float *__restrict__ bricked,
                                             const BrickDev &bk, const uint8_t *__restrict__ data_mask,
@@ -431,20 +431,24 @@ __device__ inline void project_tile_bricked(const GridDev &g, const ViewDev *__r
     RayAxes ax;
     if ((!kDataMask || data_mask[pix]) && ray_setup<kObstacle>(g, v, lp.col, lp.row, r, &ax)) {
         const float *__restrict__ base = bricked + (int64_t)v.frame * bk.frame_stride;
-        const bool wide = bk.frame_stride >= ((int64_t)1 << 30);
         const uint32_t last = (uint32_t)(bk.frame_stride - 1);
-        const auto rc = make_rsrc(base, wide ? 0u : (uint32_t)(bk.frame_stride * 4));
+        const auto rc = make_rsrc(base, kWide ? 0u : (uint32_t)(bk.frame_stride * 4));
         int i[3] = {ax.idx[0], ax.idx[1], ax.idx[2]};
         int dir[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) dir[a] = r.st[a] > 0 ? 1 : (r.st[a] < 0 ? -1 : 0);
-        // pipelined by one segment as in project_tile
+        // the kind of load is fixed per kernel (kWide: frames of 2^30 floats
+        // and more, which a buffer resource cannot span).  Pipelined by one
+        // segment: a step issues its voxel's gather before it adds the
+        // previous segment, so two gathers are in flight and each has a
+        // whole step to land
         double acc = 0.0, dl_prev = 0.0, scur = 0.0;
         float x_prev = 0.0f;
         auto step = [&]() {
             const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
             const uint32_t off = kLut ? lut[i[0]] + lut[g.n[0] + i[1]] + lut[g.n[0] + g.n[1] + i[2]]
                                       : brick_offset(bk, i[0], i[1], i[2]);
+            const float x = kWide ? base[min(off, last)] : buf_load_f32(rc, off * 4u);
             const double dl = m - scur;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -454,7 +458,7 @@ __device__ inline void project_tile_bricked(const GridDev &g, const ViewDev *__r
             }
             scur = m;
             acc = fma(dl_prev, (double)x_prev, acc);
-            x_prev = wide ? base[min(off, last)] : buf_load_f32(rc, off * 4u);
+            x_prev = x;
             dl_prev = dl;
             return m >= r.send;
         };
