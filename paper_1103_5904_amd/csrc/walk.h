@@ -340,7 +340,8 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
         const uint32_t last = (uint32_t)(g.nvox - 1);
         const auto rc = make_rsrc(base, wide ? 0u : (uint32_t)(g.nvox * 4));
         // software-pipelined by one segment: a step issues its voxel's gather
-        // and adds the previous segment, so each load has a whole step to land
+        // before it adds the previous segment, so each load has a whole step
+        // to land
         double acc = 0.0, dl_prev = 0.0;
         float x_prev = 0.0f;
         if constexpr (kMapMask) {
@@ -348,9 +349,11 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
             uint32_t m_prev = 0u;
             auto walk_masked = [&](auto load) {
                 ray_walk(r, maxit, [&](int32_t off, double dl) {
+                    const float x = load((uint32_t)off);
+                    const uint32_t mk = buf_load_u8(rm, (uint32_t)off);
                     acc = fma(dl_prev, m_prev ? (double)x_prev : 0.0, acc);
-                    x_prev = load((uint32_t)off);
-                    m_prev = buf_load_u8(rm, (uint32_t)off);
+                    x_prev = x;
+                    m_prev = mk;
                     dl_prev = dl;
                 });
             };
@@ -361,8 +364,9 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
             if (!m_prev) x_prev = 0.0f;
         } else if (wide) {
             ray_walk(r, maxit, [&](int32_t off, double dl) {
+                const float x = base[min((uint32_t)off, last)];
                 acc = fma(dl_prev, (double)x_prev, acc);
-                x_prev = base[min((uint32_t)off, last)];
+                x_prev = x;
                 dl_prev = dl;
             });
         } else if (g.nvox < ((int64_t)1 << 29)) {
@@ -371,14 +375,16 @@ __device__ inline void project_tile(const GridDev &g, const ViewDev *__restrict_
 #pragma unroll
             for (int a = 0; a < 3; ++a) r.st[a] *= 4;
             ray_walk(r, maxit, [&](int32_t off, double dl) {
+                const float x = buf_load_f32(rc, (uint32_t)off);
                 acc = fma(dl_prev, (double)x_prev, acc);
-                x_prev = buf_load_f32(rc, (uint32_t)off);
+                x_prev = x;
                 dl_prev = dl;
             });
         } else {
             ray_walk(r, maxit, [&](int32_t off, double dl) {
+                const float x = buf_load_f32(rc, (uint32_t)off * 4u);
                 acc = fma(dl_prev, (double)x_prev, acc);
-                x_prev = buf_load_f32(rc, (uint32_t)off * 4u);
+                x_prev = x;
                 dl_prev = dl;
             });
         }
