@@ -57,20 +57,19 @@ VALU_PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 # an iteration (its four-crossing loop body in the gfx950 ISA, divided by
 # four): the P^T walk with its fixed-point LDS deposit (batch.hip), and the
 # P gather-FMA walk over the 16^3-bricked cube of the dominant system with
-# its offsets from the LDS table of per-axis terms (siddon.hip; 120 VALU per
-# loop body, of which the clamped global-load path a launch does not run
-# takes 12).
-WALK_VALU_PER_CROSSING = {"k_project_bricked_lut": 108 / 4, "k_batch_backproject": 92 / 4}
+# its offsets from the LDS table of per-axis terms (siddon.hip; 110 VALU per
+# loop body, six of them register moves at the loop's back edge).
+WALK_VALU_PER_CROSSING = {"k_project_bricked_lut": 110 / 4, "k_batch_backproject": 92 / 4}
 
 # Per-launch counters of the batched kernels on the headline step, from
 # rocprofv3 --pmc passes of `bench.py --headline-only` (profiles/
 # cor1_batch_backprojection.md): SQ_INSTS_VALU (wave-level VALU instructions
-# per dispatch) and the HBM bytes per dispatch (FETCH_SIZE x 1.9998 +
+# per dispatch) and the HBM bytes per dispatch (FETCH_SIZE x 1.9997 +
 # WRITE_SIZE, the scale factors a 256 MiB device copy reads).  Valid only for
 # the sources they were taken on: sha256 over the listed files, first 16 hex
 # digits; otherwise the fields they feed are null.
 PROFILED = {
-    "k_batch_backproject": {"sha": "f0997b26d65ba41c", "valu_insts": 2893861003.0, "hbm_bytes": 1231630911.0},
+    "k_batch_backproject": {"sha": "e17753665b8d862a", "valu_insts": 2692546226.0, "hbm_bytes": 9305944590.6},
 }
 PROFILED_FILES = ["blocked.h", "batch.hip", "batch.h", "walk.h", "common.h", "api.hip", "tune.hip"]
 
