@@ -746,11 +746,14 @@ static void launch_true_res(bool hw, unsigned blocks, hipStream_t s, Args... a)
 
 // Device allocations of one solve, released on every exit path: stream-
 // ordered scratch; or consecutive 256-byte aligned pieces of a caller's
-// workspace (arena); or, to size such a workspace (measure), no memory at
-// all: every piece is a non-null placeholder that nothing dereferences.
+// workspace or of one stream-ordered block (arena; `owned` is that block,
+// freed with the buffers); or, to size such a workspace (measure), no
+// memory at all: every piece is a non-null placeholder that nothing
+// dereferences.
 struct SolveBuffers {
     hipStream_t s = nullptr;
     std::vector<void *> ptrs;
+    void *owned = nullptr;
     char *arena = nullptr;
     size_t arena_bytes = 0;
     bool measure = false;
@@ -775,6 +778,7 @@ struct SolveBuffers {
     ~SolveBuffers()
     {
         for (void *p : ptrs) (void)scratch_free(p, s);
+        if (owned) (void)scratch_free(owned, s);
     }
 };
 
@@ -959,18 +963,28 @@ int tomo_cg_solve(const tomo_geometry *g, const float *y_d, float *x_d, const to
 
     SolveBuffers buf;
     buf.s = s;
-    if (prm->workspace) {
-        if ((uintptr_t)prm->workspace & 255u)
-            return set_error(TOMO_EINVAL, "tomo_cg_solve: the workspace must be 256-byte aligned");
+    {
         SolveBuffers m;
         m.measure = true;
         CgBufs sized;
         (void)cg_buffers(m, *plan, g, prm, sized);
-        if (prm->workspace_bytes < m.used)
-            return set_error(TOMO_EINVAL, "tomo_cg_solve: workspace of %zu bytes, %zu needed", prm->workspace_bytes,
-                             m.used);
-        buf.arena = (char *)prm->workspace;
-        buf.arena_bytes = prm->workspace_bytes;
+        if (prm->workspace) {
+            if ((uintptr_t)prm->workspace & 255u)
+                return set_error(TOMO_EINVAL, "tomo_cg_solve: the workspace must be 256-byte aligned");
+            if (prm->workspace_bytes < m.used)
+                return set_error(TOMO_EINVAL, "tomo_cg_solve: workspace of %zu bytes, %zu needed",
+                                 prm->workspace_bytes, m.used);
+            buf.arena = (char *)prm->workspace;
+            buf.arena_bytes = prm->workspace_bytes;
+        } else {
+            // one block from the pool for all of the solve's buffers: the
+            // pool then reuses the same block solve after solve (separate
+            // pieces of a few hundred MB were measured to cost ~1 ms a solve)
+            if (scratch_alloc(&buf.owned, m.used, s) != hipSuccess)
+                return set_error(TOMO_ENOMEM, "tomo_cg_solve: device allocation of %zu bytes failed", m.used);
+            buf.arena = (char *)buf.owned;
+            buf.arena_bytes = m.used;
+        }
     }
     CgBufs cb;
     if (!cg_buffers(buf, *plan, g, prm, cb)) return set_error(TOMO_ENOMEM, "tomo_cg_solve: device allocation failed");
