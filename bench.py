@@ -57,9 +57,9 @@ VALU_PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 # an iteration (its four-crossing loop body in the gfx950 ISA, divided by
 # four): the P^T walk with its fixed-point LDS deposit (batch.hip), and the
 # P gather-FMA walk over the 16^3-bricked cube of the dominant system with
-# its offsets from the LDS table of per-axis terms (siddon.hip; 110 VALU per
+# its offsets from the LDS table of per-axis terms (siddon.hip; 106 VALU per
 # loop body, six of them register moves at the loop's back edge).
-WALK_VALU_PER_CROSSING = {"k_project_bricked_lut": 110 / 4, "k_batch_backproject": 92 / 4}
+WALK_VALU_PER_CROSSING = {"k_project_bricked_lut": 106 / 4, "k_batch_backproject": 92 / 4}
 
 # Per-launch counters of the batched kernels on the headline step, from
 # rocprofv3 --pmc passes of `bench.py --headline-only` (profiles/
@@ -69,7 +69,7 @@ WALK_VALU_PER_CROSSING = {"k_project_bricked_lut": 110 / 4, "k_batch_backproject
 # the sources they were taken on: sha256 over the listed files, first 16 hex
 # digits; otherwise the fields they feed are null.
 PROFILED = {
-    "k_batch_backproject": {"sha": "e17753665b8d862a", "valu_insts": 2692546226.0, "hbm_bytes": 9305944590.6},
+    "k_batch_backproject": {"sha": "2eb1d74fd1fe2e20", "valu_insts": 2692546226.0, "hbm_bytes": 9305944590.6},
 }
 PROFILED_FILES = ["blocked.h", "batch.hip", "batch.h", "walk.h", "common.h", "api.hip", "tune.hip"]
 
@@ -349,8 +349,9 @@ def learned_vs_plain(tomo, ts, seeds=tuple(range(2003, 2013)), reps=3):
 
 def obstacle_euvi(tomo, ts, wl, y, reps=10):
     """The obstacle variant on the EUVI-like workload: lines of sight end
-    where they enter the unit sphere.  P and P^T per launch and one
-    50-iteration CG step."""
+    where they enter the unit sphere.  One 50-iteration CG step, with P and
+    P^T per launch from events inside the solve (as for the EUVI-like step),
+    and the standalone tomo_backproject call beside them (no ray table)."""
     import torch
 
     g0 = wl.geom
@@ -359,17 +360,16 @@ def obstacle_euvi(tomo, ts, wl, y, reps=10):
     dg = tomo.DeviceGeometry(g)
     cross = tomo.count_crossings(dg)
     x = torch.zeros(dg.cube_shape, dtype=torch.float32, device="cuda")
-    img = torch.empty_like(y)
-    ms_p = events_ms(lambda: tomo.project(dg, x, out=img), reps)
-    ms_b = events_ms(lambda: tomo.backproject(dg, y, out=x), reps)
+    ms_call = events_ms(lambda: tomo.backproject(dg, y, out=x), reps)
     tomo.cg_solve(dg, y, lam_r=wl.lam_r, max_iter=wl.cg_iters, out=x)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    _, rep = tomo.cg_solve(dg, y, lam_r=wl.lam_r, max_iter=wl.cg_iters, out=x)
+    _, rep = tomo.cg_solve(dg, y, lam_r=wl.lam_r, max_iter=wl.cg_iters, out=x, time_kernels=True)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
-    return {"crossings": cross, "k_project_ms": ms_p, "k_backproject_ms": ms_b, "ms_per_step": 1e3 * dt,
-            "crossings_per_s": (rep["n_project"] + rep["n_backproject"]) * cross / dt}
+    return {"crossings": cross, "k_project_ms": rep["ms_project"] / rep["n_project"],
+            "k_backproject_ms": rep["ms_backproject"] / rep["n_backproject"], "backproject_call_ms": ms_call,
+            "ms_per_step": 1e3 * dt, "crossings_per_s": (rep["n_project"] + rep["n_backproject"]) * cross / dt}
 
 
 def thomson_cor1(tomo, ts, reps=5):

@@ -198,7 +198,9 @@ __global__ __launch_bounds__(kThreads) void k_project_bricked_lut(
     for (int e = threadIdx.x; e < ntab; e += kThreads) {
         const int a = e < g.n[0] ? 0 : (e < g.n[0] + g.n[1] ? 1 : 2);
         const int i = a == 0 ? e : (a == 1 ? e - g.n[0] : e - g.n[0] - g.n[1]);
-        lut[e] = brick_axis_term(bk, a, i);
+        // byte offsets where a buffer resource spans the frame (one add
+        // less per step), element offsets for the clamped global loads
+        lut[e] = brick_axis_term(bk, a, i) * (kWide ? 1u : 4u);
     }
     __syncthreads();
     project_tile_bricked<kDataMask, kObstacle, true, kWide>(g, views, nviews, bun.log2_bw, block_tile(bun), maxit,

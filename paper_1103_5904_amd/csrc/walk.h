@@ -420,8 +420,8 @@ __device__ inline uint32_t brick_axis_term(const BrickDev &bk, int a, int i)
 // axis and the offset formed from them; the same segments summed in the
 // same order, so the same bits.  With kLut the offset is the sum of three
 // per-axis terms read from LDS (lut: f0 over the n0 x indices, then f1,
-// then f2), one add and three LDS reads per step instead of the shifts,
-// masks and multiplies of brick_offset.
+// then f2; in bytes unless kWide), one add and three LDS reads per step
+// instead of the shifts, masks and multiplies of brick_offset.
 template <bool kDataMask, bool kObstacle, bool kLut, bool kWide>
 __device__ inline void project_tile_bricked(const GridDev &g, const ViewDev *__restrict__ views, int32_t nviews,
                                             int log2_bw, int64_t tile, int32_t maxit, const float *__restrict__ bricked,
@@ -454,7 +454,7 @@ __device__ inline void project_tile_bricked(const GridDev &g, const ViewDev *__r
             const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
             const uint32_t off = kLut ? lut[i[0]] + lut[g.n[0] + i[1]] + lut[g.n[0] + g.n[1] + i[2]]
                                       : brick_offset(bk, i[0], i[1], i[2]);
-            const float x = kWide ? base[min(off, last)] : buf_load_f32(rc, off * 4u);
+            const float x = kWide ? base[min(off, last)] : buf_load_f32(rc, kLut ? off : off * 4u);
             const double dl = m - scur;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
