@@ -55,11 +55,12 @@ HBM_PEAK_GBS = 8000.0
 VALU_PEAK_LANE_INSTR = 256 * 64 * 2.4e9
 # VALU instructions of one voxel crossing in the walk loop of each kernel of
 # an iteration (its four-crossing loop body in the gfx950 ISA, divided by
-# four): the P^T walk with its fixed-point LDS deposit (batch.hip), and the
+# four): the P^T walk with its fixed-point LDS deposit at the bin's LDS
+# address (batch.hip; 88 VALU per loop body), and the
 # P gather-FMA walk over the 16^3-bricked cube of the dominant system with
 # its offsets from the LDS table of per-axis terms (siddon.hip; 106 VALU per
 # loop body, six of them register moves at the loop's back edge).
-WALK_VALU_PER_CROSSING = {"k_project_bricked_lut": 106 / 4, "k_batch_backproject": 92 / 4}
+WALK_VALU_PER_CROSSING = {"k_project_bricked_lut": 106 / 4, "k_batch_backproject": 88 / 4}
 
 # Per-launch counters of the batched kernels on the headline step, from
 # rocprofv3 --pmc passes of `bench.py --headline-only` (profiles/

@@ -8,6 +8,24 @@ namespace tomo {
 
 constexpr int kYmaxParts = 64;  // partial maxima per view (64 workgroups per view keep the pass short)
 
+// LDS byte address of a pointer into shared memory, and atomic adds at such
+// an address: a walk that carries its bin as an address needs no shift or
+// base add per step (the clamp's result is the instruction's address).
+__device__ inline uint32_t lds_address(const void *p)
+{
+    return (uint32_t)(uintptr_t)(__attribute__((address_space(3))) const char *)p;
+}
+__device__ inline void lds_add_u64(uint32_t a, unsigned long long v)
+{
+    __hip_atomic_fetch_add((__attribute__((address_space(3))) unsigned long long *)(uintptr_t)a, v,
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ inline void lds_add_f32(uint32_t a, float v)
+{
+    __hip_atomic_fetch_add((__attribute__((address_space(3))) float *)(uintptr_t)a, v, __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // max |gain y| over the share `part` of view v's unmasked pixels, as an
 // FP32 bit pattern (bit patterns of magnitudes order like the magnitudes;
 // anything >= 0x7f800000 is non-finite).  The product is rounded to FP32,
@@ -212,7 +230,9 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
     (void)frexp(vdiag * ymax * 1.0000001, &e1);
     eb = eb > e1 + 11 ? eb : e1 + 11;
     const double fx_scale = ldexp(1.0, 61 - eb), fx_inv = ldexp(1.0, eb - 61);
-    float *fbins = reinterpret_cast<float *>(bins);
+    // bins as LDS byte addresses: bin l at bbase + 8 l (the FP32 bins of
+    // non-finite data in the low half of the same word); blim is the dummy bin
+    const uint32_t bbase = lds_address(bins), blim = bbase + 8u * (uint32_t)nbins;
 
     __syncthreads();  // the previous item of this workgroup is done with the bins
     for (int i = tid; i <= nbins; i += NT) bins[i] = 0ull;  // + the dummy bin
@@ -456,7 +476,7 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
             if (!hit || !(X > E)) continue;
             // walk state at E: crossings with parameter <= E are done
             int32_t loc = 0;
-            int32_t lst[3];
+            int32_t lst[3];  // bin steps in bytes
             bool inblk = true;
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -477,7 +497,7 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                     }
                     r.s[a] += (double)jj * r.ds[a];
                     idx += r.st[a] > 0 ? jj : -jj;
-                    lst[a] = r.st[a] > 0 ? lstride[a] : -lstride[a];
+                    lst[a] = 8 * (r.st[a] > 0 ? lstride[a] : -lstride[a]);
                 } else {
                     lst[a] = 0;
                 }
@@ -493,19 +513,22 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                 continue;
             }
             const double wys = (double)yv * r.dn * v.vscale;
+            uint32_t la = bbase + 8u * (uint32_t)loc;  // the bin's LDS address
             // four steps per loop body, as in ray_walk; the clamp to the
-            // dummy bin nbins only guards the LDS range
+            // dummy bin only guards the LDS range (an address below the bins,
+            // which an exact walk never reaches, would stay inside the
+            // workgroup's LDS)
             auto walk = [&](auto deposit) {
                 double scur = E;
                 auto step = [&]() {
                     const double m = fmin(fmin(r.s[0], r.s[1]), fmin(r.s[2], r.send));
-                    deposit(min((uint32_t)loc, (uint32_t)nbins), (m - scur) * wys);
+                    deposit(min(la, blim), (m - scur) * wys);
                     if (m >= X) return true;
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         const bool tie = (r.s[a] == m);
                         r.s[a] = fma(r.ds[a], tie_factor(tie), r.s[a]);
-                        loc += tie ? lst[a] : 0;
+                        la += tie ? (uint32_t)lst[a] : 0u;
                     }
                     scur = m;
                     return false;
@@ -519,10 +542,10 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
                     // val + 1.5 * 2^52 rounds val to an integer (|val| < 2^50) in the low bits
                     const double t = val + 6755399441055744.0;
                     const long long q = (long long)__builtin_bit_cast(uint64_t, t) - 0x4338000000000000ll;
-                    atomicAdd(&bins[l], (unsigned long long)q);
+                    lds_add_u64(l, (unsigned long long)q);
                 });
             } else {
-                walk([&](uint32_t l, double val) { atomicAdd(&fbins[l], (float)val); });
+                walk([&](uint32_t l, double val) { lds_add_f32(l, (float)val); });
             }
         }
     }
@@ -537,7 +560,8 @@ __device__ inline void blocked_item(const GridDev &g, const ViewDev *__restrict_
     for (int e = tid; e < nin; e += NT) {
         const int lx = e % ex, ly = (e / ex) % ey, lz = e / (ex * ey);
         const int l = (lz * bd.b[1] + ly) * bd.b[0] + lx;
-        const float val = finite ? (float)((double)(long long)bins[l] * fx_inv) : fbins[l];
+        const float val = finite ? (float)((double)(long long)bins[l] * fx_inv)
+                                 : *reinterpret_cast<const float *>(bins + l);
         const int64_t off = ((int64_t)(blo[2] + lz) * g.n[1] + (blo[1] + ly)) * g.n[0] + (blo[0] + lx);
         if (bd.splits == 1) {
             float o = (!kMapMask || map_mask[off]) ? val : 0.0f;
